@@ -1,0 +1,212 @@
+"""CPU oracle — TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product library never does, and the
+oracle never imports the product: the two share no code.  What each function
+computes, and which passage of DuMato (Ferraz et al., arXiv 2212.04551) it
+follows, is stated in ``oracle.c`` and in the docstrings below.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (in-tree)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", tmp, _SRC, "-lpthread"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB):
+        build()
+    L = ctypes.CDLL(_LIB)
+    vp, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+    L.or_canon.restype = u32
+    L.or_canon.argtypes = [ctypes.c_int, u32]
+    L.or_num_classes.restype = ctypes.c_int
+    L.or_num_classes.argtypes = [ctypes.c_int]
+    L.or_class_canon.restype = ctypes.c_int
+    L.or_class_canon.argtypes = [ctypes.c_int, vp, ctypes.c_int]
+    L.or_num_connected_labelled.restype = i64
+    L.or_num_connected_labelled.argtypes = [ctypes.c_int]
+    L.or_class_of_code.restype = ctypes.c_int
+    L.or_class_of_code.argtypes = [ctypes.c_int, u32]
+    L.or_clique_brute.restype = ctypes.c_int
+    L.or_clique_brute.argtypes = [i32, vp, vp, ctypes.c_int, vp, vp]
+    L.or_motif_brute.restype = ctypes.c_int
+    L.or_motif_brute.argtypes = [i32, vp, vp, ctypes.c_int, vp, vp]
+    for f in (L.or_clique_roots, L.or_motif_roots):
+        f.restype = ctypes.c_int
+        f.argtypes = [i32, vp, vp, ctypes.c_int, vp, i64, ctypes.c_int, vp, vp, vp, vp]
+    L.or_twohop.restype = None
+    L.or_twohop.argtypes = [i32, vp, vp, vp]
+    L.or_triangles.restype = None
+    L.or_triangles.argtypes = [i32, vp, vp, vp]
+    L.or_core.restype = None
+    L.or_core.argtypes = [i32, vp, vp, vp]
+    _lib = L
+    return L
+
+
+def _csr(g):
+    rp = np.ascontiguousarray(g.row_ptr, dtype=np.int64)
+    col = np.ascontiguousarray(g.col, dtype=np.int32)
+    if col.size == 0:
+        col = np.zeros(1, dtype=np.int32)
+    return rp, col
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data
+
+
+# ------------------------------------------------------------------ classes
+
+def canon(k: int, code: int) -> int:
+    """Minimum edge bitmap over all k! relabellings (bit i(i-1)/2+t = edge t<i)."""
+    return int(_load().or_canon(k, code))
+
+
+def num_classes(k: int) -> int:
+    return int(_load().or_num_classes(k))
+
+
+def class_canon(k: int) -> np.ndarray:
+    """Canonical codes of the connected classes, in class-id order."""
+    L = _load()
+    ncls = L.or_num_classes(k)
+    out = np.zeros(max(ncls, 1), dtype=np.uint32)
+    L.or_class_canon(k, out.ctypes.data, ncls)
+    return out[:ncls]
+
+
+def num_connected_labelled(k: int) -> int:
+    return int(_load().or_num_connected_labelled(k))
+
+
+def class_of_code(k: int, code: int) -> int:
+    """Class id of a full edge bitmap on k vertices, or -1 if disconnected."""
+    return int(_load().or_class_of_code(k, code))
+
+
+def code_of(adj: np.ndarray) -> int:
+    """Full edge bitmap of a k x k adjacency matrix (column order)."""
+    k = adj.shape[0]
+    c = 0
+    for i in range(1, k):
+        for t in range(i):
+            if adj[t, i]:
+                c |= 1 << (i * (i - 1) // 2 + t)
+    return c
+
+
+# ------------------------------------------------------------------ L1
+
+def clique_brute(g, k: int, per_root: bool = False):
+    """Number of k-subsets that are cliques (definition, every subset)."""
+    rp, col = _csr(g)
+    tot = np.zeros(1, dtype=np.uint64)
+    pr = np.zeros(max(g.n, 1), dtype=np.uint64) if per_root else None
+    rc = _load().or_clique_brute(g.n, rp.ctypes.data, col.ctypes.data, k, tot.ctypes.data, _ptr(pr))
+    if rc != 0:
+        raise ValueError("bad arguments")
+    return (int(tot[0]), pr[:g.n]) if per_root else int(tot[0])
+
+
+def motif_brute(g, k: int, per_root: bool = False):
+    """Per-class counts of connected induced k-subsets (definition, every subset)."""
+    rp, col = _csr(g)
+    ncls = num_classes(k)
+    out = np.zeros(ncls, dtype=np.uint64)
+    pr = np.zeros(max(g.n, 1), dtype=np.uint64) if per_root else None
+    rc = _load().or_motif_brute(g.n, rp.ctypes.data, col.ctypes.data, k, out.ctypes.data, _ptr(pr))
+    if rc != 0:
+        raise ValueError("bad arguments")
+    return (out, pr[:g.n]) if per_root else out
+
+
+# ------------------------------------------------------------------ L2
+
+def _roots(roots):
+    if roots is None:
+        return None, 0
+    r = np.ascontiguousarray(roots, dtype=np.int32)
+    return r, r.size
+
+
+def clique_count(g, k: int, roots=None, threads: int = 1, per_root: bool = False):
+    """k-cliques by rank-ordered backtracking.
+
+    With ``roots`` only cliques credited to those roots (lowest (degree, id) rank)
+    are counted.  With ``per_root`` returns (total, leaves, nodes, reads) arrays
+    aligned with the root list.  Raises OverflowError on a uint64 wrap.
+    """
+    rp, col = _csr(g)
+    r, nr = _roots(roots)
+    cnt = nr if r is not None else g.n
+    tot = np.zeros(1, dtype=np.uint64)
+    arrs = [np.zeros(max(cnt, 1), dtype=np.uint64) for _ in range(3)] if per_root else [None] * 3
+    rc = _load().or_clique_roots(g.n, rp.ctypes.data, col.ctypes.data, k, _ptr(r), nr, threads,
+                                 tot.ctypes.data, *[_ptr(a) for a in arrs])
+    if rc < 0:
+        raise ValueError("bad arguments")
+    if rc == 1:
+        raise OverflowError("uint64 overflow")
+    if per_root:
+        return (int(tot[0]),) + tuple(a[:cnt] for a in arrs)
+    return int(tot[0])
+
+
+def motif_count(g, k: int, roots=None, threads: int = 1, per_root: bool = False):
+    """Per-class connected induced k-set counts by ESU (Wernicke 2006).
+
+    With ``roots`` only sets whose minimum id is listed are counted.  With
+    ``per_root`` returns (counts, leaves, nodes, reads).
+    """
+    rp, col = _csr(g)
+    r, nr = _roots(roots)
+    cnt = nr if r is not None else g.n
+    out = np.zeros(num_classes(k), dtype=np.uint64)
+    arrs = [np.zeros(max(cnt, 1), dtype=np.uint64) for _ in range(3)] if per_root else [None] * 3
+    rc = _load().or_motif_roots(g.n, rp.ctypes.data, col.ctypes.data, k, _ptr(r), nr, threads,
+                                out.ctypes.data, *[_ptr(a) for a in arrs])
+    if rc < 0:
+        raise ValueError("bad arguments")
+    if rc == 1:
+        raise OverflowError("uint64 overflow")
+    if per_root:
+        return (out,) + tuple(a[:cnt] for a in arrs)
+    return out
+
+
+# ------------------------------------------------------------------ features
+
+def features(g) -> np.ndarray:
+    """[n, 4] float64: degree, 2-hop degree sum, core number, triangle count."""
+    rp, col = _csr(g)
+    L = _load()
+    two = np.zeros(max(g.n, 1), dtype=np.int64)
+    tri = np.zeros(max(g.n, 1), dtype=np.int64)
+    core = np.zeros(max(g.n, 1), dtype=np.int32)
+    L.or_twohop(g.n, rp.ctypes.data, col.ctypes.data, two.ctypes.data)
+    L.or_triangles(g.n, rp.ctypes.data, col.ctypes.data, tri.ctypes.data)
+    L.or_core(g.n, rp.ctypes.data, col.ctypes.data, core.ctypes.data)
+    deg = np.diff(rp)
+    return np.stack([deg, two[:g.n], core[:g.n], tri[:g.n]], axis=1).astype(np.float64)

@@ -1,0 +1,658 @@
+/*
+ * CPU ORACLE for k-clique and induced k-motif counting — TEST INFRASTRUCTURE.
+ *
+ * Only the test-suite, the smoke check and the benchmark's CPU-baseline leg use
+ * this file.  It shares no code, header, table or helper with the GPU library:
+ * it has its own CSR handling, its own canonical coder and its own enumerators.
+ * It is deliberately plain and slow.
+ *
+ * What it computes (DuMato, Ferraz et al., arXiv 2212.04551):
+ *   - Induced subgraphs and neighbourhoods: Section II (Background), Defs. 1-3.
+ *   - The enumeration function E(G, tr, k) with property P and output A:
+ *     Section II, Eq. (1).  Clique counting is P = "fully connected", A = count;
+ *     motif counting is A = count per canonical representative (pattern).
+ *   - Clique counting problem statement: Section IV-E (Programming with DuMato).
+ *   - Motif counting problem statement: Section IV-E; only connected
+ *     traversals are patterns (Section IV-C, Aggregate).
+ *   - Canonical representative = isomorphism class.  Class ids are contiguous
+ *     (Section IV-C, Aggregate); their order is not given by the paper and is
+ *     read as (edge count ascending, canonical code ascending), where the
+ *     canonical code is the minimum, over all k! relabellings, of the
+ *     upper-triangle edge bitmap in column order: bit i(i-1)/2 + t is the edge
+ *     between vertices t < i, so the edges of vertex i to its predecessors are
+ *     contiguous (the bitmap layout of Section IV-C, Aggregate).
+ *
+ * Levels:
+ *   L1  brute force over every k-subset, straight from the definitions.
+ *   L2  plain enumerators: clique backtracking in (degree, id) rank order, and
+ *       ESU (Wernicke 2006) for connected k-sets rooted at their minimum id.
+ *       Multi-threaded over roots with pthreads.
+ *
+ * Per-root outputs (used for sampled parity at sizes where a full run is
+ * infeasible): every clique is credited to its lowest vertex in (degree asc,
+ * id asc) rank; every connected k-set to its smallest id.  For a root r,
+ *   leaves(r) = number of k-vertex results credited to r,
+ *   nodes(r)  = number of j-vertex traversals (1 <= j <= k-1) credited to r
+ *               (j-cliques, or connected j-sets, whose root is r),
+ *   reads(r)  = sum over those traversals of the degree (out-degree in rank
+ *               order for cliques) of the vertex added last.
+ */
+#include <pthread.h>
+#include <stdatomic.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_MAXK 8          /* motif classification up to k = 8 (table 2^27 for k=8 not built) */
+#define OR_MAX_MOTIF_K 6   /* class tables are built for k <= 6 */
+
+/* ====================================================================== */
+/* canonical codes                                                         */
+/* ====================================================================== */
+
+static inline int pair_bit(int t, int i) { /* t < i */
+    return i * (i - 1) / 2 + t;
+}
+
+/* graph on k labelled vertices -> edge bitmap */
+static uint32_t code_from_adj(int k, const unsigned char adj[OR_MAXK][OR_MAXK]) {
+    uint32_t c = 0;
+    for (int i = 1; i < k; ++i)
+        for (int t = 0; t < i; ++t)
+            if (adj[t][i]) c |= 1u << pair_bit(t, i);
+    return c;
+}
+
+static void adj_from_code(int k, uint32_t c, unsigned char adj[OR_MAXK][OR_MAXK]) {
+    memset(adj, 0, sizeof(unsigned char) * OR_MAXK * OR_MAXK);
+    for (int i = 1; i < k; ++i)
+        for (int t = 0; t < i; ++t)
+            if (c >> pair_bit(t, i) & 1u) adj[t][i] = adj[i][t] = 1;
+}
+
+static int connected_code(int k, uint32_t c) {
+    unsigned char adj[OR_MAXK][OR_MAXK];
+    adj_from_code(k, c, adj);
+    int seen[OR_MAXK] = {0}, stack[OR_MAXK], sp = 0, cnt = 1;
+    seen[0] = 1;
+    stack[sp++] = 0;
+    while (sp) {
+        int x = stack[--sp];
+        for (int y = 0; y < k; ++y)
+            if (adj[x][y] && !seen[y]) { seen[y] = 1; cnt++; stack[sp++] = y; }
+    }
+    return cnt == k;
+}
+
+/* next permutation in lexicographic order; returns 0 after the last one */
+static int next_perm(int* p, int k) {
+    int i = k - 2;
+    while (i >= 0 && p[i] > p[i + 1]) --i;
+    if (i < 0) return 0;
+    int j = k - 1;
+    while (p[j] < p[i]) --j;
+    int t = p[i]; p[i] = p[j]; p[j] = t;
+    for (int a = i + 1, b = k - 1; a < b; ++a, --b) { t = p[a]; p[a] = p[b]; p[b] = t; }
+    return 1;
+}
+
+/* minimum code over all k! relabellings */
+uint32_t or_canon(int k, uint32_t c) {
+    unsigned char adj[OR_MAXK][OR_MAXK];
+    adj_from_code(k, c, adj);
+    int p[OR_MAXK];
+    for (int i = 0; i < k; ++i) p[i] = i;
+    uint32_t best = 0xffffffffu;
+    do {
+        /* relabelled graph: new vertex p[x] takes old vertex x */
+        uint32_t d = 0;
+        for (int i = 1; i < k; ++i)
+            for (int t = 0; t < i; ++t)
+                if (adj[t][i]) {
+                    int a = p[t], b = p[i];
+                    d |= 1u << (a < b ? pair_bit(a, b) : pair_bit(b, a));
+                }
+        if (d < best) best = d;
+    } while (next_perm(p, k));
+    return best;
+}
+
+typedef struct {
+    int ready;
+    int ncls;
+    uint32_t* canon;         /* ncls canonical codes, class order */
+    int16_t* class_of_code;  /* 2^(k(k-1)/2) entries, -1 when disconnected */
+    int64_t n_connected;     /* labelled connected graphs on k vertices */
+} class_info;
+
+static class_info g_cls[OR_MAX_MOTIF_K + 1];
+static pthread_mutex_t g_cls_lock = PTHREAD_MUTEX_INITIALIZER;
+
+static int cmp_canon(const void* a, const void* b) {
+    uint32_t x = *(const uint32_t*)a, y = *(const uint32_t*)b;
+    int px = __builtin_popcount(x), py = __builtin_popcount(y);
+    if (px != py) return px < py ? -1 : 1;
+    return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+static const class_info* classes(int k) {
+    if (k < 1 || k > OR_MAX_MOTIF_K) return NULL;
+    pthread_mutex_lock(&g_cls_lock);
+    class_info* ci = &g_cls[k];
+    if (!ci->ready) {
+        uint32_t ncodes = 1u << (k * (k - 1) / 2);
+        uint32_t* canon_of = (uint32_t*)malloc(sizeof(uint32_t) * ncodes);
+        uint32_t* uniq = (uint32_t*)malloc(sizeof(uint32_t) * ncodes);
+        int nu = 0;
+        ci->n_connected = 0;
+        for (uint32_t c = 0; c < ncodes; ++c) {
+            if (!connected_code(k, c)) { canon_of[c] = 0xffffffffu; continue; }
+            ci->n_connected++;
+            uint32_t cc = or_canon(k, c);
+            canon_of[c] = cc;
+            if (cc == c) uniq[nu++] = cc; /* the minimum of an orbit is its own canon */
+        }
+        qsort(uniq, (size_t)nu, sizeof(uint32_t), cmp_canon);
+        ci->ncls = nu;
+        ci->canon = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(nu > 0 ? nu : 1));
+        memcpy(ci->canon, uniq, sizeof(uint32_t) * (size_t)nu);
+        ci->class_of_code = (int16_t*)malloc(sizeof(int16_t) * ncodes);
+        for (uint32_t c = 0; c < ncodes; ++c) {
+            ci->class_of_code[c] = -1;
+            if (canon_of[c] == 0xffffffffu) continue;
+            for (int q = 0; q < nu; ++q)
+                if (ci->canon[q] == canon_of[c]) { ci->class_of_code[c] = (int16_t)q; break; }
+        }
+        free(canon_of);
+        free(uniq);
+        ci->ready = 1;
+    }
+    pthread_mutex_unlock(&g_cls_lock);
+    return ci;
+}
+
+/* number of classes of connected graphs on k vertices, -1 if unsupported */
+int or_num_classes(int k) {
+    const class_info* ci = classes(k);
+    return ci ? ci->ncls : -1;
+}
+
+/* canonical codes in class order; returns ncls */
+int or_class_canon(int k, uint32_t* out, int cap) {
+    const class_info* ci = classes(k);
+    if (!ci) return -1;
+    for (int q = 0; q < ci->ncls && q < cap; ++q) out[q] = ci->canon[q];
+    return ci->ncls;
+}
+
+int64_t or_num_connected_labelled(int k) {
+    const class_info* ci = classes(k);
+    return ci ? ci->n_connected : -1;
+}
+
+/* class of a full edge bitmap, -1 when disconnected or k unsupported */
+int or_class_of_code(int k, uint32_t code) {
+    const class_info* ci = classes(k);
+    if (!ci || code >= (1u << (k * (k - 1) / 2))) return -1;
+    return ci->class_of_code[code];
+}
+
+/* ====================================================================== */
+/* graph helpers                                                           */
+/* ====================================================================== */
+
+typedef struct {
+    int32_t n;
+    const int64_t* rp;
+    const int32_t* col;
+} graph_t;
+
+static int has_edge(const graph_t* g, int32_t a, int32_t b) {
+    int64_t lo = g->rp[a], hi = g->rp[a + 1];
+    while (lo < hi) {
+        int64_t mid = (lo + hi) / 2;
+        int32_t x = g->col[mid];
+        if (x == b) return 1;
+        if (x < b) lo = mid + 1; else hi = mid;
+    }
+    return 0;
+}
+
+static inline int64_t deg_of(const graph_t* g, int32_t v) { return g->rp[v + 1] - g->rp[v]; }
+
+/* ====================================================================== */
+/* L1: brute force over k-subsets                                          */
+/* ====================================================================== */
+
+/* out_total: number of k-cliques; per_root_leaves (nullable, n): credited to min rank */
+int or_clique_brute(int32_t n, const int64_t* rp, const int32_t* col, int k,
+                    uint64_t* out_total, uint64_t* per_root_leaves) {
+    graph_t g = { n, rp, col };
+    if (k < 1 || k > 32) return -1;
+    *out_total = 0;
+    if (per_root_leaves) memset(per_root_leaves, 0, sizeof(uint64_t) * (size_t)n);
+    if (k > n) return 0;
+    int idx[32];
+    for (int i = 0; i < k; ++i) idx[i] = i;
+    for (;;) {
+        int ok = 1;
+        for (int a = 0; a < k && ok; ++a)
+            for (int b = a + 1; b < k && ok; ++b)
+                if (!has_edge(&g, idx[a], idx[b])) ok = 0;
+        if (ok) {
+            (*out_total)++;
+            if (per_root_leaves) {
+                int r = idx[0];
+                for (int a = 1; a < k; ++a) {
+                    int x = idx[a];
+                    int64_t dx = deg_of(&g, x), dr = deg_of(&g, r);
+                    if (dx < dr || (dx == dr && x < r)) r = x;
+                }
+                per_root_leaves[r]++;
+            }
+        }
+        int i = k - 1;
+        while (i >= 0 && idx[i] == n - k + i) --i;
+        if (i < 0) break;
+        idx[i]++;
+        for (int j = i + 1; j < k; ++j) idx[j] = idx[j - 1] + 1;
+    }
+    return 0;
+}
+
+/* out_counts: ncls entries; per_root_leaves (nullable, n): connected k-sets by min id */
+int or_motif_brute(int32_t n, const int64_t* rp, const int32_t* col, int k,
+                   uint64_t* out_counts, uint64_t* per_root_leaves) {
+    graph_t g = { n, rp, col };
+    const class_info* ci = classes(k);
+    if (!ci || k < 2) return -1;
+    memset(out_counts, 0, sizeof(uint64_t) * (size_t)ci->ncls);
+    if (per_root_leaves) memset(per_root_leaves, 0, sizeof(uint64_t) * (size_t)n);
+    if (k > n) return 0;
+    int idx[OR_MAXK];
+    for (int i = 0; i < k; ++i) idx[i] = i;
+    unsigned char adj[OR_MAXK][OR_MAXK];
+    for (;;) {
+        memset(adj, 0, sizeof adj);
+        for (int a = 0; a < k; ++a)
+            for (int b = a + 1; b < k; ++b)
+                if (has_edge(&g, idx[a], idx[b])) adj[a][b] = adj[b][a] = 1;
+        uint32_t c = code_from_adj(k, adj);
+        int q = ci->class_of_code[c];
+        if (q >= 0) {
+            out_counts[q]++;
+            if (per_root_leaves) per_root_leaves[idx[0]]++;
+        }
+        int i = k - 1;
+        while (i >= 0 && idx[i] == n - k + i) --i;
+        if (i < 0) break;
+        idx[i]++;
+        for (int j = i + 1; j < k; ++j) idx[j] = idx[j - 1] + 1;
+    }
+    return 0;
+}
+
+/* ====================================================================== */
+/* L2 shared plumbing: a root list processed by a thread pool               */
+/* ====================================================================== */
+
+typedef struct {
+    graph_t g;
+    int k;
+    const int32_t* roots;
+    int64_t nroots;
+    atomic_llong next;
+    uint64_t* leaves;   /* nroots, nullable */
+    uint64_t* nodes;    /* nroots, nullable */
+    uint64_t* reads;    /* nroots, nullable */
+    /* clique */
+    const int64_t* rank;
+    const int64_t* outdeg;   /* neighbours of higher rank */
+    /* motif */
+    const class_info* ci;
+    /* reduction */
+    pthread_mutex_t lock;
+    uint64_t total;
+    uint64_t counts[128];
+    int overflow;
+} job_t;
+
+static void add_u64(uint64_t* acc, uint64_t x, int* ovf) {
+    if (__builtin_add_overflow(*acc, x, acc)) *ovf = 1;
+}
+
+/* ---------------------------------------------------------------- cliques */
+
+typedef struct {
+    uint64_t leaves, nodes, reads;
+    int ovf;
+    int32_t* buf[33];   /* candidate list per depth */
+    int64_t cap;
+} clq_ctx;
+
+
+/*
+ * cand: vertices (sorted by id) adjacent to every traversal vertex and ranked
+ * above the last one; s = traversal size.  The traversal is a clique of size s
+ * whose last vertex is `last`.
+ */
+static void clq_expand(const job_t* J, clq_ctx* C, int s, int32_t last, const int32_t* cand, int64_t nc) {
+    add_u64(&C->nodes, 1, &C->ovf);
+    add_u64(&C->reads, (uint64_t)J->outdeg[last], &C->ovf);
+    if (s == J->k - 1) { add_u64(&C->leaves, (uint64_t)nc, &C->ovf); return; }
+    int32_t* nxt = C->buf[s + 1];
+    for (int64_t i = 0; i < nc; ++i) {
+        int32_t u = cand[i];
+        /* cand ∩ N(u), keeping ranks above u (merge of two id-sorted lists) */
+        int64_t a = 0, b = J->g.rp[u], be = J->g.rp[u + 1], m = 0;
+        while (a < nc && b < be) {
+            int32_t x = cand[a], y = J->g.col[b];
+            if (x < y) a++;
+            else if (y < x) b++;
+            else { if (J->rank[x] > J->rank[u]) nxt[m++] = x; a++; b++; }
+        }
+        clq_expand(J, C, s + 1, u, nxt, m);
+    }
+}
+
+static void* clq_worker(void* arg) {
+    job_t* J = (job_t*)arg;
+    clq_ctx C;
+    memset(&C, 0, sizeof C);
+    int64_t maxd = 0;
+    for (int32_t v = 0; v < J->g.n; ++v) if (deg_of(&J->g, v) > maxd) maxd = deg_of(&J->g, v);
+    for (int s = 0; s <= J->k && s <= 32; ++s) C.buf[s] = (int32_t*)malloc(sizeof(int32_t) * (size_t)(maxd + 1));
+    uint64_t total = 0;
+    int ovf = 0;
+    for (;;) {
+        int64_t i = atomic_fetch_add(&J->next, 1);
+        if (i >= J->nroots) break;
+        int32_t r = J->roots[i];
+        C.leaves = C.nodes = C.reads = 0;
+        if (J->k == 1) {
+            C.leaves = 1;
+        } else {
+            int64_t m = 0;
+            for (int64_t e = J->g.rp[r]; e < J->g.rp[r + 1]; ++e)
+                if (J->rank[J->g.col[e]] > J->rank[r]) C.buf[1][m++] = J->g.col[e];
+            clq_expand(J, &C, 1, r, C.buf[1], m);
+        }
+        if (J->leaves) J->leaves[i] = C.leaves;
+        if (J->nodes) J->nodes[i] = C.nodes;
+        if (J->reads) J->reads[i] = C.reads;
+        add_u64(&total, C.leaves, &ovf);
+    }
+    for (int s = 0; s <= J->k && s <= 32; ++s) free(C.buf[s]);
+    pthread_mutex_lock(&J->lock);
+    add_u64(&J->total, total, &J->overflow);
+    if (ovf || C.ovf) J->overflow = 1;
+    pthread_mutex_unlock(&J->lock);
+    return NULL;
+}
+
+static int cmp_rank_key(const void* a, const void* b) {
+    const int64_t* x = (const int64_t*)a;
+    const int64_t* y = (const int64_t*)b;
+    if (x[0] != y[0]) return x[0] < y[0] ? -1 : 1;
+    return x[1] < y[1] ? -1 : (x[1] > y[1] ? 1 : 0);
+}
+
+/* rank[v] = position of v in (degree asc, id asc) order */
+static int64_t* make_rank(const graph_t* g) {
+    int64_t* key = (int64_t*)malloc(sizeof(int64_t) * 2 * (size_t)(g->n > 0 ? g->n : 1));
+    for (int32_t v = 0; v < g->n; ++v) { key[2 * v] = deg_of(g, v); key[2 * v + 1] = v; }
+    qsort(key, (size_t)g->n, 2 * sizeof(int64_t), cmp_rank_key);
+    int64_t* rank = (int64_t*)malloc(sizeof(int64_t) * (size_t)(g->n > 0 ? g->n : 1));
+    for (int32_t i = 0; i < g->n; ++i) rank[key[2 * i + 1]] = i;
+    free(key);
+    return rank;
+}
+
+static void run_pool(job_t* J, int nthreads, void* (*fn)(void*)) {
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > 256) nthreads = 256;
+    pthread_t th[256];
+    for (int t = 0; t < nthreads; ++t) pthread_create(&th[t], NULL, fn, J);
+    for (int t = 0; t < nthreads; ++t) pthread_join(th[t], NULL);
+}
+
+/*
+ * k-cliques credited to the listed roots (all vertices when roots == NULL).
+ * Returns 0, or 1 when a uint64 sum overflowed, or -1 on bad arguments.
+ */
+int or_clique_roots(int32_t n, const int64_t* rp, const int32_t* col, int k,
+                    const int32_t* roots, int64_t nroots, int nthreads, uint64_t* out_total,
+                    uint64_t* leaves, uint64_t* nodes, uint64_t* reads) {
+    if (k < 1 || k > 32 || n < 0) return -1;
+    job_t* J = (job_t*)calloc(1, sizeof(job_t));
+    J->g = (graph_t){ n, rp, col };
+    J->k = k;
+    int32_t* all = NULL;
+    if (!roots) {
+        all = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+        for (int32_t v = 0; v < n; ++v) all[v] = v;
+        roots = all;
+        nroots = n;
+    }
+    J->roots = roots;
+    J->nroots = nroots;
+    atomic_init(&J->next, 0);
+    J->leaves = leaves; J->nodes = nodes; J->reads = reads;
+    J->rank = make_rank(&J->g);
+    int64_t* od = (int64_t*)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
+    for (int32_t v = 0; v < n; ++v)
+        for (int64_t e = rp[v]; e < rp[v + 1]; ++e)
+            if (J->rank[col[e]] > J->rank[v]) od[v]++;
+    J->outdeg = od;
+    pthread_mutex_init(&J->lock, NULL);
+    run_pool(J, nthreads, clq_worker);
+    free(od);
+    *out_total = J->total;
+    int ret = J->overflow ? 1 : 0;
+    free((void*)J->rank);
+    free(all);
+    pthread_mutex_destroy(&J->lock);
+    free(J);
+    return ret;
+}
+
+/* ---------------------------------------------------------------- motifs (ESU) */
+
+typedef struct {
+    const job_t* J;
+    int32_t root;
+    int32_t sub[OR_MAXK];
+    int32_t* ext[OR_MAXK + 1];  /* extension list per depth */
+    int32_t* blocked;           /* # of sub vertices adjacent to x, or in sub (n entries) */
+    uint64_t leaves, nodes, reads;
+    uint64_t counts[128];
+    int ovf;
+} esu_ctx;
+
+static void esu_leaf(esu_ctx* E) {
+    const job_t* J = E->J;
+    int k = J->k;
+    uint32_t c = 0;
+    for (int i = 1; i < k; ++i)
+        for (int t = 0; t < i; ++t)
+            if (has_edge(&J->g, E->sub[t], E->sub[i])) c |= 1u << pair_bit(t, i);
+    int q = J->ci->class_of_code[c];
+    if (q >= 0) add_u64(&E->counts[q], 1, &E->ovf);
+    add_u64(&E->leaves, 1, &E->ovf);
+}
+
+/* mark / unmark the closed neighbourhood of a vertex that joins / leaves sub */
+static void esu_block(esu_ctx* E, int32_t w, int d) {
+    const graph_t* g = &E->J->g;
+    E->blocked[w] += d;
+    for (int64_t e = g->rp[w]; e < g->rp[w + 1]; ++e) E->blocked[g->col[e]] += d;
+}
+
+/*
+ * ESU step: sub has s vertices (blocked[] marks sub and N(sub)); ext holds
+ * candidate vertices (> root, in the exclusive neighbourhood) of length ne.
+ */
+static void esu_extend(esu_ctx* E, int s, const int32_t* ext, int64_t ne) {
+    const job_t* J = E->J;
+    const graph_t* g = &J->g;
+    if (s == J->k) { esu_leaf(E); return; }
+    add_u64(&E->nodes, 1, &E->ovf);
+    add_u64(&E->reads, (uint64_t)deg_of(g, E->sub[s - 1]), &E->ovf);
+    int32_t* nxt = E->ext[s + 1];
+    /* remove candidates one at a time from the back of the list */
+    for (int64_t i = ne - 1; i >= 0; --i) {
+        int32_t w = ext[i];
+        /* remaining extension: ext[0..i-1] plus exclusive neighbours of w above the root */
+        int64_t m = 0;
+        for (int64_t j = 0; j < i; ++j) nxt[m++] = ext[j];
+        for (int64_t e = g->rp[w]; e < g->rp[w + 1]; ++e) {
+            int32_t u = g->col[e];
+            if (u > E->root && E->blocked[u] == 0) nxt[m++] = u;
+        }
+        E->sub[s] = w;
+        esu_block(E, w, +1);
+        esu_extend(E, s + 1, nxt, m);
+        esu_block(E, w, -1);
+    }
+}
+
+static void* esu_worker(void* arg) {
+    job_t* J = (job_t*)arg;
+    esu_ctx E;
+    memset(&E, 0, sizeof E);
+    E.J = J;
+    int64_t maxd = 0;
+    for (int32_t v = 0; v < J->g.n; ++v) if (deg_of(&J->g, v) > maxd) maxd = deg_of(&J->g, v);
+    for (int s = 0; s <= J->k; ++s)
+        E.ext[s] = (int32_t*)malloc(sizeof(int32_t) * (size_t)((maxd + 1) * (s + 1) + 1));
+    E.blocked = (int32_t*)calloc((size_t)(J->g.n > 0 ? J->g.n : 1), sizeof(int32_t));
+    for (;;) {
+        int64_t i = atomic_fetch_add(&J->next, 1);
+        if (i >= J->nroots) break;
+        int32_t r = J->roots[i];
+        E.root = r;
+        E.leaves = E.nodes = E.reads = 0;
+        E.sub[0] = r;
+        if (J->k == 1) {
+            add_u64(&E.counts[0], 1, &E.ovf);
+            E.leaves = 1;
+        } else {
+            int64_t m = 0;
+            for (int64_t e = J->g.rp[r]; e < J->g.rp[r + 1]; ++e)
+                if (J->g.col[e] > r) E.ext[1][m++] = J->g.col[e];
+            esu_block(&E, r, +1);
+            esu_extend(&E, 1, E.ext[1], m);
+            esu_block(&E, r, -1);
+        }
+        if (J->leaves) J->leaves[i] = E.leaves;
+        if (J->nodes) J->nodes[i] = E.nodes;
+        if (J->reads) J->reads[i] = E.reads;
+    }
+    pthread_mutex_lock(&J->lock);
+    for (int q = 0; q < J->ci->ncls; ++q) add_u64(&J->counts[q], E.counts[q], &J->overflow);
+    if (E.ovf) J->overflow = 1;
+    pthread_mutex_unlock(&J->lock);
+    for (int s = 0; s <= J->k; ++s) free(E.ext[s]);
+    free(E.blocked);
+    return NULL;
+}
+
+/*
+ * Connected induced k-sets credited to the listed roots (all when roots == NULL),
+ * counted per class into out_counts (ncls entries).  Returns 0, 1 on overflow,
+ * -1 on bad arguments.
+ */
+int or_motif_roots(int32_t n, const int64_t* rp, const int32_t* col, int k,
+                   const int32_t* roots, int64_t nroots, int nthreads, uint64_t* out_counts,
+                   uint64_t* leaves, uint64_t* nodes, uint64_t* reads) {
+    const class_info* ci = classes(k);
+    if (!ci || n < 0 || k > OR_MAX_MOTIF_K) return -1;
+    job_t* J = (job_t*)calloc(1, sizeof(job_t));
+    J->g = (graph_t){ n, rp, col };
+    J->k = k;
+    J->ci = ci;
+    int32_t* all = NULL;
+    if (!roots) {
+        all = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+        for (int32_t v = 0; v < n; ++v) all[v] = v;
+        roots = all;
+        nroots = n;
+    }
+    J->roots = roots;
+    J->nroots = nroots;
+    atomic_init(&J->next, 0);
+    J->leaves = leaves; J->nodes = nodes; J->reads = reads;
+    pthread_mutex_init(&J->lock, NULL);
+    run_pool(J, nthreads, esu_worker);
+    for (int q = 0; q < ci->ncls; ++q) out_counts[q] = J->counts[q];
+    int ret = J->overflow ? 1 : 0;
+    free(all);
+    pthread_mutex_destroy(&J->lock);
+    free(J);
+    return ret;
+}
+
+/* ====================================================================== */
+/* per-vertex features (degree, 2-hop degree sum, core number, triangles)   */
+/* ====================================================================== */
+
+/* twohop[v] = sum of deg(u) over neighbours u of v */
+void or_twohop(int32_t n, const int64_t* rp, const int32_t* col, int64_t* out) {
+    for (int32_t v = 0; v < n; ++v) {
+        int64_t s = 0;
+        for (int64_t e = rp[v]; e < rp[v + 1]; ++e) s += rp[col[e] + 1] - rp[col[e]];
+        out[v] = s;
+    }
+}
+
+/* triangles containing each vertex: one pass over edges u < v, merging N(u), N(v) */
+void or_triangles(int32_t n, const int64_t* rp, const int32_t* col, int64_t* out) {
+    memset(out, 0, sizeof(int64_t) * (size_t)n);
+    for (int32_t u = 0; u < n; ++u)
+        for (int64_t e = rp[u]; e < rp[u + 1]; ++e) {
+            int32_t v = col[e];
+            if (v <= u) continue;
+            int64_t a = rp[u], b = rp[v];
+            while (a < rp[u + 1] && b < rp[v + 1]) {
+                int32_t x = col[a], y = col[b];
+                if (x < y) a++;
+                else if (y < x) b++;
+                else { if (x > v) { out[u]++; out[v]++; out[x]++; } a++; b++; }
+            }
+        }
+}
+
+/*
+ * Core numbers by repeated removal of a minimum-degree vertex (the peeling
+ * definition of the k-core decomposition), with the bucket queue of
+ * Batagelj & Zaversnik (2003).
+ */
+void or_core(int32_t n, const int64_t* rp, const int32_t* col, int32_t* core) {
+    if (n <= 0) return;
+    int32_t* deg = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t md = 0;
+    for (int32_t v = 0; v < n; ++v) { deg[v] = (int32_t)(rp[v + 1] - rp[v]); if (deg[v] > md) md = deg[v]; }
+    int32_t* bin = (int32_t*)calloc((size_t)md + 2, sizeof(int32_t));
+    int32_t* pos = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t* vert = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    for (int32_t v = 0; v < n; ++v) bin[deg[v]]++;
+    int32_t start = 0;
+    for (int32_t d = 0; d <= md; ++d) { int32_t num = bin[d]; bin[d] = start; start += num; }
+    for (int32_t v = 0; v < n; ++v) { pos[v] = bin[deg[v]]; vert[pos[v]] = v; bin[deg[v]]++; }
+    for (int32_t d = md; d >= 1; --d) bin[d] = bin[d - 1];
+    bin[0] = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        int32_t v = vert[i];
+        for (int64_t e = rp[v]; e < rp[v + 1]; ++e) {
+            int32_t u = col[e];
+            if (deg[u] > deg[v]) {
+                int32_t du = deg[u], pu = pos[u], pw = bin[du], w = vert[pw];
+                if (u != w) { pos[u] = pw; vert[pu] = w; pos[w] = pu; vert[pw] = u; }
+                bin[du]++;
+                deg[u]--;
+            }
+        }
+    }
+    for (int32_t v = 0; v < n; ++v) core[v] = deg[v];
+    free(deg); free(bin); free(pos); free(vert);
+}
