@@ -1,0 +1,172 @@
+/*
+ * dm.h — C ABI of libdumato_mi: exact k-clique and induced k-motif counting by
+ * DFS-wide subgraph enumeration on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: DuMato (Ferraz, Dias, Teixeira, Teodoro, Meira Jr., arXiv 2212.04551).
+ *   - Enumeration function E(G, tr, k) with property P and output A:
+ *     Section II, Eq. (1).
+ *   - Filter-process workflow (Control, Extend, Filter, Compact, Aggregate,
+ *     Move): Section IV-A; DFS-wide exploration: Section IV-B, Alg. 1 (Move);
+ *     Extend: Section IV-C, Alg. 2; Filter: Alg. 3; Compact and Aggregate:
+ *     Section IV-C.
+ *   - Clique and motif counting: Section IV-E, Alg. 4.
+ *   - Warp-level load balancing: Section IV-D (realised here inside the kernel,
+ *     the asynchronous form named as future work in Section VI).
+ *
+ * Conventions for every entry point:
+ *   - Graphs are simple and undirected (Section II): CSR with int64 row
+ *     offsets `row_ptr[n+1]` and int32 column ids `col[nnz]`, every adjacency
+ *     list sorted strictly ascending, no self-loops, both directions present.
+ *   - Counts are exact uint64.  Any uint64 wrap, in a per-wave accumulator or
+ *     in a global sum, returns DM_E_OVERFLOW; outputs are then unspecified.
+ *   - Output arrays are caller-owned HOST memory unless stated otherwise.
+ *     Calls return after the results are in host memory.
+ *   - GPU work is enqueued on `opt->stream` (a hipStream_t, e.g.
+ *     torch.cuda.current_stream().cuda_stream); NULL means the library's
+ *     own stream.  The call synchronises that stream before returning.
+ *   - On DM_E_ARG, DM_E_CSR, DM_E_K or DM_E_BUFSZ no output is written.
+ *   - A graph handle serves one call at a time; distinct handles may be used
+ *     from different threads.
+ *   - Nothing here throws; failures are reported by status code, and
+ *     dm_strerror / dm_last_error give text.
+ */
+#ifndef DM_H
+#define DM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dm_graph dm_graph; /* opaque, owned by the library, freed by dm_free */
+
+typedef enum {
+    DM_OK = 0,
+    DM_E_ARG = 1,      /* null pointer, negative size, bad flag or option */
+    DM_E_CSR = 2,      /* CSR rejected: unsorted/duplicate, self-loop, asymmetric, out of range */
+    DM_E_K = 3,        /* k outside the supported range for the operation */
+    DM_E_OVERFLOW = 4, /* a uint64 count wrapped */
+    DM_E_NOMEM = 5,    /* device or host allocation failed, or workspace cap exceeded */
+    DM_E_HIP = 6,      /* a HIP runtime call failed (text in dm_last_error) */
+    DM_E_BUFSZ = 7,    /* output buffer shorter than required */
+    DM_E_MODEL = 8     /* learned scheduling requested without valid parameters */
+} dm_status;
+
+/* dm_load_csr flags */
+enum {
+    DM_CSR_HOST = 0,    /* row_ptr / col are host pointers */
+    DM_CSR_DEVICE = 1,  /* row_ptr / col are device pointers (copied device-to-device) */
+    DM_CSR_TRUSTED = 2  /* skip validation (caller guarantees the conventions above) */
+};
+
+/* dm_options.sched bits */
+enum {
+    DM_SCHED_PLAIN = 0,    /* roots in natural order (rank order for cliques, id order for motifs) */
+    DM_SCHED_LEARNED = 1,  /* order and chunk roots by the MLP's predicted subtree size */
+    DM_SCHED_AUTOTUNE = 2, /* pick chunk / rebalance / waves-per-CU from the tuner cache */
+    DM_RECORD_ROOTS = 4,   /* write per-root {tree nodes, leaves, adjacency reads} */
+    DM_NO_DONATION = 8     /* disable in-kernel work donation (ablation: static schedule) */
+};
+
+enum { DM_OP_CLIQUE = 0, DM_OP_MOTIF = 1 };
+
+/*
+ * Options.  opt == NULL means all defaults (plain schedule).  `size` must be
+ * sizeof(dm_options) so the struct can grow.
+ */
+typedef struct {
+    uint32_t size;
+    uint32_t sched;          /* DM_SCHED_* | DM_RECORD_ROOTS | DM_NO_DONATION */
+    void* stream;            /* hipStream_t or NULL */
+    uint32_t chunk;          /* roots per queue grab; 0 = default */
+    float rebalance;         /* donate once at least this fraction of waves is idle; 0 = default */
+    uint32_t waves_per_cu;   /* resident waves per CU for the persistent grid; 0 = occupancy maximum */
+    const float* mlp;        /* DM_SCHED_LEARNED: device pointer to DM_MLP_NPARAMS floats */
+    const int32_t* roots;    /* host pointer: explicit root order/subset (original vertex ids),
+                                NULL = every vertex */
+    int64_t num_roots;       /* length of `roots` */
+    uint64_t* root_stats;    /* DM_RECORD_ROOTS: device pointer, 3 uint64 per root, indexed by
+                                vertex id (or by position in `roots` when given):
+                                {tree nodes, leaves, adjacency entries read} */
+    uint64_t* wave_stats;    /* optional device pointer, 4 uint64 per wave:
+                                {busy ticks, idle ticks, tree nodes, tasks taken} */
+    uint32_t wave_stats_len; /* number of waves wave_stats can hold */
+    uint64_t counter_bias;   /* test hook: global accumulators start at this value (0 normally) */
+} dm_options;
+
+/*
+ * Load a graph.  Arrays are borrowed for the call only and copied to the
+ * device; validated on the GPU unless DM_CSR_TRUSTED.  `stream` may be NULL.
+ * Errors: DM_E_ARG (n < 0, null pointers), DM_E_CSR (validation), DM_E_NOMEM,
+ * DM_E_HIP.  On error *out is NULL.
+ */
+dm_status dm_load_csr(int32_t n, const int64_t* row_ptr, const int32_t* col, uint32_t flags,
+                      void* stream, dm_graph** out);
+
+/* Free a handle (NULL is a no-op). */
+void dm_free(dm_graph* g);
+
+/* Vertex and adjacency-entry counts of a loaded graph. */
+dm_status dm_graph_info(const dm_graph* g, int32_t* n, int64_t* nnz);
+
+/*
+ * Number of k-cliques (Section IV-E, clique counting; Alg. 4 left).  The graph
+ * is oriented once by (degree, id) rank and cached on the handle; each clique
+ * is found from its lowest-rank vertex.  k in 1..32 (k=1 gives n, k=2 gives m).
+ * Errors: DM_E_ARG, DM_E_K, DM_E_OVERFLOW, DM_E_NOMEM, DM_E_HIP, DM_E_MODEL.
+ */
+dm_status dm_count_cliques(dm_graph* g, int k, uint64_t* out_count, const dm_options* opt);
+
+/* Number of connected k-vertex classes: 2, 6, 21, 112 for k = 3..6; -1 otherwise. */
+int dm_motif_num_classes(int k);
+
+/*
+ * Canonical adjacency of class `cls`: bit i(i-1)/2 + t set iff vertices t < i
+ * are adjacent, the minimum such bitmap over all relabellings.  Classes are
+ * numbered by (edge count, canonical bitmap) ascending.
+ * Errors: DM_E_K, DM_E_ARG (cls out of range or null pointer).
+ */
+dm_status dm_motif_class_mask(int k, int cls, uint32_t* upper_tri_mask);
+
+/*
+ * The canonical-relabeling dictionary of Section IV-C (Aggregate): entry c, for
+ * a traversal code c of 2^(k(k-1)/2 - 1) values (edge v0-v1 implied; vertex
+ * v_i, i >= 2, stores its edges to v_0..v_{i-1} in bits i(i-1)/2 - 1 + t),
+ * is the class id, or 0xFF when some v_i has no edge to its predecessors.
+ * `len` must be at least 2^(k(k-1)/2 - 1).  Host-only; needs no GPU.
+ */
+dm_status dm_motif_class_table(int k, uint8_t* out, size_t len);
+
+/*
+ * Per-class counts of connected induced k-vertex subgraphs (Section IV-E,
+ * motif counting; Alg. 4 right).  out_counts[cls] for cls < ncls(k); k in 3..6.
+ * Errors: DM_E_ARG, DM_E_K, DM_E_BUFSZ (out_len < ncls), DM_E_OVERFLOW,
+ * DM_E_NOMEM, DM_E_HIP, DM_E_MODEL.
+ */
+dm_status dm_count_motifs(dm_graph* g, int k, uint64_t* out_counts, size_t out_len,
+                          const dm_options* opt);
+
+/*
+ * Count many graphs in one persistent launch.  op is DM_OP_CLIQUE (one count
+ * per graph) or DM_OP_MOTIF (ncls(k) counts per graph).  out_counts is
+ * row-major [num_graphs][per-graph width].  The graphs are concatenated as a
+ * disjoint union (no traversal crosses graphs), so each row equals the count
+ * of the corresponding single-graph call.
+ * Errors: as the single-graph calls, plus DM_E_BUFSZ.
+ */
+dm_status dm_batch(dm_graph* const* gs, int32_t num_graphs, int op, int k, uint64_t* out_counts,
+                   size_t out_len, const dm_options* opt);
+
+/* Static text for a status code. */
+const char* dm_strerror(dm_status s);
+
+/* Text of the last error raised on the calling thread ("" if none). */
+const char* dm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DM_H */

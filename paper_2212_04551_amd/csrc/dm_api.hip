@@ -1,0 +1,774 @@
+// C ABI of libdumato_mi (declared in include/dm.h).
+//
+// Host side of the library: graph handles, input validation, the canonical
+// relabeling dictionary (DuMato, Section IV-C, Aggregate), workspace, the
+// persistent-kernel launch for clique and motif counting (Section IV-E,
+// Alg. 4), batching of many graphs into one launch, and the final uint64
+// reduction with overflow checks.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "dm.h"
+#include "dm_internal.hpp"
+
+using namespace dm;
+
+// ====================================================================== errors
+
+static thread_local std::string g_last_error;
+
+static dm_status fail(dm_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+static dm_status hip_fail(hipError_t e, const char* where) {
+  g_last_error = std::string(where) + ": " + hipGetErrorString(e);
+  return e == hipErrorOutOfMemory ? DM_E_NOMEM : DM_E_HIP;
+}
+
+#define HIP_OR_RETURN(expr, where)            \
+  do {                                        \
+    hipError_t e_ = (expr);                   \
+    if (e_ != hipSuccess) return hip_fail(e_, where); \
+  } while (0)
+
+extern "C" const char* dm_strerror(dm_status s) {
+  switch (s) {
+    case DM_OK: return "ok";
+    case DM_E_ARG: return "invalid argument";
+    case DM_E_CSR: return "invalid CSR graph";
+    case DM_E_K: return "k out of supported range";
+    case DM_E_OVERFLOW: return "uint64 count overflow";
+    case DM_E_NOMEM: return "out of memory";
+    case DM_E_HIP: return "HIP runtime error";
+    case DM_E_BUFSZ: return "output buffer too small";
+    case DM_E_MODEL: return "invalid or missing model parameters";
+  }
+  return "unknown status";
+}
+
+extern "C" const char* dm_last_error(void) { return g_last_error.c_str(); }
+
+// ====================================================================== class tables
+
+namespace {
+
+struct ClassTables {
+  int ncls = 0;
+  std::vector<uint32_t> canon;   // class -> canonical full bitmap
+  std::vector<uint8_t> table;    // traversal code -> class (0xFF unreachable)
+};
+
+inline int pair_index(int t, int i) { return i * (i - 1) / 2 + t; }  // t < i
+
+bool bitmap_connected(int k, uint32_t code) {
+  uint32_t adj[8] = {0};
+  for (int i = 1; i < k; ++i)
+    for (int t = 0; t < i; ++t)
+      if ((code >> pair_index(t, i)) & 1u) {
+        adj[t] |= 1u << i;
+        adj[i] |= 1u << t;
+      }
+  uint32_t reach = 1u, prev = 0u;
+  while (reach != prev) {
+    prev = reach;
+    for (int v = 0; v < k; ++v)
+      if ((reach >> v) & 1u) reach |= adj[v];
+  }
+  return reach == (1u << k) - 1u;
+}
+
+// Canonical forms by orbit enumeration: every permutation of S_k is turned
+// into a map of bitmap positions (Heap's algorithm), each still-unlabelled
+// connected bitmap has its whole orbit generated, and the orbit minimum is
+// the canonical form of all its members.
+ClassTables build_tables(int k) {
+  ClassTables T;
+  const int P = k * (k - 1) / 2;
+  const uint32_t ncodes = 1u << P;
+  std::vector<std::vector<uint8_t>> perm_maps;
+  {
+    std::vector<int> p(k), c(k, 0);
+    std::iota(p.begin(), p.end(), 0);
+    auto add = [&]() {
+      std::vector<uint8_t> m(P);
+      for (int i = 1; i < k; ++i)
+        for (int t = 0; t < i; ++t) {
+          int a = p[t], b = p[i];
+          if (a > b) std::swap(a, b);
+          m[pair_index(t, i)] = static_cast<uint8_t>(pair_index(a, b));
+        }
+      perm_maps.push_back(std::move(m));
+    };
+    add();
+    int i = 0;
+    while (i < k) {
+      if (c[i] < i) {
+        if (i % 2 == 0) std::swap(p[0], p[i]); else std::swap(p[c[i]], p[i]);
+        add();
+        ++c[i];
+        i = 0;
+      } else {
+        c[i] = 0;
+        ++i;
+      }
+    }
+  }
+  const uint32_t kNone = 0xffffffffu;
+  std::vector<uint32_t> canon_of(ncodes, kNone);
+  std::vector<uint32_t> reps;
+  std::vector<uint32_t> orbit;
+  for (uint32_t c = 0; c < ncodes; ++c) {
+    if (canon_of[c] != kNone || !bitmap_connected(k, c)) continue;
+    orbit.clear();
+    uint32_t best = c;
+    for (const auto& m : perm_maps) {
+      uint32_t d = 0;
+      for (int b = 0; b < P; ++b)
+        if ((c >> b) & 1u) d |= 1u << m[b];
+      orbit.push_back(d);
+      best = std::min(best, d);
+    }
+    for (uint32_t d : orbit) canon_of[d] = best;
+    reps.push_back(best);
+  }
+  std::sort(reps.begin(), reps.end(), [](uint32_t a, uint32_t b) {
+    const int pa = __builtin_popcount(a), pb = __builtin_popcount(b);
+    return pa != pb ? pa < pb : a < b;
+  });
+  T.ncls = static_cast<int>(reps.size());
+  T.canon = reps;
+  std::map<uint32_t, int> id;
+  for (int q = 0; q < T.ncls; ++q) id[reps[q]] = q;
+  // traversal code t: full bitmap (t << 1) | 1 (edge v0-v1 implied)
+  const uint32_t ntrav = 1u << (P - 1);
+  T.table.assign(ntrav, 0xFF);
+  for (uint32_t t = 0; t < ntrav; ++t) {
+    bool reach = true;
+    for (int i = 2; i < k; ++i) {
+      const uint32_t field = (t >> (i * (i - 1) / 2 - 1)) & ((1u << i) - 1u);
+      if (!field) reach = false;
+    }
+    if (!reach) continue;
+    const uint32_t full = (t << 1) | 1u;
+    T.table[t] = static_cast<uint8_t>(id.at(canon_of[full]));
+  }
+  return T;
+}
+
+std::mutex g_tables_lock;
+ClassTables* g_tables[8] = {nullptr};
+
+const ClassTables* tables(int k) {
+  if (k < 3 || k > 6) return nullptr;
+  std::lock_guard<std::mutex> lk(g_tables_lock);
+  if (!g_tables[k]) g_tables[k] = new ClassTables(build_tables(k));
+  return g_tables[k];
+}
+
+// device copies of the dictionary, per (device, k)
+std::mutex g_dev_tables_lock;
+std::map<std::pair<int, int>, uint8_t*> g_dev_tables;
+
+hipError_t device_table(int k, uint8_t** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(g_dev_tables_lock);
+  auto key = std::make_pair(dev, k);
+  auto it = g_dev_tables.find(key);
+  if (it != g_dev_tables.end()) {
+    *out = it->second;
+    return hipSuccess;
+  }
+  const ClassTables* T = tables(k);
+  uint8_t* p = nullptr;
+  e = hipMalloc(&p, T->table.size());
+  if (e != hipSuccess) return e;
+  e = hipMemcpy(p, T->table.data(), T->table.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(p);
+    return e;
+  }
+  g_dev_tables[key] = p;
+  *out = p;
+  return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" int dm_motif_num_classes(int k) {
+  const ClassTables* T = tables(k);
+  return T ? T->ncls : -1;
+}
+
+extern "C" dm_status dm_motif_class_mask(int k, int cls, uint32_t* mask) {
+  const ClassTables* T = tables(k);
+  if (!T) return fail(DM_E_K, "motif k must be in 3..6");
+  if (!mask || cls < 0 || cls >= T->ncls) return fail(DM_E_ARG, "class id out of range or null output");
+  *mask = T->canon[cls];
+  return DM_OK;
+}
+
+extern "C" dm_status dm_motif_class_table(int k, uint8_t* out, size_t len) {
+  const ClassTables* T = tables(k);
+  if (!T) return fail(DM_E_K, "motif k must be in 3..6");
+  if (!out) return fail(DM_E_ARG, "null output");
+  if (len < T->table.size()) return fail(DM_E_BUFSZ, "table needs 2^(k(k-1)/2-1) bytes");
+  std::memcpy(out, T->table.data(), T->table.size());
+  return DM_OK;
+}
+
+// ====================================================================== graph handles
+
+struct Buf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  ~Buf() {
+    if (p) (void)hipFree(p);
+  }
+  hipError_t ensure(size_t need) {
+    if (need == 0) need = 16;
+    if (bytes >= need) return hipSuccess;
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+    hipError_t e = hipMalloc(&p, need);
+    if (e == hipSuccess) bytes = need;
+    return e;
+  }
+  template <class T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
+struct dm_graph {
+  uint64_t uid = 0;  // process-unique id (batch cache key)
+  int device = 0;
+  int32_t n = 0;
+  int64_t nnz = 0;
+  int dmax = 0;
+  Buf rp, col;
+  // degree-ordered DAG (clique counting), built on first use
+  bool dag = false;
+  int ddmax = 0;
+  Buf rank, order, drp, dcol;
+  // workspace reused across calls
+  Buf ctrl, out, rows, ext_vert, ext_mask, newbuf, qroot, qstat, qlo, qhi, qbounds, rgraph;
+  hipStream_t own = nullptr;
+};
+
+static hipStream_t pick_stream(dm_graph* g, void* s) {
+  if (s) return static_cast<hipStream_t>(s);
+  if (!g->own) (void)hipStreamCreateWithFlags(&g->own, hipStreamNonBlocking);
+  return g->own;
+}
+
+// Host-side check of the CSR conventions (simple undirected graph, sorted lists).
+static bool host_validate(int32_t n, const int64_t* rp, const int32_t* col, std::string* why) {
+  if (rp[0] != 0) { *why = "row_ptr[0] != 0"; return false; }
+  for (int32_t v = 0; v < n; ++v)
+    if (rp[v + 1] < rp[v]) { *why = "row_ptr decreases"; return false; }
+  for (int32_t v = 0; v < n; ++v) {
+    for (int64_t i = rp[v]; i < rp[v + 1]; ++i) {
+      const int32_t u = col[i];
+      if (u < 0 || u >= n) { *why = "column id out of range"; return false; }
+      if (u == v) { *why = "self-loop"; return false; }
+      if (i > rp[v] && col[i - 1] >= u) { *why = "adjacency not strictly ascending (or repeated edge)"; return false; }
+      const int32_t* b = col + rp[u];
+      const int32_t* e = col + rp[u + 1];
+      const int32_t* f = std::lower_bound(b, e, v);
+      if (f == e || *f != v) { *why = "asymmetric adjacency"; return false; }
+    }
+  }
+  return true;
+}
+
+extern "C" dm_status dm_load_csr(int32_t n, const int64_t* row_ptr, const int32_t* col, uint32_t flags, void* stream,
+                                 dm_graph** out) {
+  if (!out) return fail(DM_E_ARG, "null output handle");
+  *out = nullptr;
+  if (n < 0 || !row_ptr || (!col && n > 0)) return fail(DM_E_ARG, "n < 0 or null CSR array");
+  if (flags & ~3u) return fail(DM_E_ARG, "unknown flag");
+  const bool on_device = flags & DM_CSR_DEVICE;
+  const bool trusted = flags & DM_CSR_TRUSTED;
+  int64_t nnz = 0;
+  if (!on_device) {
+    nnz = row_ptr[n];
+    if (nnz < 0 || nnz % 2) return fail(DM_E_CSR, "nnz must be even and non-negative");
+    std::string why;
+    if (!trusted && !host_validate(n, row_ptr, col, &why)) return fail(DM_E_CSR, why);
+  }
+  dm_graph* g = new dm_graph();
+  static std::atomic<uint64_t> next_uid{1};
+  g->uid = next_uid++;
+  (void)hipGetDevice(&g->device);
+  hipStream_t s = pick_stream(g, stream);
+  auto bail = [&](dm_status st) {
+    dm_free(g);
+    return st;
+  };
+  if (on_device) {
+    hipError_t e = hipMemcpyAsync(&nnz, row_ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return bail(hip_fail(e, "dm_load_csr: read nnz"));
+    if (nnz < 0 || nnz % 2) return bail(fail(DM_E_CSR, "nnz must be even and non-negative"));
+  }
+  g->n = n;
+  g->nnz = nnz;
+  hipError_t e = g->rp.ensure(sizeof(int64_t) * (static_cast<size_t>(n) + 1));
+  if (e == hipSuccess) e = g->col.ensure(sizeof(int32_t) * static_cast<size_t>(nnz > 0 ? nnz : 1));
+  if (e != hipSuccess) return bail(hip_fail(e, "dm_load_csr: allocate"));
+  const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  e = hipMemcpyAsync(g->rp.p, row_ptr, sizeof(int64_t) * (static_cast<size_t>(n) + 1), kind, s);
+  if (e == hipSuccess && nnz > 0) e = hipMemcpyAsync(g->col.p, col, sizeof(int32_t) * nnz, kind, s);
+  if (e != hipSuccess) return bail(hip_fail(e, "dm_load_csr: copy"));
+  // device-side validation and maximum degree share one small scratch word pair
+  Buf tmp;
+  e = tmp.ensure(2 * sizeof(int));
+  if (e == hipSuccess) e = launch_fill_i32(tmp.as<int>(), 2, 0, s);
+  if (e == hipSuccess && on_device && !trusted && n > 0)
+    e = launch_validate(g->rp.as<int64_t>(), g->col.as<int32_t>(), n, nnz, tmp.as<int>(), s);
+  if (e == hipSuccess && n > 0) e = launch_max_degree(g->rp.as<int64_t>(), n, tmp.as<int>() + 1, s);
+  int hostw[2] = {0, 0};
+  if (e == hipSuccess) e = hipMemcpyAsync(hostw, tmp.p, 2 * sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return bail(hip_fail(e, "dm_load_csr: validate"));
+  if (hostw[0]) {
+    char buf[96];
+    std::snprintf(buf, sizeof buf, "device CSR validation failed (flags 0x%x)", hostw[0]);
+    return bail(fail(DM_E_CSR, buf));
+  }
+  g->dmax = hostw[1];
+  *out = g;
+  return DM_OK;
+}
+
+extern "C" void dm_free(dm_graph* g) {
+  if (!g) return;
+  if (g->own) (void)hipStreamDestroy(g->own);
+  delete g;
+}
+
+extern "C" dm_status dm_graph_info(const dm_graph* g, int32_t* n, int64_t* nnz) {
+  if (!g) return fail(DM_E_ARG, "null graph");
+  if (n) *n = g->n;
+  if (nnz) *nnz = g->nnz;
+  return DM_OK;
+}
+
+static dm_status ensure_dag(dm_graph* g, hipStream_t s) {
+  if (g->dag) return DM_OK;
+  const size_t n1 = static_cast<size_t>(g->n) + 1;
+  HIP_OR_RETURN(g->rank.ensure(sizeof(int32_t) * n1), "orient: allocate");
+  HIP_OR_RETURN(g->order.ensure(sizeof(int32_t) * n1), "orient: allocate");
+  HIP_OR_RETURN(g->drp.ensure(sizeof(int64_t) * n1), "orient: allocate");
+  HIP_OR_RETURN(g->dcol.ensure(sizeof(int32_t) * static_cast<size_t>(g->nnz / 2 + 1)), "orient: allocate");
+  HIP_OR_RETURN(orient_by_degree(g->rp.as<int64_t>(), g->col.as<int32_t>(), g->n, g->nnz, g->rank.as<int32_t>(),
+                                 g->order.as<int32_t>(), g->drp.as<int64_t>(), g->dcol.as<int32_t>(), &g->ddmax, s),
+                "orient");
+  g->dag = true;
+  return DM_OK;
+}
+
+// ====================================================================== options
+
+namespace {
+
+struct Opt {
+  uint32_t sched = 0;
+  hipStream_t stream = nullptr;
+  uint32_t chunk = 0;
+  float rebalance = 0.f;
+  uint32_t waves_per_cu = 0;
+  const float* mlp = nullptr;
+  const int32_t* roots = nullptr;
+  int64_t num_roots = 0;
+  uint64_t* root_stats = nullptr;
+  uint64_t* wave_stats = nullptr;
+  uint32_t wave_stats_len = 0;
+  uint64_t bias = 0;
+};
+
+dm_status read_opt(const dm_options* o, Opt* r) {
+  *r = Opt();
+  if (!o) return DM_OK;
+  if (o->size != sizeof(dm_options)) return fail(DM_E_ARG, "dm_options.size != sizeof(dm_options)");
+  if (o->sched & ~15u) return fail(DM_E_ARG, "unknown sched bits");
+  if (o->rebalance < 0.f || o->rebalance > 1.f) return fail(DM_E_ARG, "rebalance must be in [0, 1]");
+  if (o->num_roots < 0 || (o->num_roots > 0 && !o->roots)) return fail(DM_E_ARG, "bad root list");
+  if ((o->sched & DM_RECORD_ROOTS) && !o->root_stats) return fail(DM_E_ARG, "DM_RECORD_ROOTS needs root_stats");
+  r->sched = o->sched;
+  r->stream = static_cast<hipStream_t>(o->stream);
+  r->chunk = o->chunk;
+  r->rebalance = o->rebalance;
+  r->waves_per_cu = o->waves_per_cu;
+  r->mlp = o->mlp;
+  r->roots = o->roots;
+  r->num_roots = o->roots ? o->num_roots : 0;
+  r->root_stats = (o->sched & DM_RECORD_ROOTS) ? o->root_stats : nullptr;
+  r->wave_stats = o->wave_stats;
+  r->wave_stats_len = o->wave_stats ? o->wave_stats_len : 0;
+  r->bias = o->counter_bias;
+  return DM_OK;
+}
+
+int cu_count() {
+  int dev = 0, cus = 0;
+  (void)hipGetDevice(&dev);
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+  return cus;
+}
+
+constexpr int kSlots = 1024;
+constexpr size_t kCtrlHead = 0;    // u64 qhead
+constexpr size_t kCtrlState = 8;   // u64 state
+constexpr size_t kCtrlIdle = 16;   // int idle
+constexpr size_t kCtrlFlags = 20;  // int flags[2]
+constexpr size_t kCtrlSlots = 32;  // int slot_state[kSlots], then slot_data
+
+size_t ctrl_bytes() { return kCtrlSlots + sizeof(int) * kSlots + sizeof(int) * kSlots * kTaskInts; }
+
+// scheduler fields common to both kernels
+Sched make_sched(dm_graph* g, const Opt& o, int grid, int64_t nq, const int32_t* qroot, const int32_t* qstat) {
+  Sched S{};
+  char* c = g->ctrl.as<char>();
+  S.qhead = reinterpret_cast<unsigned long long*>(c + kCtrlHead);
+  S.state = reinterpret_cast<unsigned long long*>(c + kCtrlState);
+  S.idle = reinterpret_cast<int*>(c + kCtrlIdle);
+  S.slot_state = reinterpret_cast<int*>(c + kCtrlSlots);
+  S.slot_data = reinterpret_cast<int*>(c + kCtrlSlots + sizeof(int) * kSlots);
+  S.qroot = qroot;
+  S.qlo = nullptr;
+  S.qhi = nullptr;
+  S.qstat = qstat;
+  S.qbounds = nullptr;
+  S.nq = nq;
+  S.nchunks = 0;
+  S.chunk = o.chunk ? static_cast<int>(o.chunk) : 1;
+  S.nslots = kSlots;
+  S.donate = (o.sched & DM_NO_DONATION) ? 0 : 1;
+  const float r = o.rebalance > 0.f ? o.rebalance : 0.0f;
+  int trig = static_cast<int>(r * grid);
+  S.idle_trigger = trig < 1 ? 1 : trig;
+  S.period = 8;
+  return S;
+}
+
+int* ctrl_flags(dm_graph* g) { return reinterpret_cast<int*>(g->ctrl.as<char>() + kCtrlFlags); }
+
+}  // namespace
+
+// ====================================================================== launches
+
+namespace {
+
+// Common tail: copy counters and flags, synchronise, map flags to a status.
+dm_status finish(dm_graph* g, hipStream_t s, uint64_t* host_out, size_t count) {
+  int flags[2] = {0, 0};
+  hipError_t e = hipMemcpyAsync(host_out, g->out.p, sizeof(uint64_t) * count, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(flags, ctrl_flags(g), sizeof flags, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "kernel / copy-back");
+  if (flags[1]) {
+    char buf[96];
+    std::snprintf(buf, sizeof buf, "internal capacity check failed (0x%x)", flags[1]);
+    return fail(DM_E_HIP, buf);
+  }
+  if (flags[0]) return fail(DM_E_OVERFLOW, "a uint64 counter wrapped");
+  return DM_OK;
+}
+
+// queue of explicit roots (original ids), optionally mapped into rank space
+dm_status upload_roots(dm_graph* g, const Opt& o, bool to_rank, hipStream_t s) {
+  const size_t bytes = sizeof(int32_t) * static_cast<size_t>(o.num_roots);
+  HIP_OR_RETURN(g->qroot.ensure(bytes), "roots: allocate");
+  for (int64_t i = 0; i < o.num_roots; ++i)
+    if (o.roots[i] < 0 || o.roots[i] >= g->n) return fail(DM_E_ARG, "root id out of range");
+  if (!to_rank) {
+    HIP_OR_RETURN(hipMemcpyAsync(g->qroot.p, o.roots, bytes, hipMemcpyHostToDevice, s), "roots: copy");
+    return DM_OK;
+  }
+  HIP_OR_RETURN(g->qlo.ensure(bytes), "roots: allocate");
+  HIP_OR_RETURN(hipMemcpyAsync(g->qlo.p, o.roots, bytes, hipMemcpyHostToDevice, s), "roots: copy");
+  HIP_OR_RETURN(launch_gather_i32(g->rank.as<int32_t>(), g->qlo.as<int32_t>(), g->qroot.as<int32_t>(), o.num_roots, s),
+                "roots: map");
+  return DM_OK;
+}
+
+dm_status clique_run(dm_graph* g, int k, const Opt& o, hipStream_t s, const int32_t* root_graph, int ngraphs,
+                     uint64_t* host_out) {
+  dm_status st = ensure_dag(g, s);
+  if (st != DM_OK) return st;
+  const int dmax = g->ddmax > 0 ? g->ddmax : 1;
+  const int W = (dmax + 63) / 64;
+  bool rows_lds = true;
+  size_t lds = clique_lds_bytes(dmax, W, k, true);
+  if (lds > 64 * 1024) {
+    rows_lds = false;
+    lds = clique_lds_bytes(dmax, W, k, false);
+  }
+  if (lds > 160 * 1024) return fail(DM_E_NOMEM, "maximum out-degree too large for the LDS stack");
+  int per_cu = 0;
+  HIP_OR_RETURN(clique_occupancy(rows_lds, lds, &per_cu), "occupancy");
+  if (per_cu < 1) per_cu = 1;
+  if (o.waves_per_cu && static_cast<int>(o.waves_per_cu) < per_cu) per_cu = static_cast<int>(o.waves_per_cu);
+  const int grid = per_cu * cu_count();
+  // queue
+  int64_t nq = g->n;
+  const int32_t* qroot = nullptr;
+  const int32_t* qstat = g->order.as<int32_t>();
+  if (o.roots) {
+    st = upload_roots(g, o, true, s);
+    if (st != DM_OK) return st;
+    nq = o.num_roots;
+    qroot = g->qroot.as<int32_t>();
+    qstat = nullptr;
+  }
+  HIP_OR_RETURN(g->ctrl.ensure(ctrl_bytes()), "workspace");
+  HIP_OR_RETURN(g->out.ensure(sizeof(uint64_t) * ngraphs), "workspace");
+  if (!rows_lds) HIP_OR_RETURN(g->rows.ensure(sizeof(uint64_t) * static_cast<size_t>(grid) * W * dmax), "workspace");
+  HIP_OR_RETURN(launch_fill_u64(g->ctrl.as<unsigned long long>(), static_cast<int64_t>(ctrl_bytes() / 8), 0ull, s),
+                "clear");
+  HIP_OR_RETURN(launch_fill_u64(g->out.as<unsigned long long>(), ngraphs, o.bias, s), "clear");
+  if (o.root_stats)
+    HIP_OR_RETURN(launch_fill_u64(reinterpret_cast<unsigned long long*>(o.root_stats), 3 * (o.roots ? o.num_roots : g->n),
+                                  0ull, s),
+                  "clear");
+  CliqueArgs A{};
+  A.rp = g->drp.as<int64_t>();
+  A.col = g->dcol.as<int32_t>();
+  A.n = g->n;
+  A.k = k;
+  A.dmax = dmax;
+  A.W = W;
+  A.out = g->out.as<unsigned long long>();
+  A.root_graph = root_graph;
+  A.flags = ctrl_flags(g);
+  A.root_stats = reinterpret_cast<unsigned long long*>(o.root_stats);
+  A.wave_stats = reinterpret_cast<unsigned long long*>(o.wave_stats);
+  A.wave_stats_len = static_cast<int>(o.wave_stats_len);
+  A.rows_global = rows_lds ? nullptr : g->rows.as<unsigned long long>();
+  A.prune = o.root_stats ? 0 : 1;
+  A.S = make_sched(g, o, grid, nq, qroot, qstat);
+  if (nq > 0) HIP_OR_RETURN(launch_clique(A, grid, rows_lds, lds, s), "clique kernel launch");
+  return finish(g, s, host_out, static_cast<size_t>(ngraphs));
+}
+
+dm_status motif_run(dm_graph* g, int k, const Opt& o, hipStream_t s, const int32_t* root_graph, int ngraphs,
+                    uint64_t* host_out) {
+  const ClassTables* T = tables(k);
+  uint8_t* dtab = nullptr;
+  HIP_OR_RETURN(device_table(k, &dtab), "class table upload");
+  const int dmax = g->dmax > 0 ? g->dmax : 1;
+  const size_t lds = motif_lds_bytes(k, T->ncls);
+  int per_cu = 0;
+  HIP_OR_RETURN(motif_occupancy(lds, &per_cu), "occupancy");
+  if (per_cu < 1) per_cu = 1;
+  if (per_cu > 16) per_cu = 16;  // the extension stacks live in global memory; bound the footprint
+  if (o.waves_per_cu && static_cast<int>(o.waves_per_cu) < per_cu) per_cu = static_cast<int>(o.waves_per_cu);
+  const int grid = per_cu * cu_count();
+  MotifArgs A{};
+  int64_t cap_total = 0;
+  for (int s2 = 1; s2 <= k - 2 && s2 < 8; ++s2) {
+    A.level_off[s2] = cap_total;
+    A.level_cap[s2] = static_cast<int64_t>(s2) * dmax;
+    cap_total += A.level_cap[s2];
+  }
+  int64_t nq = g->n;
+  const int32_t* qroot = nullptr;
+  if (o.roots) {
+    dm_status st = upload_roots(g, o, false, s);
+    if (st != DM_OK) return st;
+    nq = o.num_roots;
+    qroot = g->qroot.as<int32_t>();
+  }
+  HIP_OR_RETURN(g->ctrl.ensure(ctrl_bytes()), "workspace");
+  HIP_OR_RETURN(g->out.ensure(sizeof(uint64_t) * static_cast<size_t>(ngraphs) * T->ncls), "workspace");
+  HIP_OR_RETURN(g->ext_vert.ensure(sizeof(int32_t) * static_cast<size_t>(grid) * cap_total), "workspace");
+  HIP_OR_RETURN(g->ext_mask.ensure(static_cast<size_t>(grid) * cap_total), "workspace");
+  HIP_OR_RETURN(g->newbuf.ensure(sizeof(int32_t) * static_cast<size_t>(grid) * dmax), "workspace");
+  HIP_OR_RETURN(launch_fill_u64(g->ctrl.as<unsigned long long>(), static_cast<int64_t>(ctrl_bytes() / 8), 0ull, s),
+                "clear");
+  HIP_OR_RETURN(launch_fill_u64(g->out.as<unsigned long long>(), static_cast<int64_t>(ngraphs) * T->ncls, o.bias, s),
+                "clear");
+  if (o.root_stats)
+    HIP_OR_RETURN(launch_fill_u64(reinterpret_cast<unsigned long long*>(o.root_stats), 3 * (o.roots ? o.num_roots : g->n),
+                                  0ull, s),
+                  "clear");
+  A.rp = g->rp.as<int64_t>();
+  A.col = g->col.as<int32_t>();
+  A.n = g->n;
+  A.k = k;
+  A.dmax = dmax;
+  A.ncls = T->ncls;
+  A.table = dtab;
+  A.out = g->out.as<unsigned long long>();
+  A.root_graph = root_graph;
+  A.flags = ctrl_flags(g);
+  A.root_stats = reinterpret_cast<unsigned long long*>(o.root_stats);
+  A.wave_stats = reinterpret_cast<unsigned long long*>(o.wave_stats);
+  A.wave_stats_len = static_cast<int>(o.wave_stats_len);
+  A.ext_vert = g->ext_vert.as<int32_t>();
+  A.ext_mask = g->ext_mask.as<uint8_t>();
+  A.new_buf = g->newbuf.as<int32_t>();
+  A.wave_ext_cap = cap_total;
+  A.S = make_sched(g, o, grid, nq, qroot, nullptr);
+  if (nq > 0) HIP_OR_RETURN(launch_motif(A, grid, lds, s), "motif kernel launch");
+  return finish(g, s, host_out, static_cast<size_t>(ngraphs) * T->ncls);
+}
+
+}  // namespace
+
+extern "C" dm_status dm_count_cliques(dm_graph* g, int k, uint64_t* out_count, const dm_options* opt) {
+  if (!g || !out_count) return fail(DM_E_ARG, "null graph or output");
+  if (k < 1 || k > kMaxK) return fail(DM_E_K, "clique k must be in 1..32");
+  Opt o;
+  dm_status st = read_opt(opt, &o);
+  if (st != DM_OK) return st;
+  if ((o.sched & DM_SCHED_LEARNED) && !o.mlp) return fail(DM_E_MODEL, "DM_SCHED_LEARNED needs mlp parameters");
+  hipStream_t s = pick_stream(g, o.stream);
+  uint64_t c = 0;
+  st = clique_run(g, k, o, s, nullptr, 1, &c);
+  if (st == DM_OK) *out_count = c;
+  return st;
+}
+
+extern "C" dm_status dm_count_motifs(dm_graph* g, int k, uint64_t* out_counts, size_t out_len, const dm_options* opt) {
+  if (!g || !out_counts) return fail(DM_E_ARG, "null graph or output");
+  const ClassTables* T = tables(k);
+  if (!T) return fail(DM_E_K, "motif k must be in 3..6");
+  if (out_len < static_cast<size_t>(T->ncls)) return fail(DM_E_BUFSZ, "out_len < number of classes");
+  Opt o;
+  dm_status st = read_opt(opt, &o);
+  if (st != DM_OK) return st;
+  if ((o.sched & DM_SCHED_LEARNED) && !o.mlp) return fail(DM_E_MODEL, "DM_SCHED_LEARNED needs mlp parameters");
+  hipStream_t s = pick_stream(g, o.stream);
+  std::vector<uint64_t> tmp(T->ncls);
+  st = motif_run(g, k, o, s, nullptr, 1, tmp.data());
+  if (st == DM_OK) std::memcpy(out_counts, tmp.data(), sizeof(uint64_t) * T->ncls);
+  return st;
+}
+
+// ====================================================================== batching
+
+namespace {
+
+// A batch is the disjoint union of its graphs: vertex ids of graph i are
+// shifted by the vertex count of graphs 0..i-1, so no traversal crosses
+// graphs and per-graph counters can be kept by mapping each root to its graph.
+struct BatchCache {
+  dm_graph* uni = nullptr;
+  Buf gov;  // graph index of every union vertex
+  Buf gor;  // graph index of every union vertex in rank order
+  bool gor_ready = false;
+  ~BatchCache() { dm_free(uni); }
+};
+
+std::mutex g_batch_lock;
+std::map<std::vector<uint64_t>, BatchCache*> g_batches;
+
+dm_status build_union(dm_graph* const* gs, int32_t num, hipStream_t s, BatchCache* B) {
+  int64_t ntot = 0, etot = 0;
+  int dmax = 0;
+  for (int32_t i = 0; i < num; ++i) {
+    ntot += gs[i]->n;
+    etot += gs[i]->nnz;
+    dmax = std::max(dmax, gs[i]->dmax);
+  }
+  if (ntot > 2000000000LL) return fail(DM_E_ARG, "batch has more than 2e9 vertices");
+  dm_graph* u = new dm_graph();
+  u->device = gs[0]->device;
+  u->n = static_cast<int32_t>(ntot);
+  u->nnz = etot;
+  u->dmax = dmax;
+  B->uni = u;
+  HIP_OR_RETURN(u->rp.ensure(sizeof(int64_t) * (ntot + 1)), "batch: allocate");
+  HIP_OR_RETURN(u->col.ensure(sizeof(int32_t) * (etot > 0 ? etot : 1)), "batch: allocate");
+  HIP_OR_RETURN(B->gov.ensure(sizeof(int32_t) * (ntot > 0 ? ntot : 1)), "batch: allocate");
+  int64_t voff = 0, eoff = 0;
+  for (int32_t i = 0; i < num; ++i) {
+    const dm_graph* g = gs[i];
+    HIP_OR_RETURN(launch_offset_i64(g->rp.as<int64_t>(), u->rp.as<int64_t>() + voff, g->n, eoff, s), "batch: rows");
+    HIP_OR_RETURN(launch_offset_i32(g->col.as<int32_t>(), u->col.as<int32_t>() + eoff, g->nnz, static_cast<int32_t>(voff), s),
+                  "batch: cols");
+    HIP_OR_RETURN(launch_fill_i32(B->gov.as<int32_t>() + voff, g->n, i, s), "batch: graph map");
+    voff += g->n;
+    eoff += g->nnz;
+  }
+  HIP_OR_RETURN(launch_fill_u64(reinterpret_cast<unsigned long long*>(u->rp.as<int64_t>() + ntot), 1,
+                                static_cast<unsigned long long>(etot), s),
+                "batch: rows");
+  HIP_OR_RETURN(hipStreamSynchronize(s), "batch: build");
+  return DM_OK;
+}
+
+dm_status batch_run(dm_graph* const* gs, int32_t num, int op, int k, int width, const Opt& o, uint64_t* out) {
+  std::vector<uint64_t> key(static_cast<size_t>(num));
+  for (int32_t i = 0; i < num; ++i) key[i] = gs[i]->uid;
+  std::lock_guard<std::mutex> lk(g_batch_lock);
+  BatchCache*& B = g_batches[key];
+  hipStream_t s = o.stream ? o.stream : pick_stream(gs[0], nullptr);
+  if (!B) {
+    B = new BatchCache();
+    dm_status st = build_union(gs, num, s, B);
+    if (st != DM_OK) {
+      delete B;
+      B = nullptr;
+      g_batches.erase(key);
+      return st;
+    }
+  }
+  std::vector<uint64_t> tmp(static_cast<size_t>(num) * width);
+  dm_status st;
+  if (op == DM_OP_CLIQUE) {
+    st = ensure_dag(B->uni, s);
+    if (st != DM_OK) return st;
+    if (!B->gor_ready) {
+      HIP_OR_RETURN(B->gor.ensure(sizeof(int32_t) * (B->uni->n > 0 ? B->uni->n : 1)), "batch: allocate");
+      HIP_OR_RETURN(launch_gather_i32(B->gov.as<int32_t>(), B->uni->order.as<int32_t>(), B->gor.as<int32_t>(),
+                                      B->uni->n, s),
+                    "batch: rank map");
+      B->gor_ready = true;
+    }
+    st = clique_run(B->uni, k, o, s, B->gor.as<int32_t>(), num, tmp.data());
+  } else {
+    st = motif_run(B->uni, k, o, s, B->gov.as<int32_t>(), num, tmp.data());
+  }
+  if (st == DM_OK) std::memcpy(out, tmp.data(), sizeof(uint64_t) * tmp.size());
+  return st;
+}
+
+}  // namespace
+
+extern "C" dm_status dm_batch(dm_graph* const* gs, int32_t num_graphs, int op, int k, uint64_t* out_counts,
+                              size_t out_len, const dm_options* opt) {
+  if (!gs || num_graphs <= 0 || !out_counts) return fail(DM_E_ARG, "null graphs / output or num_graphs <= 0");
+  if (op != DM_OP_CLIQUE && op != DM_OP_MOTIF) return fail(DM_E_ARG, "unknown op");
+  int width = 1;
+  if (op == DM_OP_CLIQUE) {
+    if (k < 1 || k > kMaxK) return fail(DM_E_K, "clique k must be in 1..32");
+  } else {
+    const ClassTables* T = tables(k);
+    if (!T) return fail(DM_E_K, "motif k must be in 3..6");
+    width = T->ncls;
+  }
+  if (out_len < static_cast<size_t>(num_graphs) * width) return fail(DM_E_BUFSZ, "out_len < num_graphs * width");
+  for (int32_t i = 0; i < num_graphs; ++i)
+    if (!gs[i]) return fail(DM_E_ARG, "null graph in batch");
+  Opt o;
+  dm_status st = read_opt(opt, &o);
+  if (st != DM_OK) return st;
+  if (o.roots) return fail(DM_E_ARG, "root lists are not supported in batches");
+  if ((o.sched & DM_SCHED_LEARNED) && !o.mlp) return fail(DM_E_MODEL, "DM_SCHED_LEARNED needs mlp parameters");
+  return batch_run(gs, num_graphs, op, k, width, o, out_counts);
+}

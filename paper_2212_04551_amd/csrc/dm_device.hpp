@@ -1,0 +1,278 @@
+// Device-side building blocks shared by the enumeration kernels: wave64
+// primitives and the persistent-wave work scheduler (root queue + donation
+// pool + termination detection).
+//
+// Every enumeration kernel runs one 64-lane wavefront per workgroup; a wave
+// owns one traversal stack (the TE structure of DuMato, Section IV-B) and all
+// its lanes work on that stack together (Section IV-A, warp-centric task
+// allocation), so LDS written by one lane and read by another only needs a
+// workgroup barrier, which for a one-wave workgroup is cheap.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dm {
+
+constexpr int kWave = 64;
+constexpr int kMaxK = 32;          // largest clique size
+constexpr int kTaskInts = 40;      // payload of a donated task
+constexpr int kMaxTaskPrefix = kTaskInts - 5;
+
+// ------------------------------------------------------------------ wave64 primitives
+
+__device__ __forceinline__ int lane_id() {
+  return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+
+// number of set bits of m strictly below the calling lane
+__device__ __forceinline__ int mbcnt(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(m >> 32),
+                                   __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), 0u));
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+__device__ __forceinline__ int64_t uni64(int64_t x) {
+  uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(x));
+  uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(static_cast<uint64_t>(x) >> 32));
+  return static_cast<int64_t>((static_cast<uint64_t>(hi) << 32) | lo);
+}
+
+__device__ __forceinline__ uint64_t uniu64(uint64_t x) { return static_cast<uint64_t>(uni64(static_cast<int64_t>(x))); }
+
+// value of lane `src` (wave-uniform src)
+__device__ __forceinline__ int read_lane(int x, int src) { return __shfl(x, src, kWave); }
+
+// wave-wide uint64 sum with carry detection (sets *ovf on a wrap)
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t x, int* ovf) {
+  int o = 0;
+#pragma unroll
+  for (int sh = 32; sh >= 1; sh >>= 1) {
+    uint64_t y = __shfl_xor(x, sh, kWave);
+    uint64_t s = x + y;
+    o |= (s < x);
+    x = s;
+  }
+  if (ballot(o != 0)) *ovf = 1;
+  return x;
+}
+
+__device__ __forceinline__ int wave_sum_i32(int x) {
+#pragma unroll
+  for (int sh = 32; sh >= 1; sh >>= 1) x += __shfl_xor(x, sh, kWave);
+  return x;
+}
+
+// make LDS / global writes of this wave visible to all its lanes
+__device__ __forceinline__ void wave_sync() { __syncthreads(); }
+
+// ------------------------------------------------------------------ device-scope atomics
+
+__device__ __forceinline__ int ld_acquire(int* p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int ld_relaxed(const int* p) {
+  return __hip_atomic_load(const_cast<int*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long ld_relaxed_u64(unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_relaxed(int* p, int v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_release(int* p, int v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ bool cas_acq_rel(int* p, int expected, int desired) {
+  return __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_ACQ_REL, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long add_u64(unsigned long long* p, unsigned long long v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int add_i32(int* p, int v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// add v to a global uint64 counter; a wrap sets *flag
+__device__ __forceinline__ void add_counter(unsigned long long* p, unsigned long long v, int* flag) {
+  if (v == 0) return;
+  unsigned long long old = add_u64(p, v);
+  if (old + v < old) atomicOr(flag, 1);
+}
+
+// ------------------------------------------------------------------ scheduler
+
+// Termination word: (active waves << 32) | pending donated tasks.
+constexpr unsigned long long kActiveOne = 1ull << 32;
+
+struct Sched {
+  unsigned long long* qhead;  // next queue entry (or chunk index when qbounds != null)
+  unsigned long long* state;  // (active << 32) | pending
+  int* idle;                  // waves waiting for a donated task
+  int* slot_state;            // per slot: 0 empty, 1 being written, 2 full, 3 being read
+  int* slot_data;             // nslots * kTaskInts
+  const int32_t* qroot;       // queue entry -> root vertex (kernel id space); null = identity
+  const int32_t* qlo;         // queue entry -> first-level range start; null = 0
+  const int32_t* qhi;         // queue entry -> first-level range end; null = whole list
+  const int32_t* qstat;       // queue entry -> root_stats row; null = the entry index
+  const int64_t* qbounds;     // variable chunks: entries [qbounds[c], qbounds[c+1]); null = fixed
+  int64_t nq;                 // queue entries
+  int64_t nchunks;            // number of variable chunks
+  int chunk;                  // fixed chunk size
+  int nslots;
+  int donate;                 // donation enabled
+  int idle_trigger;           // donate only when at least this many waves are idle
+  int period;                 // DFS steps between donation checks
+};
+
+// A unit of work: root vertex, its stats row, the traversal depth the task
+// starts at, the iteration range at that depth, and the prefix choices.
+struct Task {
+  int root;
+  int64_t stat;
+  int depth;  // traversal size at which iteration happens (1 = root level)
+  int lo, hi;
+  int full_root;  // the task starts the root (counts the root node itself)
+};
+
+// Grab the next range of queue entries; returns false when the queue is drained.
+// All lanes get the same result.
+__device__ __forceinline__ bool sched_grab(const Sched& S, int64_t* b, int64_t* e) {
+  long long base = 0;
+  if (lane_id() == 0) base = static_cast<long long>(add_u64(S.qhead, 1ull * (S.qbounds ? 1 : S.chunk)));
+  base = uni64(base);
+  if (S.qbounds) {
+    if (base >= S.nchunks) return false;
+    *b = S.qbounds[base];
+    *e = S.qbounds[base + 1];
+  } else {
+    if (base >= S.nq) return false;
+    *b = base;
+    *e = base + S.chunk < S.nq ? base + S.chunk : S.nq;
+  }
+  return true;
+}
+
+__device__ __forceinline__ Task sched_entry(const Sched& S, int64_t e, int hi_default) {
+  Task t;
+  t.root = S.qroot ? S.qroot[e] : static_cast<int>(e);
+  t.stat = S.qstat ? static_cast<int64_t>(S.qstat[e]) : e;
+  t.depth = 1;
+  t.lo = S.qlo ? S.qlo[e] : 0;
+  t.hi = S.qhi ? S.qhi[e] : hi_default;
+  t.full_root = (t.lo == 0);
+  return t;
+}
+
+// Should a busy wave donate now?  Cheap: two relaxed loads by lane 0.
+__device__ __forceinline__ bool sched_want_donation(const Sched& S) {
+  int want = 0;
+  if (lane_id() == 0) {
+    int idle = ld_relaxed(S.idle);
+    unsigned long long st = ld_relaxed_u64(S.state);
+    int pending = static_cast<int>(st & 0xffffffffu);
+    want = (idle >= S.idle_trigger && idle > pending && pending < S.nslots) ? 1 : 0;
+  }
+  return uni(want) != 0;
+}
+
+// Publish a task (payload in `data`, lane i holds int i).  Returns true when
+// published.  The caller must be active while publishing.
+__device__ __forceinline__ bool sched_publish(const Sched& S, int data_lane, int wave_gid) {
+  const int lane = lane_id();
+  int got = -1;
+  // lanes look at disjoint slots starting at a wave-dependent offset
+  for (int base = 0; base < S.nslots && got < 0; base += kWave) {
+    int slot = (wave_gid + base + lane) % S.nslots;
+    bool empty = (base + lane < S.nslots) && ld_relaxed(&S.slot_state[slot]) == 0;
+    uint64_t cand = ballot(empty);
+    while (cand && got < 0) {
+      int l = __ffsll(static_cast<long long>(cand)) - 1;
+      cand &= cand - 1;
+      int ok = 0;
+      if (lane == l) ok = cas_acq_rel(&S.slot_state[slot], 0, 1) ? 1 : 0;
+      ok = read_lane(ok, l);
+      if (ok) got = read_lane(slot, l);
+    }
+  }
+  got = uni(got);
+  if (got < 0) return false;
+  if (lane < kTaskInts) st_relaxed(&S.slot_data[static_cast<int64_t>(got) * kTaskInts + lane], data_lane);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  wave_sync();
+  if (lane == 0) {
+    add_u64(S.state, 1ull);  // pending++ before the slot becomes visible
+    st_release(&S.slot_state[got], 2);
+  }
+  return true;
+}
+
+// Try to claim a published task; on success lane i holds payload int i and
+// the wave is counted active (pending handed over atomically).
+__device__ __forceinline__ bool sched_take(const Sched& S, int* data_lane, int wave_gid) {
+  const int lane = lane_id();
+  int got = -1;
+  for (int base = 0; base < S.nslots && got < 0; base += kWave) {
+    int slot = (wave_gid * 7 + base + lane) % S.nslots;
+    bool full = (base + lane < S.nslots) && ld_relaxed(&S.slot_state[slot]) == 2;
+    uint64_t cand = ballot(full);
+    while (cand && got < 0) {
+      int l = __ffsll(static_cast<long long>(cand)) - 1;
+      cand &= cand - 1;
+      int ok = 0;
+      if (lane == l) ok = cas_acq_rel(&S.slot_state[slot], 2, 3) ? 1 : 0;
+      ok = read_lane(ok, l);
+      if (ok) got = read_lane(slot, l);
+    }
+  }
+  got = uni(got);
+  if (got < 0) return false;
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  int v = 0;
+  if (lane < kTaskInts) v = ld_relaxed(&S.slot_data[static_cast<int64_t>(got) * kTaskInts + lane]);
+  *data_lane = v;
+  wave_sync();
+  if (lane == 0) {
+    st_release(&S.slot_state[got], 0);
+    add_u64(S.state, kActiveOne - 1ull);  // active++, pending-- in one step
+  }
+  return true;
+}
+
+// payload layout (one int per lane): [0] root, [1] stat low, [2] stat high,
+// [3] depth, [4] lo, [5] hi, [6 ..] prefix choices for depths 1 .. depth-1.
+__device__ __forceinline__ int task_payload(int root, int64_t stat, int depth, int lo, int hi,
+                                            const int* prefix_lds) {
+  const int lane = lane_id();
+  int v = 0;
+  if (lane == 0) v = root;
+  else if (lane == 1) v = static_cast<int>(static_cast<uint64_t>(stat) & 0xffffffffu);
+  else if (lane == 2) v = static_cast<int>(static_cast<uint64_t>(stat) >> 32);
+  else if (lane == 3) v = depth;
+  else if (lane == 4) v = lo;
+  else if (lane == 5) v = hi;
+  else if (lane >= 6 && lane < 6 + depth - 1 && lane < kTaskInts) v = prefix_lds[lane - 6 + 1];
+  return v;
+}
+
+__device__ __forceinline__ Task task_unpack(int data_lane, int* prefix_lds) {
+  Task t;
+  t.root = uni(read_lane(data_lane, 0));
+  uint32_t slo = static_cast<uint32_t>(uni(read_lane(data_lane, 1)));
+  uint32_t shi = static_cast<uint32_t>(uni(read_lane(data_lane, 2)));
+  t.stat = static_cast<int64_t>((static_cast<uint64_t>(shi) << 32) | slo);
+  t.depth = uni(read_lane(data_lane, 3));
+  t.lo = uni(read_lane(data_lane, 4));
+  t.hi = uni(read_lane(data_lane, 5));
+  t.full_root = 0;
+  const int lane = lane_id();
+  if (lane >= 6 && lane < 6 + t.depth - 1) prefix_lds[lane - 6 + 1] = data_lane;
+  wave_sync();
+  return t;
+}
+
+}  // namespace dm

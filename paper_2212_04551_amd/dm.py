@@ -1,0 +1,261 @@
+"""Python binding of libdumato_mi (C ABI in include/dm.h).
+
+Argument marshalling only: every step of the counting path runs in the HIP
+library.  The raw entry points are exposed under their C names
+(``dm_load_csr``, ``dm_count_cliques``, ``dm_count_motifs``, ``dm_batch``, ...)
+and wrapped by small helpers that accept numpy arrays or torch tensors.  torch
+is used for device memory and streams only.
+
+If the shared library has not been built, importing the helpers raises
+``ImportError`` — there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libdumato_mi.so")
+
+DM_OK, DM_E_ARG, DM_E_CSR, DM_E_K, DM_E_OVERFLOW, DM_E_NOMEM, DM_E_HIP, DM_E_BUFSZ, DM_E_MODEL = range(9)
+DM_CSR_HOST, DM_CSR_DEVICE, DM_CSR_TRUSTED = 0, 1, 2
+DM_SCHED_PLAIN, DM_SCHED_LEARNED, DM_SCHED_AUTOTUNE, DM_RECORD_ROOTS, DM_NO_DONATION = 0, 1, 2, 4, 8
+DM_OP_CLIQUE, DM_OP_MOTIF = 0, 1
+DM_MLP_NPARAMS = 4 * 64 + 64 + 64 * 64 + 64 + 64 + 1  # 4 -> 64 -> 64 -> 1
+
+EXPORTS = [
+    "dm_load_csr", "dm_free", "dm_graph_info", "dm_count_cliques", "dm_motif_num_classes",
+    "dm_motif_class_mask", "dm_motif_class_table", "dm_count_motifs", "dm_batch", "dm_strerror",
+    "dm_last_error",
+]
+
+
+class dm_options(ctypes.Structure):
+    _fields_ = [
+        ("size", ctypes.c_uint32),
+        ("sched", ctypes.c_uint32),
+        ("stream", ctypes.c_void_p),
+        ("chunk", ctypes.c_uint32),
+        ("rebalance", ctypes.c_float),
+        ("waves_per_cu", ctypes.c_uint32),
+        ("mlp", ctypes.c_void_p),
+        ("roots", ctypes.c_void_p),
+        ("num_roots", ctypes.c_int64),
+        ("root_stats", ctypes.c_void_p),
+        ("wave_stats", ctypes.c_void_p),
+        ("wave_stats_len", ctypes.c_uint32),
+        ("counter_bias", ctypes.c_uint64),
+    ]
+
+
+class DMError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{message} (status {status})")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load the shared library (raises ImportError when it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2212_04551_amd.build.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+    L.dm_load_csr.restype = ctypes.c_int
+    L.dm_load_csr.argtypes = [i32, vp, vp, u32, vp, ctypes.POINTER(vp)]
+    L.dm_free.restype = None
+    L.dm_free.argtypes = [vp]
+    L.dm_graph_info.restype = ctypes.c_int
+    L.dm_graph_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i64)]
+    L.dm_count_cliques.restype = ctypes.c_int
+    L.dm_count_cliques.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(dm_options)]
+    L.dm_motif_num_classes.restype = ctypes.c_int
+    L.dm_motif_num_classes.argtypes = [ctypes.c_int]
+    L.dm_motif_class_mask.restype = ctypes.c_int
+    L.dm_motif_class_mask.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(u32)]
+    L.dm_motif_class_table.restype = ctypes.c_int
+    L.dm_motif_class_table.argtypes = [ctypes.c_int, vp, ctypes.c_size_t]
+    L.dm_count_motifs.restype = ctypes.c_int
+    L.dm_count_motifs.argtypes = [vp, ctypes.c_int, vp, ctypes.c_size_t, ctypes.POINTER(dm_options)]
+    L.dm_batch.restype = ctypes.c_int
+    L.dm_batch.argtypes = [ctypes.POINTER(vp), i32, ctypes.c_int, ctypes.c_int, vp, ctypes.c_size_t,
+                           ctypes.POINTER(dm_options)]
+    L.dm_strerror.restype = ctypes.c_char_p
+    L.dm_strerror.argtypes = [ctypes.c_int]
+    L.dm_last_error.restype = ctypes.c_char_p
+    L.dm_last_error.argtypes = []
+    _lib = L
+    return L
+
+
+def _check(status: int):
+    if status != DM_OK:
+        L = lib()
+        msg = L.dm_strerror(status).decode()
+        detail = L.dm_last_error().decode()
+        raise DMError(status, f"{msg}: {detail}" if detail else msg)
+
+
+def _ptr(x) -> Optional[int]:
+    """Address of a numpy array or torch tensor (None passes through)."""
+    if x is None:
+        return None
+    if isinstance(x, np.ndarray):
+        return x.ctypes.data
+    if hasattr(x, "data_ptr"):
+        return x.data_ptr()
+    if isinstance(x, int):
+        return x
+    raise TypeError(f"cannot take the address of {type(x)}")
+
+
+def _stream(s) -> Optional[int]:
+    if s is None:
+        return None
+    if hasattr(s, "cuda_stream"):
+        return s.cuda_stream
+    return int(s)
+
+
+def make_options(sched: int = 0, stream=None, chunk: int = 0, rebalance: float = 0.0, waves_per_cu: int = 0,
+                 mlp=None, roots=None, root_stats=None, wave_stats=None, counter_bias: int = 0):
+    """Build a dm_options struct; returns (struct, keep-alive list)."""
+    keep = []
+    o = dm_options()
+    o.size = ctypes.sizeof(dm_options)
+    o.sched = sched
+    o.stream = _stream(stream)
+    o.chunk = chunk
+    o.rebalance = rebalance
+    o.waves_per_cu = waves_per_cu
+    o.mlp = _ptr(mlp)
+    if roots is not None:
+        r = np.ascontiguousarray(roots, dtype=np.int32)
+        keep.append(r)
+        o.roots = r.ctypes.data
+        o.num_roots = r.size
+    if root_stats is not None:
+        o.root_stats = _ptr(root_stats)
+        o.sched |= DM_RECORD_ROOTS
+    if wave_stats is not None:
+        o.wave_stats = _ptr(wave_stats)
+        o.wave_stats_len = int(wave_stats.numel() // 4) if hasattr(wave_stats, "numel") else int(wave_stats.size // 4)
+    o.counter_bias = counter_bias
+    keep.append(mlp)
+    return o, keep
+
+
+class DMGraph:
+    """A graph loaded into the library (owns the dm_graph handle)."""
+
+    def __init__(self, handle: int):
+        self.handle = ctypes.c_void_p(handle)
+        n = ctypes.c_int32(0)
+        nnz = ctypes.c_int64(0)
+        _check(lib().dm_graph_info(self.handle, ctypes.byref(n), ctypes.byref(nnz)))
+        self.n, self.nnz = n.value, nnz.value
+
+    def close(self):
+        if self.handle:
+            lib().dm_free(self.handle)
+            self.handle = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def load_csr(n: int, row_ptr, col, device: bool = False, trusted: bool = False, stream=None) -> DMGraph:
+    """dm_load_csr on numpy arrays (host) or torch CUDA tensors (device=True)."""
+    if not device:
+        row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        col = np.ascontiguousarray(col, dtype=np.int32)
+        if col.size == 0:
+            col = np.zeros(1, dtype=np.int32)
+    flags = (DM_CSR_DEVICE if device else DM_CSR_HOST) | (DM_CSR_TRUSTED if trusted else 0)
+    h = ctypes.c_void_p(None)
+    _check(lib().dm_load_csr(n, _ptr(row_ptr), _ptr(col), flags, _stream(stream), ctypes.byref(h)))
+    return DMGraph(h.value)
+
+
+def load_graph(g, **kw) -> DMGraph:
+    """Load a graphgen.Graph (host arrays)."""
+    return load_csr(g.n, g.row_ptr, g.col, **kw)
+
+
+def _check_stats(g: DMGraph, opt: dict):
+    st = opt.get("root_stats")
+    if st is None:
+        return
+    rows = len(opt["roots"]) if opt.get("roots") is not None else g.n
+    size = st.numel() if hasattr(st, "numel") else st.size
+    if size < 3 * rows:
+        raise ValueError(f"root_stats needs {3 * rows} uint64 entries, got {size}")
+
+
+def count_cliques(g: DMGraph, k: int, **opt) -> int:
+    _check_stats(g, opt)
+    o, keep = make_options(**opt)
+    out = ctypes.c_uint64(0)
+    _check(lib().dm_count_cliques(g.handle, k, ctypes.byref(out), ctypes.byref(o)))
+    del keep
+    return int(out.value)
+
+
+def motif_num_classes(k: int) -> int:
+    return int(lib().dm_motif_num_classes(k))
+
+
+def motif_class_mask(k: int, cls: int) -> int:
+    m = ctypes.c_uint32(0)
+    _check(lib().dm_motif_class_mask(k, cls, ctypes.byref(m)))
+    return int(m.value)
+
+
+def motif_class_table(k: int) -> np.ndarray:
+    n = 1 << (k * (k - 1) // 2 - 1)
+    out = np.zeros(n, dtype=np.uint8)
+    _check(lib().dm_motif_class_table(k, out.ctypes.data, n))
+    return out
+
+
+def count_motifs(g: DMGraph, k: int, **opt) -> np.ndarray:
+    ncls = motif_num_classes(k)
+    if ncls < 0:
+        _check(DM_E_K)
+    out = np.zeros(ncls, dtype=np.uint64)
+    _check_stats(g, opt)
+    o, keep = make_options(**opt)
+    _check(lib().dm_count_motifs(g.handle, k, out.ctypes.data, ncls, ctypes.byref(o)))
+    del keep
+    return out
+
+
+def batch(graphs: Sequence[DMGraph], op: int, k: int, **opt) -> np.ndarray:
+    """dm_batch: returns [num_graphs, width] uint64."""
+    width = 1 if op == DM_OP_CLIQUE else motif_num_classes(k)
+    if width < 0:
+        _check(DM_E_K)
+    arr = (ctypes.c_void_p * len(graphs))(*[g.handle.value for g in graphs])
+    out = np.zeros((len(graphs), width), dtype=np.uint64)
+    o, keep = make_options(**opt)
+    _check(lib().dm_batch(arr, len(graphs), op, k, out.ctypes.data, out.size, ctypes.byref(o)))
+    del keep
+    return out
+
+
+# C names re-exported for callers that want the raw ABI
+def __getattr__(name):
+    if name in EXPORTS:
+        return getattr(lib(), name)
+    raise AttributeError(name)

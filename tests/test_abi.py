@@ -1,0 +1,107 @@
+"""C-ABI library: loads, exports every declared symbol, host-only entry points
+agree with the oracle, and argument / CSR errors are reported before any GPU
+work (so these run without a GPU)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2212_04551_amd import dm
+from paper_2212_04551_amd import graphgen as gg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    src = open(os.path.join(ROOT, "include", "dm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(dm_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = dm.lib()
+    names = _declared_symbols()
+    assert "dm_load_csr" in names and "dm_batch" in names
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(dm.EXPORTS)
+
+
+def test_options_struct_layout():
+    # matches the C layout: 13 fields, pointer-aligned, 88 bytes on LP64
+    assert ctypes.sizeof(dm.dm_options) == 88
+    assert dm.dm_options.counter_bias.offset == 80
+    assert dm.dm_options.mlp.offset == 32
+
+
+@pytest.mark.parametrize("k", [3, 4, 5, 6])
+def test_class_ids_and_masks_match_oracle(k):
+    assert dm.motif_num_classes(k) == O.num_classes(k)
+    canon = O.class_canon(k)
+    for c in range(len(canon)):
+        assert dm.motif_class_mask(k, c) == int(canon[c])
+
+
+@pytest.mark.parametrize("k,reachable", [(3, 3), (4, 21), (5, 315), (6, 9765)])
+def test_dictionary_matches_oracle_on_every_code(k, reachable):
+    """Section IV-C dictionary: traversal code t is the full bitmap (t<<1)|1."""
+    T = dm.motif_class_table(k)
+    assert T.size == 1 << (k * (k - 1) // 2 - 1)
+    hit = 0
+    for t in range(T.size):
+        fields_ok = all((t >> (i * (i - 1) // 2 - 1)) & ((1 << i) - 1) for i in range(2, k))
+        if fields_ok:
+            hit += 1
+            assert T[t] == O.class_of_code(k, (t << 1) | 1), t
+        else:
+            assert T[t] == 0xFF
+    assert hit == reachable
+
+
+def test_unsupported_k():
+    assert dm.motif_num_classes(2) == -1 and dm.motif_num_classes(7) == -1
+    with pytest.raises(dm.DMError) as e:
+        dm.motif_class_table(7)
+    assert e.value.status == dm.DM_E_K
+    with pytest.raises(dm.DMError) as e:
+        dm.motif_class_mask(4, 6)
+    assert e.value.status == dm.DM_E_ARG
+
+
+def _bad_csrs():
+    ok = gg.cycle(5)
+    yield "self-loop", ok.n, ok.row_ptr, np.array([0, 1, 4, 0, 2, 1, 3, 2, 4, 0, 3], np.int32)[: ok.nnz]
+    rp = ok.row_ptr.copy()
+    col = ok.col.copy()
+    col[0], col[1] = col[1], col[0]
+    yield "unsorted", ok.n, rp, col
+    col = ok.col.copy()
+    col[0] = 9
+    yield "out of range", ok.n, rp, col
+    g = gg.from_edges(3, [(0, 1)])
+    yield "asymmetric", 3, np.array([0, 1, 1, 1], np.int64), np.array([1], np.int32)
+    yield "repeat", 2, np.array([0, 2, 4], np.int64), np.array([1, 1, 0, 0], np.int32)
+    yield "bad offsets", 2, np.array([1, 1, 2], np.int64), np.array([1, 0], np.int32)
+
+
+@pytest.mark.parametrize("case", list(_bad_csrs()), ids=lambda c: c[0])
+def test_host_csr_validation_rejects(case):
+    _, n, rp, col = case
+    with pytest.raises(dm.DMError) as e:
+        dm.load_csr(n, rp, col)
+    assert e.value.status == dm.DM_E_CSR
+
+
+def test_argument_errors_without_gpu():
+    L = dm.lib()
+    out = ctypes.c_uint64(0)
+    assert L.dm_count_cliques(None, 3, ctypes.byref(out), None) == dm.DM_E_ARG
+    assert L.dm_count_motifs(None, 4, None, 0, None) == dm.DM_E_ARG
+    assert L.dm_batch(None, 0, 0, 3, None, 0, None) == dm.DM_E_ARG
+    h = ctypes.c_void_p(None)
+    assert L.dm_load_csr(-1, None, None, 0, None, ctypes.byref(h)) == dm.DM_E_ARG
+    assert L.dm_load_csr(3, None, None, 0, None, None) == dm.DM_E_ARG
+    assert L.dm_strerror(dm.DM_E_OVERFLOW) == b"uint64 count overflow"

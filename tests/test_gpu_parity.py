@@ -1,0 +1,310 @@
+"""GPU parity: every count from the HIP library equals the CPU oracle exactly
+(uint64), on closed-form families, exhaustive tiny graphs, seeded random
+graphs with ragged sizes (several 64-bit tiles plus a tail), per-root records,
+and under every scheduling knob.  All calls go through the C ABI."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2212_04551_amd import dm
+from paper_2212_04551_amd import graphgen as gg
+
+pytestmark = pytest.mark.gpu
+
+
+def _esym(parts, k):
+    poly = np.array([1], dtype=object)
+    for a in parts:
+        poly = np.convolve(poly, np.array([1, a], dtype=object))
+    return int(poly[k]) if k < len(poly) else 0
+
+
+def cliques(g, k, **kw):
+    h = dm.load_graph(g)
+    return dm.count_cliques(h, k, **kw)
+
+
+def motifs(g, k, **kw):
+    h = dm.load_graph(g)
+    return dm.count_motifs(h, k, **kw)
+
+
+def test_native_library_is_loaded():
+    dm.lib()
+    maps = open("/proc/self/maps").read()
+    assert "libdumato_mi.so" in maps
+
+
+# ------------------------------------------------------------------ closed forms
+
+@pytest.mark.parametrize("n", [1, 2, 5, 30, 65, 130])
+def test_clique_complete(n):
+    """K_n: C(n, k); k is kept where the (k-2)-clique level stays below ~1e7 nodes."""
+    h = dm.load_graph(gg.complete(n))
+    for k in range(1, n + 2):
+        if k > 2 and math.comb(n, k - 2) > 10_000_000:
+            break
+        assert dm.count_cliques(h, k) == math.comb(n, k), (n, k)
+
+
+@pytest.mark.parametrize("parts", [[3] * 12, [1, 2, 3, 4, 5, 6, 7], [2] * 9, [40, 1, 1, 25]])
+def test_clique_multipartite(parts):
+    h = dm.load_graph(gg.complete_multipartite(parts))
+    for k in range(1, len(parts) + 2):
+        assert dm.count_cliques(h, k) == _esym(parts, k), (parts, k)
+
+
+def test_clique_global_rows_path():
+    """Out-degrees up to 897: bitmap rows exceed LDS and live in global scratch."""
+    parts = [3] * 300
+    h = dm.load_graph(gg.complete_multipartite(parts))
+    for k in (3, 4):
+        assert dm.count_cliques(h, k) == _esym(parts, k), k
+
+
+@pytest.mark.parametrize("g", [gg.complete_bipartite(70, 90), gg.hypercube(7), gg.cycle(200), gg.star(300),
+                               gg.empty(50), gg.path(129)], ids=["K70,90", "Q7", "C200", "S300", "E50", "P129"])
+def test_clique_bipartite_zero(g):
+    h = dm.load_graph(g)
+    assert dm.count_cliques(h, 1) == g.n
+    assert dm.count_cliques(h, 2) == g.m
+    for k in range(3, 7):
+        assert dm.count_cliques(h, k) == 0
+
+
+@pytest.mark.parametrize("k", [3, 4, 5, 6])
+def test_motif_closed_forms(k):
+    ncls = dm.motif_num_classes(k)
+    for G, n_expected_class_pattern, count in [
+        (gg.path(150), gg.path(k), 150 - k + 1),
+        (gg.cycle(131), gg.path(k), 131),
+        (gg.star(200), gg.star(k - 1), math.comb(200, k - 1)),
+        (gg.complete(20), gg.complete(k), math.comb(20, k)),
+    ]:
+        cls = int(np.nonzero(O.motif_brute(n_expected_class_pattern, k))[0][0])
+        exp = np.zeros(ncls, np.uint64)
+        exp[cls] = count
+        assert np.array_equal(motifs(G, k), exp), (k, G.n)
+    assert not motifs(gg.empty(40), k).any()
+
+
+def test_motif_complete_bipartite():
+    a, b = 70, 65
+    g = gg.complete_bipartite(a, b)
+    c4 = int(np.nonzero(O.motif_brute(gg.cycle(4), 4))[0][0])
+    s3 = int(np.nonzero(O.motif_brute(gg.star(3), 4))[0][0])
+    exp = np.zeros(6, np.uint64)
+    exp[c4] = math.comb(a, 2) * math.comb(b, 2)
+    exp[s3] = a * math.comb(b, 3) + b * math.comb(a, 3)
+    assert np.array_equal(motifs(g, 4), exp)
+
+
+# ------------------------------------------------------------------ exhaustive tiny graphs
+
+def _all_graphs(n):
+    pairs = [(i, j) for i in range(n) for j in range(i + 1, n)]
+    for mask in range(1 << len(pairs)):
+        yield gg.from_edges(n, [p for b, p in enumerate(pairs) if mask >> b & 1])
+
+
+def test_exhaustive_five_vertices_batched():
+    graphs = list(_all_graphs(5))
+    hs = [dm.load_graph(g) for g in graphs]
+    for k in (3, 4, 5):
+        got = dm.batch(hs, dm.DM_OP_MOTIF, k)
+        exp = np.stack([O.motif_brute(g, k) for g in graphs])
+        assert np.array_equal(got, exp), k
+        got = dm.batch(hs, dm.DM_OP_CLIQUE, k)[:, 0]
+        exp = np.array([O.clique_brute(g, k) for g in graphs], np.uint64)
+        assert np.array_equal(got, exp), k
+
+
+def test_exhaustive_six_vertices_sampled():
+    pairs = [(i, j) for i in range(6) for j in range(i + 1, 6)]
+    graphs = [gg.from_edges(6, [p for b, p in enumerate(pairs) if m >> b & 1]) for m in range(0, 1 << 15, 37)]
+    hs = [dm.load_graph(g) for g in graphs]
+    for k in (4, 5, 6):
+        got = dm.batch(hs, dm.DM_OP_MOTIF, k)
+        exp = np.stack([O.motif_brute(g, k) for g in graphs])
+        assert np.array_equal(got, exp), k
+
+
+# ------------------------------------------------------------------ seeded random graphs
+
+def test_er516_motifs_and_cliques():
+    g = gg.workload_graph("er516", 0)
+    h = dm.load_graph(g)
+    for k in (3, 4, 5, 6):
+        assert np.array_equal(dm.count_motifs(h, k), O.motif_count(g, k, threads=8)), k
+    for k in range(1, 9):
+        assert dm.count_cliques(h, k) == O.clique_count(g, k), k
+
+
+RANDOM = [
+    ("er", lambda s: gg.erdos_renyi(300, 9000, s)),       # dense: out-degrees span 2-3 tiles
+    ("er_sparse", lambda s: gg.erdos_renyi(2000, 6000, s)),
+    ("ba", lambda s: gg.barabasi_albert(1500, 5, s)),     # hubs: long neighbour scans
+    ("cl", lambda s: gg.chung_lu(3000, 12000, 2.2, 80.0, s)[0]),
+    ("sbm", lambda s: gg.sbm(12, 40, 0.5, 0.01, s)),
+]
+
+
+@pytest.mark.parametrize("name,make", RANDOM, ids=[r[0] for r in RANDOM])
+@pytest.mark.parametrize("seed", [1, 2])
+def test_random_graphs_cliques(name, make, seed):
+    g = make(seed)
+    h = dm.load_graph(g)
+    for k in range(3, 8):
+        assert dm.count_cliques(h, k) == O.clique_count(g, k, threads=8), (name, seed, k)
+
+
+@pytest.mark.parametrize("name,make", RANDOM, ids=[r[0] for r in RANDOM])
+@pytest.mark.parametrize("seed", [1])
+def test_random_graphs_motifs(name, make, seed):
+    g = make(seed)
+    h = dm.load_graph(g)
+    kmax = {"er": 4, "sbm": 5}.get(name, 5 if name in ("ba", "cl") else 6)
+    for k in range(3, kmax + 1):
+        assert np.array_equal(dm.count_motifs(h, k), O.motif_count(g, k, threads=8)), (name, seed, k)
+
+
+# ------------------------------------------------------------------ per-root records
+
+def test_clique_record_mode():
+    import torch
+    g = gg.chung_lu(2000, 12000, 2.2, 300.0, 5)[0]
+    h = dm.load_graph(g)
+    for k in (3, 4, 5):
+        stats = torch.zeros((g.n, 3), dtype=torch.int64, device="cuda")
+        tot = dm.count_cliques(h, k, root_stats=stats)
+        st = stats.cpu().numpy().astype(np.uint64)
+        t2, leaves, nodes, reads = O.clique_count(g, k, per_root=True, threads=8)
+        assert tot == t2
+        assert np.array_equal(st[:, 1], leaves)
+        assert np.array_equal(st[:, 0], nodes)
+        assert np.array_equal(st[:, 2], reads)
+
+
+def test_motif_record_mode_leaves_and_nodes():
+    import torch
+    g = gg.barabasi_albert(800, 3, 4)
+    h = dm.load_graph(g)
+    for k in (3, 4, 5):
+        stats = torch.zeros((g.n, 3), dtype=torch.int64, device="cuda")
+        c = dm.count_motifs(h, k, root_stats=stats)
+        st = stats.cpu().numpy().astype(np.uint64)
+        c2, leaves, nodes, _ = O.motif_count(g, k, per_root=True, threads=8)
+        assert np.array_equal(c, c2)
+        assert np.array_equal(st[:, 1], leaves)
+        assert np.array_equal(st[:, 0], nodes)
+
+
+# ------------------------------------------------------------------ schedule invariance
+
+SCHED = [
+    dict(),
+    dict(chunk=1),
+    dict(chunk=37),
+    dict(chunk=512),
+    dict(sched=dm.DM_NO_DONATION),
+    dict(waves_per_cu=1),
+    dict(waves_per_cu=2, chunk=3),
+    dict(rebalance=0.5),
+    dict(rebalance=0.01, chunk=2),
+]
+
+
+def test_schedule_invariance_cliques():
+    g = gg.chung_lu(20000, 200000, 2.1, 1500.0, 3)[0]
+    h = dm.load_graph(g)
+    for k in (4, 6):
+        ref = O.clique_count(g, k, threads=8)
+        for s in SCHED:
+            assert dm.count_cliques(h, k, **s) == ref, (k, s)
+        for _ in range(5):
+            assert dm.count_cliques(h, k) == ref
+
+
+def test_schedule_invariance_motifs():
+    for k, g in ((4, gg.chung_lu(5000, 20000, 2.2, 300.0, 9)[0]), (5, gg.chung_lu(2000, 6000, 2.2, 60.0, 9)[0])):
+        h = dm.load_graph(g)
+        ref = O.motif_count(g, k, threads=8)
+        for s in SCHED:
+            assert np.array_equal(dm.count_motifs(h, k, **s), ref), (k, s)
+
+
+def test_root_lists_partition_the_count():
+    g = gg.chung_lu(4000, 16000, 2.2, 80.0, 11)[0]
+    h = dm.load_graph(g)
+    rng = np.random.default_rng(0)
+    perm = rng.permutation(g.n).astype(np.int32)
+    a, b = perm[:1500], perm[1500:]
+    for k in (3, 5):
+        tot = dm.count_cliques(h, k)
+        ca, cb = dm.count_cliques(h, k, roots=a), dm.count_cliques(h, k, roots=b)
+        assert ca + cb == tot
+        assert ca == O.clique_count(g, k, roots=a, threads=8)
+        ma, mb = dm.count_motifs(h, k, roots=a), dm.count_motifs(h, k, roots=b)
+        assert np.array_equal(ma + mb, dm.count_motifs(h, k))
+        assert np.array_equal(mb, O.motif_count(g, k, roots=b, threads=8))
+        assert dm.count_cliques(h, k, roots=perm) == tot
+
+
+# ------------------------------------------------------------------ batching
+
+def test_batch_matches_single_calls():
+    graphs = [gg.batch_graph(i, nhi=300) for i in range(24)]
+    hs = [dm.load_graph(g) for g in graphs]
+    for k in (3, 4, 5):
+        got = dm.batch(hs, dm.DM_OP_MOTIF, k)
+        for i, g in enumerate(graphs):
+            assert np.array_equal(got[i], O.motif_count(g, k)), (k, i)
+    got = dm.batch(hs, dm.DM_OP_CLIQUE, 4)[:, 0]
+    assert list(got) == [O.clique_count(g, 4) for g in graphs]
+    # the cached union is reused on a second call
+    assert np.array_equal(dm.batch(hs, dm.DM_OP_MOTIF, 4), dm.batch(hs, dm.DM_OP_MOTIF, 4))
+
+
+# ------------------------------------------------------------------ errors
+
+def test_error_paths():
+    import torch
+    g = gg.erdos_renyi(100, 400, 1)
+    h = dm.load_graph(g)
+    for bad_k in (0, 33):
+        with pytest.raises(dm.DMError) as e:
+            dm.count_cliques(h, bad_k)
+        assert e.value.status == dm.DM_E_K
+    for bad_k in (2, 7):
+        with pytest.raises(dm.DMError) as e:
+            dm.count_motifs(h, bad_k)
+        assert e.value.status == dm.DM_E_K
+    with pytest.raises(dm.DMError) as e:
+        dm.count_cliques(h, 3, sched=dm.DM_SCHED_LEARNED)
+    assert e.value.status == dm.DM_E_MODEL
+    # device-side validation
+    rp = torch.tensor([0, 1, 1], dtype=torch.int64, device="cuda")
+    col = torch.tensor([1], dtype=torch.int32, device="cuda")
+    with pytest.raises(dm.DMError) as e:
+        dm.load_csr(2, rp, col, device=True)
+    assert e.value.status == dm.DM_E_CSR
+    rpd = torch.from_numpy(g.row_ptr).cuda()
+    cold = torch.from_numpy(g.col).cuda()
+    hd = dm.load_csr(g.n, rpd, cold, device=True)
+    assert dm.count_cliques(hd, 3) == O.clique_count(g, 3)
+
+
+def test_overflow_detected():
+    g = gg.complete(30)
+    h = dm.load_graph(g)
+    c = math.comb(30, 4)
+    assert dm.count_cliques(h, 4, counter_bias=2**64 - c - 1) == 2**64 - 1
+    with pytest.raises(dm.DMError) as e:
+        dm.count_cliques(h, 4, counter_bias=2**64 - c)
+    assert e.value.status == dm.DM_E_OVERFLOW
+    m = O.motif_count(g, 4).max()
+    with pytest.raises(dm.DMError) as e:
+        dm.count_motifs(h, 4, counter_bias=2**64 - int(m))
+    assert e.value.status == dm.DM_E_OVERFLOW
