@@ -41,6 +41,8 @@ struct CliqueLds {
   int* offs;        // [dmax+1] exclusive prefix of |N+(nbr[i])|
   int* cur;         // [kMaxK+2] chosen position per depth
   int* hiv;         // [kMaxK+2] iteration end per depth
+  uint64_t* lr;     // [64] rows of a candidate set of <= 64 members, in local ids
+  int* pos;         // [64] positions (in N+(root)) of those members
 };
 
 __device__ __forceinline__ size_t align16(size_t x) { return (x + 15) & ~static_cast<size_t>(15); }
@@ -66,7 +68,106 @@ __device__ CliqueLds carve(unsigned char* smem, int dmax, int W, int k, bool row
   L.cur = reinterpret_cast<int*>(smem + off);
   off += (kMaxK + 2) * 4;
   L.hiv = reinterpret_cast<int*>(smem + off);
+  off += (kMaxK + 2) * 4;
+  off = align16(off);
+  L.lr = reinterpret_cast<uint64_t*>(smem + off);
+  off += 64 * 8;
+  L.pos = reinterpret_cast<int*>(smem + off);
   return L;
+}
+
+// ---------------------------------------------------------------- small dense solver
+//
+// Once a candidate set has at most 64 members, the remaining q levels of the
+// enumeration tree are counted inside registers: members get local ids
+// 0..m-1 (rank order), row lr[i] holds the members adjacent to member i with
+// a larger id, and a q-clique count is a nested loop of AND + popcount.  The
+// wave walks the first member i; lane j takes the second member j in
+// C & lr[i] and counts the (q-2)-cliques of C & lr[i] & lr[j] on its own.
+
+constexpr int kSolverMaxQ = 8;
+
+template <int D>
+__device__ __forceinline__ uint64_t count_in(uint64_t C, const uint64_t* lr) {
+  if constexpr (D == 1) {
+    return static_cast<uint64_t>(__popcll(C));
+  } else {
+    uint64_t s = 0;
+    while (C) {
+      const int x = __builtin_ctzll(C);
+      C &= C - 1;
+      s += count_in<D - 1>(C & lr[x], lr);
+    }
+    return s;
+  }
+}
+
+__device__ __forceinline__ uint64_t count_in_depth(int D, uint64_t C, const uint64_t* lr) {
+  switch (D) {
+    case 1: return count_in<1>(C, lr);
+    case 2: return count_in<2>(C, lr);
+    case 3: return count_in<3>(C, lr);
+    case 4: return count_in<4>(C, lr);
+    case 5: return count_in<5>(C, lr);
+    case 6: return count_in<6>(C, lr);
+    default: return 0;
+  }
+}
+
+__device__ __forceinline__ uint64_t range_mask64(int lo, int hi) {
+  if (lo < 0) lo = 0;
+  if (hi > 64) hi = 64;
+  if (lo >= hi) return 0ull;
+  const uint64_t upper = hi == 64 ? ~0ull : ((1ull << hi) - 1);
+  return upper & (~0ull << lo);
+}
+
+// q-cliques (1 <= q <= kSolverMaxQ) inside C whose first member lies in
+// [lo, hi); returns this lane's share.
+__device__ __forceinline__ uint64_t small_solve(uint64_t C, int q, const uint64_t* lr, int lo, int hi) {
+  const int lane = lane_id();
+  C = uniu64(C);
+  uint64_t first = C & range_mask64(lo, hi);
+  uint64_t add = 0;
+  if (q == 1) {
+    if (lane == 0) add = static_cast<uint64_t>(__popcll(first));
+  } else if (q == 2) {
+    if ((first >> lane) & 1ull) add = static_cast<uint64_t>(__popcll(C & lr[lane]));
+  } else {
+    while (first) {
+      const int i = __builtin_ctzll(first);
+      first &= first - 1;
+      const uint64_t Ci = uniu64(C & lr[i]);
+      if ((Ci >> lane) & 1ull) add += count_in_depth(q - 2, Ci & lr[lane], lr);
+    }
+  }
+  return add;
+}
+
+// Local ids for the members of the multi-word set C: positions into L.pos,
+// rows into L.lr.  Returns the member count (<= 64 by the caller's check).
+__device__ __forceinline__ int reindex(const uint64_t* C, int Wd, const uint64_t* rows, int dmax, const CliqueLds& L) {
+  const int lane = lane_id();
+  int base = 0;
+  for (int w = 0; w < Wd; ++w) {
+    const bool bit = (C[w] >> lane) & 1ull;
+    const uint64_t b = ballot(bit);
+    if (bit && base + mbcnt(b) < 64) L.pos[base + mbcnt(b)] = w * 64 + lane;
+    base += __popcll(b);
+  }
+  const int m = uni(base < 64 ? base : 64);
+  wave_sync();
+  if (lane < m) {
+    const int pa = L.pos[lane];
+    uint64_t row = 0;
+    for (int b = lane + 1; b < m; ++b) {
+      const int pb = L.pos[b];
+      if ((rows[static_cast<size_t>(pb >> 6) * dmax + pa] >> (pb & 63)) & 1ull) row |= 1ull << b;
+    }
+    L.lr[lane] = row;
+  }
+  wave_sync();
+  return m;
 }
 
 // smallest set bit of C within [from, to), or -1 (wave-uniform)
@@ -211,6 +312,17 @@ __device__ void run_task(const CliqueArgs& A, const CliqueLds& L, uint64_t* rows
       for (int w = lane; w < Wd; w += kWave) L.stk[(s + 1) * W + w] = L.stk[s * W + w] & rows[static_cast<size_t>(w) * dmax + p];
       wave_sync();
     }
+    // one-word roots: their rows already are local rows
+    const bool solver = A.prune != 0;
+    if (solver && Wd == 1) {
+      if (lane < d) L.lr[lane] = rows[lane];
+      wave_sync();
+    }
+    auto add_acc = [&](uint64_t x) {
+      const uint64_t before = WA.acc;
+      WA.acc += x;
+      if (WA.acc < before) WA.ovf = 1;
+    };
 
     // leaf-parent step: traversal of size s = k-2 with candidate set C_s;
     // each lane takes extensions p (one per word) inside [lo, hi).
@@ -233,7 +345,9 @@ __device__ void run_task(const CliqueArgs& A, const CliqueLds& L, uint64_t* rows
     };
 
     const int s0 = t.depth;
-    if (s0 == k - 2) {
+    if (solver && Wd == 1 && k - s0 <= kSolverMaxQ) {
+      add_acc(small_solve(L.stk[s0 * W], k - s0, L.lr, t.lo, hi_t));
+    } else if (s0 == k - 2) {
       leaf_parent(s0, t.lo, hi_t);
     } else {
       int depth = s0;
@@ -260,8 +374,16 @@ __device__ void run_task(const CliqueArgs& A, const CliqueLds& L, uint64_t* rows
         }
         cnt = uni(wave_sum_i32(cnt));
         wave_sync();
-        if (!A.prune || cnt >= k - depth - 1) {
-          if (depth + 1 == k - 2) {
+        const int q = k - depth - 1;  // vertices still to add below the child
+        if (!A.prune || cnt >= q) {
+          if (solver && cnt <= 64 && q <= kSolverMaxQ) {
+            if (Wd == 1) {
+              add_acc(small_solve(L.stk[(depth + 1) * W], q, L.lr, 0, 64));
+            } else {
+              const int m = reindex(L.stk + (depth + 1) * W, Wd, rows, dmax, L);
+              add_acc(small_solve(m == 64 ? ~0ull : ((1ull << m) - 1), q, L.lr, 0, 64));
+            }
+          } else if (depth + 1 == k - 2) {
             leaf_parent(depth + 1, 0, d);
           } else {
             ++depth;
@@ -381,6 +503,7 @@ size_t clique_lds_bytes(int dmax, int W, int k, bool rows_in_lds) {
   off = a16(off) + static_cast<size_t>(dmax) * 4;
   off = a16(off) + static_cast<size_t>(dmax + 1) * 4;
   off = a16(off) + 2 * (kMaxK + 2) * 4;
+  off = a16(off) + 64 * 8 + 64 * 4;
   return a16(off);
 }
 
