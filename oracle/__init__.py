@@ -55,6 +55,10 @@ def _load():
     for f in (L.or_clique_roots, L.or_motif_roots):
         f.restype = ctypes.c_int
         f.argtypes = [i32, vp, vp, ctypes.c_int, vp, i64, ctypes.c_int, vp, vp, vp, vp]
+    for f in (L.or_clique_timed, L.or_motif_timed):
+        f.restype = ctypes.c_uint64
+        f.argtypes = [i32, vp, vp, ctypes.c_int, vp, i64, ctypes.c_int, ctypes.c_double,
+                      ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double)]
     L.or_twohop.restype = None
     L.or_twohop.argtypes = [i32, vp, vp, vp]
     L.or_triangles.restype = None
@@ -194,6 +198,31 @@ def motif_count(g, k: int, roots=None, threads: int = 1, per_root: bool = False)
     if per_root:
         return (out,) + tuple(a[:cnt] for a in arrs)
     return out
+
+
+# ------------------------------------------------------------------ time-bounded runs
+
+def _timed(fn, g, k, roots, threads, seconds):
+    rp, col = _csr(g)
+    r = np.ascontiguousarray(roots, dtype=np.int32)
+    started = ctypes.c_int64(0)
+    elapsed = ctypes.c_double(0.0)
+    found = fn(g.n, rp.ctypes.data, col.ctypes.data, k, r.ctypes.data, r.size, threads, seconds,
+               ctypes.byref(started), ctypes.byref(elapsed))
+    return int(found), int(started.value), float(elapsed.value)
+
+
+def clique_timed(g, k: int, roots, threads: int, seconds: float):
+    """k-cliques found from `roots` (in order) within `seconds` of wall-clock time.
+
+    Returns (subgraphs found, roots begun, seconds used); roots still running at
+    the deadline are abandoned after counting what they had found."""
+    return _timed(_load().or_clique_timed, g, k, roots, threads, seconds)
+
+
+def motif_timed(g, k: int, roots, threads: int, seconds: float):
+    """Connected induced k-sets found from `roots` within `seconds` (see clique_timed)."""
+    return _timed(_load().or_motif_timed, g, k, roots, threads, seconds)
 
 
 # ------------------------------------------------------------------ features

@@ -37,11 +37,13 @@
  *   reads(r)  = sum over those traversals of the degree (out-degree in rank
  *               order for cliques) of the vertex added last.
  */
+#define _POSIX_C_SOURCE 200809L
 #include <pthread.h>
 #include <stdatomic.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <time.h>
 
 #define OR_MAXK 8          /* motif classification up to k = 8 (table 2^27 for k=8 not built) */
 #define OR_MAX_MOTIF_K 6   /* class tables are built for k <= 6 */
@@ -310,6 +312,10 @@ typedef struct {
     const int64_t* outdeg;   /* neighbours of higher rank */
     /* motif */
     const class_info* ci;
+    /* optional wall-clock deadline (CLOCK_MONOTONIC seconds; 0 = none) */
+    double deadline;
+    atomic_int expired;
+    atomic_llong started;
     /* reduction */
     pthread_mutex_t lock;
     uint64_t total;
@@ -321,6 +327,20 @@ static void add_u64(uint64_t* acc, uint64_t x, int* ovf) {
     if (__builtin_add_overflow(*acc, x, acc)) *ovf = 1;
 }
 
+static double now_s(void) {
+    struct timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
+}
+
+/* true once the job's deadline has passed (checked every 4096 calls per thread) */
+static int past_deadline(job_t* J, unsigned* tick) {
+    if (J->deadline <= 0.0) return 0;
+    if (atomic_load(&J->expired)) return 1;
+    if ((++*tick & 4095u) == 0 && now_s() > J->deadline) atomic_store(&J->expired, 1);
+    return atomic_load(&J->expired);
+}
+
 /* ---------------------------------------------------------------- cliques */
 
 typedef struct {
@@ -328,6 +348,7 @@ typedef struct {
     int ovf;
     int32_t* buf[33];   /* candidate list per depth */
     int64_t cap;
+    unsigned tick;
 } clq_ctx;
 
 
@@ -336,7 +357,8 @@ typedef struct {
  * above the last one; s = traversal size.  The traversal is a clique of size s
  * whose last vertex is `last`.
  */
-static void clq_expand(const job_t* J, clq_ctx* C, int s, int32_t last, const int32_t* cand, int64_t nc) {
+static void clq_expand(job_t* J, clq_ctx* C, int s, int32_t last, const int32_t* cand, int64_t nc) {
+    if (past_deadline(J, &C->tick)) return;
     add_u64(&C->nodes, 1, &C->ovf);
     add_u64(&C->reads, (uint64_t)J->outdeg[last], &C->ovf);
     if (s == J->k - 1) { add_u64(&C->leaves, (uint64_t)nc, &C->ovf); return; }
@@ -365,8 +387,10 @@ static void* clq_worker(void* arg) {
     uint64_t total = 0;
     int ovf = 0;
     for (;;) {
+        if (J->deadline > 0.0 && (atomic_load(&J->expired) || now_s() > J->deadline)) break;
         int64_t i = atomic_fetch_add(&J->next, 1);
         if (i >= J->nroots) break;
+        atomic_fetch_add(&J->started, 1);
         int32_t r = J->roots[i];
         C.leaves = C.nodes = C.reads = 0;
         if (J->k == 1) {
@@ -459,7 +483,8 @@ int or_clique_roots(int32_t n, const int64_t* rp, const int32_t* col, int k,
 /* ---------------------------------------------------------------- motifs (ESU) */
 
 typedef struct {
-    const job_t* J;
+    job_t* J;
+    unsigned tick;
     int32_t root;
     int32_t sub[OR_MAXK];
     int32_t* ext[OR_MAXK + 1];  /* extension list per depth */
@@ -493,9 +518,10 @@ static void esu_block(esu_ctx* E, int32_t w, int d) {
  * candidate vertices (> root, in the exclusive neighbourhood) of length ne.
  */
 static void esu_extend(esu_ctx* E, int s, const int32_t* ext, int64_t ne) {
-    const job_t* J = E->J;
+    job_t* J = E->J;
     const graph_t* g = &J->g;
     if (s == J->k) { esu_leaf(E); return; }
+    if (past_deadline(J, &E->tick)) return;
     add_u64(&E->nodes, 1, &E->ovf);
     add_u64(&E->reads, (uint64_t)deg_of(g, E->sub[s - 1]), &E->ovf);
     int32_t* nxt = E->ext[s + 1];
@@ -527,8 +553,10 @@ static void* esu_worker(void* arg) {
         E.ext[s] = (int32_t*)malloc(sizeof(int32_t) * (size_t)((maxd + 1) * (s + 1) + 1));
     E.blocked = (int32_t*)calloc((size_t)(J->g.n > 0 ? J->g.n : 1), sizeof(int32_t));
     for (;;) {
+        if (J->deadline > 0.0 && (atomic_load(&J->expired) || now_s() > J->deadline)) break;
         int64_t i = atomic_fetch_add(&J->next, 1);
         if (i >= J->nroots) break;
+        atomic_fetch_add(&J->started, 1);
         int32_t r = J->roots[i];
         E.root = r;
         E.leaves = E.nodes = E.reads = 0;
@@ -655,4 +683,71 @@ void or_core(int32_t n, const int64_t* rp, const int32_t* col, int32_t* core) {
     }
     for (int32_t v = 0; v < n; ++v) core[v] = deg[v];
     free(deg); free(bin); free(pos); free(vert);
+}
+
+/* ====================================================================== */
+/* time-bounded runs (CPU throughput baseline)                             */
+/* ====================================================================== */
+
+/*
+ * Same enumeration as or_clique_roots / or_motif_roots over the listed roots,
+ * stopped once `seconds` of wall-clock time have passed: threads take no new
+ * root and abandon the current one.  Every subgraph found before the stop is
+ * counted.  Returns the subgraphs found; *started = roots begun, *elapsed =
+ * seconds used.
+ */
+uint64_t or_clique_timed(int32_t n, const int64_t* rp, const int32_t* col, int k, const int32_t* roots,
+                         int64_t nroots, int nthreads, double seconds, int64_t* started, double* elapsed) {
+    job_t* J = (job_t*)calloc(1, sizeof(job_t));
+    J->g = (graph_t){ n, rp, col };
+    J->k = k;
+    J->roots = roots;
+    J->nroots = nroots;
+    atomic_init(&J->next, 0);
+    atomic_init(&J->expired, 0);
+    atomic_init(&J->started, 0);
+    J->rank = make_rank(&J->g);
+    int64_t* od = (int64_t*)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
+    for (int32_t v = 0; v < n; ++v)
+        for (int64_t e = rp[v]; e < rp[v + 1]; ++e)
+            if (J->rank[col[e]] > J->rank[v]) od[v]++;
+    J->outdeg = od;
+    pthread_mutex_init(&J->lock, NULL);
+    double t0 = now_s();
+    J->deadline = t0 + seconds;
+    run_pool(J, nthreads, clq_worker);
+    *elapsed = now_s() - t0;
+    *started = atomic_load(&J->started);
+    uint64_t tot = J->total;
+    free(od);
+    free((void*)J->rank);
+    pthread_mutex_destroy(&J->lock);
+    free(J);
+    return tot;
+}
+
+uint64_t or_motif_timed(int32_t n, const int64_t* rp, const int32_t* col, int k, const int32_t* roots,
+                        int64_t nroots, int nthreads, double seconds, int64_t* started, double* elapsed) {
+    const class_info* ci = classes(k);
+    if (!ci) return 0;
+    job_t* J = (job_t*)calloc(1, sizeof(job_t));
+    J->g = (graph_t){ n, rp, col };
+    J->k = k;
+    J->ci = ci;
+    J->roots = roots;
+    J->nroots = nroots;
+    atomic_init(&J->next, 0);
+    atomic_init(&J->expired, 0);
+    atomic_init(&J->started, 0);
+    pthread_mutex_init(&J->lock, NULL);
+    double t0 = now_s();
+    J->deadline = t0 + seconds;
+    run_pool(J, nthreads, esu_worker);
+    *elapsed = now_s() - t0;
+    *started = atomic_load(&J->started);
+    uint64_t tot = 0;
+    for (int q = 0; q < ci->ncls; ++q) tot += J->counts[q];
+    pthread_mutex_destroy(&J->lock);
+    free(J);
+    return tot;
 }
