@@ -142,6 +142,8 @@ dm_status dm_motif_class_table(int k, uint8_t* out, size_t len);
 /*
  * Per-class counts of connected induced k-vertex subgraphs (Section IV-E,
  * motif counting; Alg. 4 right).  out_counts[cls] for cls < ncls(k); k in 3..6.
+ * Each subgraph is enumerated once, from its lowest (degree, id) vertex (the
+ * same root rule as cliques; per-root records and root lists use it).
  * Errors: DM_E_ARG, DM_E_K, DM_E_BUFSZ (out_len < ncls), DM_E_OVERFLOW,
  * DM_E_NOMEM, DM_E_HIP, DM_E_MODEL.
  */
@@ -158,6 +160,52 @@ dm_status dm_count_motifs(dm_graph* g, int k, uint64_t* out_counts, size_t out_l
  */
 dm_status dm_batch(dm_graph* const* gs, int32_t num_graphs, int op, int k, uint64_t* out_counts,
                    size_t out_len, const dm_options* opt);
+
+/* ---------------------------------------------------------------------------
+ * Learned root ordering (an addition to the paper's method; it only orders and
+ * chunks the initial root queue and never changes a count).  The model is a
+ * 4 -> 64 -> 64 -> 1 FP32 MLP with ReLU that maps the standardised log1p of
+ * four per-vertex features (degree, 2-hop degree sum, core number, triangle
+ * count) to log(1 + enumeration-tree nodes of the root).  Parameter blob
+ * (device, DM_MLP_NPARAMS floats): W1[64][4], b1[64], W2[64][64], b2[64],
+ * w3[64], b3, then feature mean[4] and std[4] of log1p(feature).
+ * All pointers below are device pointers unless stated; calls synchronise
+ * `stream` before returning.
+ * ------------------------------------------------------------------------- */
+#define DM_MLP_NET 4545
+#define DM_MLP_NPARAMS 4553
+
+/* Per-vertex features as int64 [n][4]: degree, sum of neighbour degrees, core
+ * number (k-core decomposition), number of triangles containing the vertex. */
+dm_status dm_features(dm_graph* g, int64_t* out, void* stream);
+
+/* He-uniform weights from `seed`, zero biases, identity normaliser. */
+dm_status dm_mlp_init(float* params, uint64_t seed, void* stream);
+
+/* Set the normaliser slots to the mean / std of log1p(feats) over n rows. */
+dm_status dm_mlp_fit_normalizer(float* params, const int64_t* feats, int64_t n, void* stream);
+
+/* out[r] = network(feats[r]) for r < n. */
+dm_status dm_mlp_forward(const float* params, const int64_t* feats, int64_t n, float* out, void* stream);
+
+/* out[r] = log1p(root_stats[r][0]) (tree nodes recorded by DM_RECORD_ROOTS). */
+dm_status dm_mlp_targets(const uint64_t* root_stats, int64_t n, float* out, void* stream);
+
+/* Mean squared error over the n rows and its gradient (DM_MLP_NET floats);
+ * *loss is host memory. */
+dm_status dm_mlp_loss_grad(const float* params, const int64_t* feats, const float* targets, int64_t n,
+                           float* grad, float* loss, void* stream);
+
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8, bias-corrected, step t >= 1) on
+ * the DM_MLP_NET network weights; m and v are caller-owned moment buffers. */
+dm_status dm_mlp_adam_step(float* params, const float* grad, float* m, float* v, int64_t t, float lr,
+                           void* stream);
+
+/* Minibatch Adam training: every epoch shuffles the rows (seeded) and takes
+ * one step per batch.  loss_history (host, `epochs` floats, nullable) gets the
+ * mean batch loss of each epoch. */
+dm_status dm_mlp_train(float* params, const int64_t* feats, const float* targets, int64_t n, int epochs,
+                       int batch, float lr, uint64_t seed, float* loss_history, void* stream);
 
 /* Static text for a status code. */
 const char* dm_strerror(dm_status s);

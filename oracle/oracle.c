@@ -25,12 +25,13 @@
  * Levels:
  *   L1  brute force over every k-subset, straight from the definitions.
  *   L2  plain enumerators: clique backtracking in (degree, id) rank order, and
- *       ESU (Wernicke 2006) for connected k-sets rooted at their minimum id.
+ *       ESU (Wernicke 2006) for connected k-sets rooted at their lowest
+ *       (degree, id) vertex.
  *       Multi-threaded over roots with pthreads.
  *
  * Per-root outputs (used for sampled parity at sizes where a full run is
- * infeasible): every clique is credited to its lowest vertex in (degree asc,
- * id asc) rank; every connected k-set to its smallest id.  For a root r,
+ * infeasible): every clique and every connected k-set is credited to its
+ * lowest vertex in (degree asc, id asc) rank.  For a root r,
  *   leaves(r) = number of k-vertex results credited to r,
  *   nodes(r)  = number of j-vertex traversals (1 <= j <= k-1) credited to r
  *               (j-cliques, or connected j-sets, whose root is r),
@@ -283,7 +284,15 @@ int or_motif_brute(int32_t n, const int64_t* rp, const int32_t* col, int k,
         int q = ci->class_of_code[c];
         if (q >= 0) {
             out_counts[q]++;
-            if (per_root_leaves) per_root_leaves[idx[0]]++;
+            if (per_root_leaves) {
+                int r = idx[0];
+                for (int a = 1; a < k; ++a) {
+                    int x = idx[a];
+                    int64_t dx = deg_of(&g, x), dr = deg_of(&g, r);
+                    if (dx < dr || (dx == dr && x < r)) r = x;
+                }
+                per_root_leaves[r]++;
+            }
         }
         int i = k - 1;
         while (i >= 0 && idx[i] == n - k + i) --i;
@@ -480,7 +489,9 @@ int or_clique_roots(int32_t n, const int64_t* rp, const int32_t* col, int k,
     return ret;
 }
 
-/* ---------------------------------------------------------------- motifs (ESU) */
+/* ---------------------------------------------------------------- motifs (ESU)
+ * ESU over the total order (degree, id): a connected k-set is enumerated once,
+ * from its lowest-ranked vertex (Wernicke 2006 works for any total order). */
 
 typedef struct {
     job_t* J;
@@ -515,7 +526,7 @@ static void esu_block(esu_ctx* E, int32_t w, int d) {
 
 /*
  * ESU step: sub has s vertices (blocked[] marks sub and N(sub)); ext holds
- * candidate vertices (> root, in the exclusive neighbourhood) of length ne.
+ * candidate vertices (ranked above the root, in the exclusive neighbourhood).
  */
 static void esu_extend(esu_ctx* E, int s, const int32_t* ext, int64_t ne) {
     job_t* J = E->J;
@@ -533,7 +544,7 @@ static void esu_extend(esu_ctx* E, int s, const int32_t* ext, int64_t ne) {
         for (int64_t j = 0; j < i; ++j) nxt[m++] = ext[j];
         for (int64_t e = g->rp[w]; e < g->rp[w + 1]; ++e) {
             int32_t u = g->col[e];
-            if (u > E->root && E->blocked[u] == 0) nxt[m++] = u;
+            if (J->rank[u] > J->rank[E->root] && E->blocked[u] == 0) nxt[m++] = u;
         }
         E->sub[s] = w;
         esu_block(E, w, +1);
@@ -567,7 +578,7 @@ static void* esu_worker(void* arg) {
         } else {
             int64_t m = 0;
             for (int64_t e = J->g.rp[r]; e < J->g.rp[r + 1]; ++e)
-                if (J->g.col[e] > r) E.ext[1][m++] = J->g.col[e];
+                if (J->rank[J->g.col[e]] > J->rank[r]) E.ext[1][m++] = J->g.col[e];
             esu_block(&E, r, +1);
             esu_extend(&E, 1, E.ext[1], m);
             esu_block(&E, r, -1);
@@ -610,10 +621,12 @@ int or_motif_roots(int32_t n, const int64_t* rp, const int32_t* col, int k,
     J->nroots = nroots;
     atomic_init(&J->next, 0);
     J->leaves = leaves; J->nodes = nodes; J->reads = reads;
+    J->rank = make_rank(&J->g);
     pthread_mutex_init(&J->lock, NULL);
     run_pool(J, nthreads, esu_worker);
     for (int q = 0; q < ci->ncls; ++q) out_counts[q] = J->counts[q];
     int ret = J->overflow ? 1 : 0;
+    free((void*)J->rank);
     free(all);
     pthread_mutex_destroy(&J->lock);
     free(J);
@@ -739,10 +752,12 @@ uint64_t or_motif_timed(int32_t n, const int64_t* rp, const int32_t* col, int k,
     atomic_init(&J->next, 0);
     atomic_init(&J->expired, 0);
     atomic_init(&J->started, 0);
+    J->rank = make_rank(&J->g);
     pthread_mutex_init(&J->lock, NULL);
     double t0 = now_s();
     J->deadline = t0 + seconds;
     run_pool(J, nthreads, esu_worker);
+    free((void*)J->rank);
     *elapsed = now_s() - t0;
     *started = atomic_load(&J->started);
     uint64_t tot = 0;

@@ -262,8 +262,14 @@ struct dm_graph {
   bool dag = false;
   int ddmax = 0;
   Buf rank, order, drp, dcol;
+  // the undirected graph renamed by rank (motif counting), built on first use
+  bool ranked = false;
+  Buf urp, ucol;
   // workspace reused across calls
   Buf ctrl, out, rows, ext_vert, ext_mask, newbuf, qroot, qstat, qlo, qhi, qbounds, rgraph;
+  // learned ordering: features (cached), predictions, LPT order
+  bool feat_ready = false;
+  Buf feat, pred, lorder;
   hipStream_t own = nullptr;
 };
 
@@ -380,6 +386,19 @@ static dm_status ensure_dag(dm_graph* g, hipStream_t s) {
   return DM_OK;
 }
 
+static dm_status ensure_ranked(dm_graph* g, hipStream_t s) {
+  if (g->ranked) return DM_OK;
+  dm_status st = ensure_dag(g, s);
+  if (st != DM_OK) return st;
+  HIP_OR_RETURN(g->urp.ensure(sizeof(int64_t) * (static_cast<size_t>(g->n) + 1)), "relabel: allocate");
+  HIP_OR_RETURN(g->ucol.ensure(sizeof(int32_t) * static_cast<size_t>(g->nnz > 0 ? g->nnz : 1)), "relabel: allocate");
+  HIP_OR_RETURN(relabel_by_rank(g->rp.as<int64_t>(), g->col.as<int32_t>(), g->n, g->nnz, g->rank.as<int32_t>(),
+                                g->order.as<int32_t>(), g->urp.as<int64_t>(), g->ucol.as<int32_t>(), s),
+                "relabel");
+  g->ranked = true;
+  return DM_OK;
+}
+
 // ====================================================================== options
 
 namespace {
@@ -407,6 +426,7 @@ dm_status read_opt(const dm_options* o, Opt* r) {
   if (o->rebalance < 0.f || o->rebalance > 1.f) return fail(DM_E_ARG, "rebalance must be in [0, 1]");
   if (o->num_roots < 0 || (o->num_roots > 0 && !o->roots)) return fail(DM_E_ARG, "bad root list");
   if ((o->sched & DM_RECORD_ROOTS) && !o->root_stats) return fail(DM_E_ARG, "DM_RECORD_ROOTS needs root_stats");
+  if ((o->sched & DM_SCHED_LEARNED) && o->roots) return fail(DM_E_ARG, "learned ordering orders every root; no root list");
   r->sched = o->sched;
   r->stream = static_cast<hipStream_t>(o->stream);
   r->chunk = o->chunk;
@@ -505,6 +525,37 @@ dm_status upload_roots(dm_graph* g, const Opt& o, bool to_rank, hipStream_t s) {
   return DM_OK;
 }
 
+dm_status ensure_features(dm_graph* g, hipStream_t s) {
+  if (g->feat_ready) return DM_OK;
+  dm_status st = ensure_dag(g, s);
+  if (st != DM_OK) return st;
+  HIP_OR_RETURN(g->feat.ensure(sizeof(int64_t) * 4 * static_cast<size_t>(g->n > 0 ? g->n : 1)), "features: allocate");
+  HIP_OR_RETURN(compute_features(g->rp.as<int64_t>(), g->col.as<int32_t>(), g->n, g->drp.as<int64_t>(),
+                                 g->dcol.as<int32_t>(), g->order.as<int32_t>(), g->feat.as<int64_t>(), s),
+                "features");
+  g->feat_ready = true;
+  return DM_OK;
+}
+
+// Learned queue: MLP prediction of every root's tree size, longest first,
+// chunks of about equal predicted cost (about `per_wave` chunks per wave).
+// On return g->lorder holds vertex ids in queue order and g->qbounds the chunk
+// starts (+ n).
+dm_status learned_queue(dm_graph* g, const Opt& o, int grid, hipStream_t s, int64_t* nchunks) {
+  dm_status st = ensure_features(g, s);
+  if (st != DM_OK) return st;
+  const size_t n = static_cast<size_t>(g->n > 0 ? g->n : 1);
+  HIP_OR_RETURN(g->pred.ensure(sizeof(float) * n), "learned: allocate");
+  HIP_OR_RETURN(g->lorder.ensure(sizeof(int32_t) * n), "learned: allocate");
+  HIP_OR_RETURN(g->qbounds.ensure(sizeof(int64_t) * (n + 1)), "learned: allocate");
+  HIP_OR_RETURN(mlp_forward(o.mlp, g->feat.as<int64_t>(), g->n, g->pred.as<float>(), s), "learned: forward");
+  const int per_wave = 4;
+  HIP_OR_RETURN(lpt_order(g->pred.as<float>(), g->n, grid * per_wave, g->lorder.as<int32_t>(), g->qbounds.as<int64_t>(),
+                          nchunks, s),
+                "learned: order");
+  return DM_OK;
+}
+
 dm_status clique_run(dm_graph* g, int k, const Opt& o, hipStream_t s, const int32_t* root_graph, int ngraphs,
                      uint64_t* host_out) {
   dm_status st = ensure_dag(g, s);
@@ -527,12 +578,22 @@ dm_status clique_run(dm_graph* g, int k, const Opt& o, hipStream_t s, const int3
   int64_t nq = g->n;
   const int32_t* qroot = nullptr;
   const int32_t* qstat = g->order.as<int32_t>();
+  int64_t nchunks = 0;
+  const bool learned = (o.sched & DM_SCHED_LEARNED) && !o.roots;
   if (o.roots) {
     st = upload_roots(g, o, true, s);
     if (st != DM_OK) return st;
     nq = o.num_roots;
     qroot = g->qroot.as<int32_t>();
     qstat = nullptr;
+  } else if (learned) {
+    st = learned_queue(g, o, grid, s, &nchunks);
+    if (st != DM_OK) return st;
+    HIP_OR_RETURN(g->qroot.ensure(sizeof(int32_t) * static_cast<size_t>(g->n > 0 ? g->n : 1)), "workspace");
+    HIP_OR_RETURN(launch_gather_i32(g->rank.as<int32_t>(), g->lorder.as<int32_t>(), g->qroot.as<int32_t>(), g->n, s),
+                  "learned: rank map");
+    qroot = g->qroot.as<int32_t>();
+    qstat = g->lorder.as<int32_t>();
   }
   HIP_OR_RETURN(g->ctrl.ensure(ctrl_bytes()), "workspace");
   HIP_OR_RETURN(g->out.ensure(sizeof(uint64_t) * ngraphs), "workspace");
@@ -560,6 +621,10 @@ dm_status clique_run(dm_graph* g, int k, const Opt& o, hipStream_t s, const int3
   A.rows_global = rows_lds ? nullptr : g->rows.as<unsigned long long>();
   A.prune = o.root_stats ? 0 : 1;
   A.S = make_sched(g, o, grid, nq, qroot, qstat);
+  if (learned) {
+    A.S.qbounds = g->qbounds.as<int64_t>();
+    A.S.nchunks = nchunks;
+  }
   if (nq > 0) HIP_OR_RETURN(launch_clique(A, grid, rows_lds, lds, s), "clique kernel launch");
   return finish(g, s, host_out, static_cast<size_t>(ngraphs));
 }
@@ -569,6 +634,10 @@ dm_status motif_run(dm_graph* g, int k, const Opt& o, hipStream_t s, const int32
   const ClassTables* T = tables(k);
   uint8_t* dtab = nullptr;
   HIP_OR_RETURN(device_table(k, &dtab), "class table upload");
+  {
+    dm_status st = ensure_ranked(g, s);
+    if (st != DM_OK) return st;
+  }
   const int dmax = g->dmax > 0 ? g->dmax : 1;
   const size_t lds = motif_lds_bytes(k, T->ncls);
   int per_cu = 0;
@@ -584,13 +653,26 @@ dm_status motif_run(dm_graph* g, int k, const Opt& o, hipStream_t s, const int32
     A.level_cap[s2] = static_cast<int64_t>(s2) * dmax;
     cap_total += A.level_cap[s2];
   }
+  // queue in rank space; root_stats rows by original vertex id (or list position)
   int64_t nq = g->n;
   const int32_t* qroot = nullptr;
+  const int32_t* qstat = g->order.as<int32_t>();
+  int64_t nchunks = 0;
+  const bool learned = (o.sched & DM_SCHED_LEARNED) && !o.roots;
   if (o.roots) {
-    dm_status st = upload_roots(g, o, false, s);
+    dm_status st = upload_roots(g, o, true, s);
     if (st != DM_OK) return st;
     nq = o.num_roots;
     qroot = g->qroot.as<int32_t>();
+    qstat = nullptr;
+  } else if (learned) {
+    dm_status st = learned_queue(g, o, grid, s, &nchunks);
+    if (st != DM_OK) return st;
+    HIP_OR_RETURN(g->qroot.ensure(sizeof(int32_t) * static_cast<size_t>(g->n > 0 ? g->n : 1)), "workspace");
+    HIP_OR_RETURN(launch_gather_i32(g->rank.as<int32_t>(), g->lorder.as<int32_t>(), g->qroot.as<int32_t>(), g->n, s),
+                  "learned: rank map");
+    qroot = g->qroot.as<int32_t>();
+    qstat = g->lorder.as<int32_t>();
   }
   HIP_OR_RETURN(g->ctrl.ensure(ctrl_bytes()), "workspace");
   HIP_OR_RETURN(g->out.ensure(sizeof(uint64_t) * static_cast<size_t>(ngraphs) * T->ncls), "workspace");
@@ -605,8 +687,8 @@ dm_status motif_run(dm_graph* g, int k, const Opt& o, hipStream_t s, const int32
     HIP_OR_RETURN(launch_fill_u64(reinterpret_cast<unsigned long long*>(o.root_stats), 3 * (o.roots ? o.num_roots : g->n),
                                   0ull, s),
                   "clear");
-  A.rp = g->rp.as<int64_t>();
-  A.col = g->col.as<int32_t>();
+  A.rp = g->urp.as<int64_t>();
+  A.col = g->ucol.as<int32_t>();
   A.n = g->n;
   A.k = k;
   A.dmax = dmax;
@@ -622,7 +704,11 @@ dm_status motif_run(dm_graph* g, int k, const Opt& o, hipStream_t s, const int32
   A.ext_mask = g->ext_mask.as<uint8_t>();
   A.new_buf = g->newbuf.as<int32_t>();
   A.wave_ext_cap = cap_total;
-  A.S = make_sched(g, o, grid, nq, qroot, nullptr);
+  A.S = make_sched(g, o, grid, nq, qroot, qstat);
+  if (learned) {
+    A.S.qbounds = g->qbounds.as<int64_t>();
+    A.S.nchunks = nchunks;
+  }
   if (nq > 0) HIP_OR_RETURN(launch_motif(A, grid, lds, s), "motif kernel launch");
   return finish(g, s, host_out, static_cast<size_t>(ngraphs) * T->ncls);
 }
@@ -729,21 +815,20 @@ dm_status batch_run(dm_graph* const* gs, int32_t num, int op, int k, int width, 
     }
   }
   std::vector<uint64_t> tmp(static_cast<size_t>(num) * width);
-  dm_status st;
-  if (op == DM_OP_CLIQUE) {
-    st = ensure_dag(B->uni, s);
-    if (st != DM_OK) return st;
-    if (!B->gor_ready) {
-      HIP_OR_RETURN(B->gor.ensure(sizeof(int32_t) * (B->uni->n > 0 ? B->uni->n : 1)), "batch: allocate");
-      HIP_OR_RETURN(launch_gather_i32(B->gov.as<int32_t>(), B->uni->order.as<int32_t>(), B->gor.as<int32_t>(),
-                                      B->uni->n, s),
-                    "batch: rank map");
-      B->gor_ready = true;
-    }
-    st = clique_run(B->uni, k, o, s, B->gor.as<int32_t>(), num, tmp.data());
-  } else {
-    st = motif_run(B->uni, k, o, s, B->gov.as<int32_t>(), num, tmp.data());
+  // both kernels take roots in rank space: graph index of every rank
+  dm_status st = ensure_dag(B->uni, s);
+  if (st != DM_OK) return st;
+  if (!B->gor_ready) {
+    HIP_OR_RETURN(B->gor.ensure(sizeof(int32_t) * (B->uni->n > 0 ? B->uni->n : 1)), "batch: allocate");
+    HIP_OR_RETURN(launch_gather_i32(B->gov.as<int32_t>(), B->uni->order.as<int32_t>(), B->gor.as<int32_t>(),
+                                    B->uni->n, s),
+                  "batch: rank map");
+    B->gor_ready = true;
   }
+  if (op == DM_OP_CLIQUE)
+    st = clique_run(B->uni, k, o, s, B->gor.as<int32_t>(), num, tmp.data());
+  else
+    st = motif_run(B->uni, k, o, s, B->gor.as<int32_t>(), num, tmp.data());
   if (st == DM_OK) std::memcpy(out, tmp.data(), sizeof(uint64_t) * tmp.size());
   return st;
 }
@@ -771,4 +856,120 @@ extern "C" dm_status dm_batch(dm_graph* const* gs, int32_t num_graphs, int op, i
   if (o.roots) return fail(DM_E_ARG, "root lists are not supported in batches");
   if ((o.sched & DM_SCHED_LEARNED) && !o.mlp) return fail(DM_E_MODEL, "DM_SCHED_LEARNED needs mlp parameters");
   return batch_run(gs, num_graphs, op, k, width, o, out_counts);
+}
+
+// ====================================================================== learned ordering ABI
+
+extern "C" dm_status dm_features(dm_graph* g, int64_t* out, void* stream) {
+  if (!g || !out) return fail(DM_E_ARG, "null graph or output");
+  hipStream_t s = pick_stream(g, stream);
+  dm_status st = ensure_features(g, s);
+  if (st != DM_OK) return st;
+  HIP_OR_RETURN(hipMemcpyAsync(out, g->feat.p, sizeof(int64_t) * 4 * static_cast<size_t>(g->n), hipMemcpyDeviceToDevice, s),
+                "features: copy");
+  HIP_OR_RETURN(hipStreamSynchronize(s), "features: sync");
+  return DM_OK;
+}
+
+static hipStream_t plain_stream(void* s) { return static_cast<hipStream_t>(s); }
+
+extern "C" dm_status dm_mlp_init(float* params, uint64_t seed, void* stream) {
+  if (!params) return fail(DM_E_ARG, "null params");
+  hipStream_t s = plain_stream(stream);
+  HIP_OR_RETURN(mlp_init(params, seed, s), "mlp init");
+  HIP_OR_RETURN(hipStreamSynchronize(s), "mlp init");
+  return DM_OK;
+}
+
+extern "C" dm_status dm_mlp_fit_normalizer(float* params, const int64_t* feats, int64_t n, void* stream) {
+  if (!params || !feats || n <= 0) return fail(DM_E_ARG, "null pointer or n <= 0");
+  hipStream_t s = plain_stream(stream);
+  HIP_OR_RETURN(mlp_fit_normaliser(params, feats, n, s), "mlp normaliser");
+  HIP_OR_RETURN(hipStreamSynchronize(s), "mlp normaliser");
+  return DM_OK;
+}
+
+extern "C" dm_status dm_mlp_forward(const float* params, const int64_t* feats, int64_t n, float* out, void* stream) {
+  if (!params || !feats || !out || n < 0) return fail(DM_E_ARG, "null pointer or n < 0");
+  hipStream_t s = plain_stream(stream);
+  HIP_OR_RETURN(mlp_forward(params, feats, n, out, s), "mlp forward");
+  HIP_OR_RETURN(hipStreamSynchronize(s), "mlp forward");
+  return DM_OK;
+}
+
+extern "C" dm_status dm_mlp_targets(const uint64_t* root_stats, int64_t n, float* out, void* stream) {
+  if (!root_stats || !out || n < 0) return fail(DM_E_ARG, "null pointer or n < 0");
+  hipStream_t s = plain_stream(stream);
+  HIP_OR_RETURN(mlp_targets(reinterpret_cast<const unsigned long long*>(root_stats), n, out, s), "mlp targets");
+  HIP_OR_RETURN(hipStreamSynchronize(s), "mlp targets");
+  return DM_OK;
+}
+
+extern "C" dm_status dm_mlp_loss_grad(const float* params, const int64_t* feats, const float* targets, int64_t n,
+                                      float* grad, float* loss, void* stream) {
+  if (!params || !feats || !targets || !grad || !loss || n <= 0) return fail(DM_E_ARG, "null pointer or n <= 0");
+  hipStream_t s = plain_stream(stream);
+  Buf partial, dloss;
+  HIP_OR_RETURN(partial.ensure(sizeof(float) * (kMlpNet + 1) * static_cast<size_t>((n + 63) / 64)), "mlp grad: allocate");
+  HIP_OR_RETURN(dloss.ensure(sizeof(float)), "mlp grad: allocate");
+  HIP_OR_RETURN(mlp_loss_grad(params, feats, targets, nullptr, n, partial.as<float>(), grad, dloss.as<float>(), s),
+                "mlp grad");
+  HIP_OR_RETURN(hipMemcpyAsync(loss, dloss.p, sizeof(float), hipMemcpyDeviceToHost, s), "mlp grad: copy");
+  HIP_OR_RETURN(hipStreamSynchronize(s), "mlp grad");
+  return DM_OK;
+}
+
+extern "C" dm_status dm_mlp_adam_step(float* params, const float* grad, float* m, float* v, int64_t t, float lr,
+                                      void* stream) {
+  if (!params || !grad || !m || !v || t < 1) return fail(DM_E_ARG, "null pointer or step < 1");
+  hipStream_t s = plain_stream(stream);
+  HIP_OR_RETURN(mlp_adam(params, grad, m, v, t, lr, s), "adam");
+  HIP_OR_RETURN(hipStreamSynchronize(s), "adam");
+  return DM_OK;
+}
+
+extern "C" dm_status dm_mlp_train(float* params, const int64_t* feats, const float* targets, int64_t n, int epochs,
+                                  int batch, float lr, uint64_t seed, float* loss_history, void* stream) {
+  if (!params || !feats || !targets || n <= 0 || epochs < 0 || batch <= 0) return fail(DM_E_ARG, "bad arguments");
+  if (n > 2000000000LL) return fail(DM_E_ARG, "n too large");
+  hipStream_t s = plain_stream(stream);
+  const int64_t nb = (n + batch - 1) / batch;
+  Buf partial, grad, m, v, keys, keys2, perm_in, perm, temp, losses;
+  const size_t tb = mlp_shuffle_temp_bytes(n);
+  HIP_OR_RETURN(partial.ensure(sizeof(float) * (kMlpNet + 1) * static_cast<size_t>((batch + 63) / 64)), "train: allocate");
+  HIP_OR_RETURN(grad.ensure(sizeof(float) * kMlpNet), "train: allocate");
+  HIP_OR_RETURN(m.ensure(sizeof(float) * kMlpNet), "train: allocate");
+  HIP_OR_RETURN(v.ensure(sizeof(float) * kMlpNet), "train: allocate");
+  HIP_OR_RETURN(keys.ensure(sizeof(unsigned long long) * n), "train: allocate");
+  HIP_OR_RETURN(keys2.ensure(sizeof(unsigned long long) * n), "train: allocate");
+  HIP_OR_RETURN(perm_in.ensure(sizeof(int32_t) * n), "train: allocate");
+  HIP_OR_RETURN(perm.ensure(sizeof(int32_t) * n), "train: allocate");
+  HIP_OR_RETURN(temp.ensure(tb), "train: allocate");
+  HIP_OR_RETURN(losses.ensure(sizeof(float) * nb), "train: allocate");
+  HIP_OR_RETURN(launch_fill_i32(m.as<int32_t>(), kMlpNet, 0, s), "train: clear");
+  HIP_OR_RETURN(launch_fill_i32(v.as<int32_t>(), kMlpNet, 0, s), "train: clear");
+  std::vector<float> host_losses(static_cast<size_t>(nb));
+  int64_t step = 0;
+  for (int ep = 0; ep < epochs; ++ep) {
+    HIP_OR_RETURN(mlp_shuffle(seed * 1000003ull + static_cast<uint64_t>(ep), n, keys.as<unsigned long long>(),
+                              keys2.as<unsigned long long>(), perm_in.as<int32_t>(), perm.as<int32_t>(), temp.p, tb, s),
+                  "train: shuffle");
+    for (int64_t b = 0; b < nb; ++b) {
+      const int64_t rows = std::min<int64_t>(batch, n - b * batch);
+      HIP_OR_RETURN(mlp_loss_grad(params, feats, targets, perm.as<int32_t>() + b * batch, rows, partial.as<float>(),
+                                  grad.as<float>(), losses.as<float>() + b, s),
+                    "train: grad");
+      HIP_OR_RETURN(mlp_adam(params, grad.as<float>(), m.as<float>(), v.as<float>(), ++step, lr, s), "train: adam");
+    }
+    if (loss_history) {
+      HIP_OR_RETURN(hipMemcpyAsync(host_losses.data(), losses.p, sizeof(float) * nb, hipMemcpyDeviceToHost, s),
+                    "train: loss");
+      HIP_OR_RETURN(hipStreamSynchronize(s), "train: loss");
+      double acc = 0.0;
+      for (int64_t b = 0; b < nb; ++b) acc += host_losses[b];
+      loss_history[ep] = static_cast<float>(acc / static_cast<double>(nb));
+    }
+  }
+  HIP_OR_RETURN(hipStreamSynchronize(s), "train");
+  return DM_OK;
 }

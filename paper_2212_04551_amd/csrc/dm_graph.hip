@@ -106,6 +106,27 @@ __global__ void __launch_bounds__(256) emit_kernel(const int64_t* rp, const int3
   }
 }
 
+// write (rank(u) << 32 | rank(w)) for every directed edge u -> w
+__global__ void __launch_bounds__(256) emit_all_kernel(const int64_t* rp, const int32_t* col, int32_t n,
+                                                       const int32_t* rank, unsigned long long* keys) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t nnz = rp[n];
+  if (i >= nnz) return;
+  // source vertex of entry i: last v with rp[v] <= i
+  int64_t lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (rp[mid] <= i) lo = mid; else hi = mid;
+  }
+  keys[i] = (static_cast<unsigned long long>(rank[lo]) << 32) | static_cast<uint32_t>(rank[col[i]]);
+}
+
+__global__ void deg_by_rank_kernel(const int64_t* rp, const int32_t* order, int32_t n, int64_t* cnt) {
+  const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r < n) cnt[r] = rp[order[r] + 1] - rp[order[r]];
+  if (r == n) cnt[n] = 0;
+}
+
 __global__ void split_low_kernel(const unsigned long long* keys, int64_t m, int32_t* dcol) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < m) dcol[i] = static_cast<int32_t>(keys[i] & 0xffffffffull);
@@ -294,6 +315,52 @@ done:
   (void)hipFree(eoff);
   (void)hipFree(cnt_rank);
   (void)hipFree(dmax_dev);
+  (void)hipFree(temp);
+  return err;
+}
+
+}  // namespace dm
+
+namespace dm {
+
+// The same graph with vertex v renamed rank[v]: urp / ucol in rank space,
+// adjacency sorted.  Used by motif counting so that every traversal is rooted
+// at its lowest (degree, id) vertex.
+hipError_t relabel_by_rank(const int64_t* rp, const int32_t* col, int32_t n, int64_t nnz, const int32_t* rank,
+                           const int32_t* order, int64_t* urp, int32_t* ucol, hipStream_t s) {
+  if (n <= 0) return launch_fill_u64(reinterpret_cast<unsigned long long*>(urp), 1, 0ull, s);
+  hipError_t err = hipSuccess;
+  unsigned long long *keys = nullptr, *keys2 = nullptr;
+  int64_t* cnt = nullptr;
+  void* temp = nullptr;
+  size_t need = 0, tb = 0;
+  const int64_t mk = nnz > 0 ? nnz : 1;
+  DM_TRY(hipMalloc(&keys, sizeof(unsigned long long) * mk));
+  DM_TRY(hipMalloc(&keys2, sizeof(unsigned long long) * mk));
+  DM_TRY(hipMalloc(&cnt, sizeof(int64_t) * (static_cast<int64_t>(n) + 1)));
+  DM_TRY(hipcub::DeviceRadixSort::SortKeys(nullptr, need, keys, keys2, static_cast<int>(mk), 0, 64, s));
+  tb = need;
+  DM_TRY(hipcub::DeviceScan::ExclusiveSum(nullptr, need, cnt, urp, n + 1, s));
+  tb = need > tb ? need : tb;
+  DM_TRY(hipMalloc(&temp, tb > 0 ? tb : 16));
+  if (nnz > 0) {
+    hipLaunchKernelGGL(emit_all_kernel, dim3(blocks_for(nnz, 256)), dim3(256), 0, s, rp, col, n, rank, keys);
+    DM_TRY(hipGetLastError());
+    need = tb;
+    DM_TRY(hipcub::DeviceRadixSort::SortKeys(temp, need, keys, keys2, static_cast<int>(nnz), 0, 32 + bits_for(n), s));
+    hipLaunchKernelGGL(split_low_kernel, dim3(blocks_for(nnz, 256)), dim3(256), 0, s, keys2, nnz, ucol);
+    DM_TRY(hipGetLastError());
+  }
+  hipLaunchKernelGGL(deg_by_rank_kernel, dim3(blocks_for(static_cast<int64_t>(n) + 1, 256)), dim3(256), 0, s, rp, order,
+                     n, cnt);
+  DM_TRY(hipGetLastError());
+  need = tb;
+  DM_TRY(hipcub::DeviceScan::ExclusiveSum(temp, need, cnt, urp, n + 1, s));
+  DM_TRY(hipStreamSynchronize(s));
+done:
+  (void)hipFree(keys);
+  (void)hipFree(keys2);
+  (void)hipFree(cnt);
   (void)hipFree(temp);
   return err;
 }

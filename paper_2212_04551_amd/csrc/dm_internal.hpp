@@ -11,6 +11,9 @@
 
 namespace dm {
 
+constexpr int kMlpNet = 4 * 64 + 64 + 64 * 64 + 64 + 64 + 1;  // 4545 weights
+constexpr int kMlpBlob = kMlpNet + 8;                          // + feature mean[4], std[4]
+
 // Arguments of the persistent k-clique kernel (graph in rank space, DAG CSR).
 struct CliqueArgs {
   const int64_t* rp;       // DAG row offsets, n+1
@@ -69,6 +72,9 @@ hipError_t launch_validate(const int64_t* rp, const int32_t* col, int32_t n, int
 // (degree, id) rank orientation: out rank[n], order[n] (rank -> vertex), drp[n+1], dcol[nnz/2]
 hipError_t orient_by_degree(const int64_t* rp, const int32_t* col, int32_t n, int64_t nnz, int32_t* rank,
                             int32_t* order, int64_t* drp, int32_t* dcol, int* dmax_out, hipStream_t s);
+// the graph renamed by rank: urp[n+1], ucol[nnz] (sorted adjacency)
+hipError_t relabel_by_rank(const int64_t* rp, const int32_t* col, int32_t n, int64_t nnz, const int32_t* rank,
+                           const int32_t* order, int64_t* urp, int32_t* ucol, hipStream_t s);
 // max degree of a CSR (device), written to *out (device int)
 hipError_t launch_max_degree(const int64_t* rp, int32_t n, int* out, hipStream_t s);
 // map vertex ids through a table: out[i] = map[in[i]]
@@ -78,5 +84,21 @@ hipError_t launch_offset_i64(const int64_t* in, int64_t* out, int64_t count, int
 hipError_t launch_offset_i32(const int32_t* in, int32_t* out, int64_t count, int32_t off, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* out, int64_t count, int32_t value, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* out, int64_t count, unsigned long long value, hipStream_t s);
+
+// learned ordering (dm_learn.hip)
+hipError_t compute_features(const int64_t* rp, const int32_t* col, int32_t n, const int64_t* drp,
+                            const int32_t* dcol, const int32_t* order, int64_t* F, hipStream_t s);
+hipError_t mlp_init(float* P, uint64_t seed, hipStream_t s);
+hipError_t mlp_fit_normaliser(float* P, const int64_t* F, int64_t n, hipStream_t s);
+hipError_t mlp_forward(const float* P, const int64_t* F, int64_t n, float* out, hipStream_t s);
+hipError_t mlp_targets(const unsigned long long* stats, int64_t n, float* out, hipStream_t s);
+hipError_t mlp_loss_grad(const float* P, const int64_t* F, const float* T, const int32_t* rows, int64_t nrows,
+                         float* partial, float* grad, float* loss, hipStream_t s);
+hipError_t mlp_adam(float* P, const float* g, float* m, float* v, int64_t t, float lr, hipStream_t s);
+hipError_t mlp_shuffle(uint64_t seed, int64_t n, unsigned long long* keys, unsigned long long* keys_out,
+                       int32_t* vals, int32_t* vals_out, void* temp, size_t temp_bytes, hipStream_t s);
+size_t mlp_shuffle_temp_bytes(int64_t n);
+hipError_t lpt_order(const float* pred, int64_t n, int chunks_wanted, int32_t* order_out, int64_t* bounds_out,
+                     int64_t* nchunks, hipStream_t s);
 
 }  // namespace dm

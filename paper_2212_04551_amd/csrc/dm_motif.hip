@@ -16,6 +16,10 @@
 //     id, with one mask byte per entry: bit t = adjacent to v_t.  The mask makes
 //     `induce` free (the new vertex's bitmap field is its mask) and turns the
 //     canonical filter into an O(1) test.
+//   - Vertices are renamed by (degree, id) rank before the kernel runs, so
+//     "smaller" below means lower rank and each subgraph is rooted at its
+//     lowest-degree vertex (a cost that depends on graph structure, not on
+//     arbitrary labels, which is what the learned ordering predicts).
 //   - Canonical filter (the paper names Arabesque's rule without stating it;
 //     reading used here): a traversal is canonical iff v_0 is its smallest
 //     vertex and each later vertex is the smallest vertex adjacent to the

@@ -24,12 +24,14 @@ DM_OK, DM_E_ARG, DM_E_CSR, DM_E_K, DM_E_OVERFLOW, DM_E_NOMEM, DM_E_HIP, DM_E_BUF
 DM_CSR_HOST, DM_CSR_DEVICE, DM_CSR_TRUSTED = 0, 1, 2
 DM_SCHED_PLAIN, DM_SCHED_LEARNED, DM_SCHED_AUTOTUNE, DM_RECORD_ROOTS, DM_NO_DONATION = 0, 1, 2, 4, 8
 DM_OP_CLIQUE, DM_OP_MOTIF = 0, 1
-DM_MLP_NPARAMS = 4 * 64 + 64 + 64 * 64 + 64 + 64 + 1  # 4 -> 64 -> 64 -> 1
+DM_MLP_NET = 4 * 64 + 64 + 64 * 64 + 64 + 64 + 1  # 4 -> 64 -> 64 -> 1 weights
+DM_MLP_NPARAMS = DM_MLP_NET + 8                     # + feature mean[4], std[4]
 
 EXPORTS = [
     "dm_load_csr", "dm_free", "dm_graph_info", "dm_count_cliques", "dm_motif_num_classes",
     "dm_motif_class_mask", "dm_motif_class_table", "dm_count_motifs", "dm_batch", "dm_strerror",
-    "dm_last_error",
+    "dm_last_error", "dm_features", "dm_mlp_init", "dm_mlp_fit_normalizer", "dm_mlp_forward", "dm_mlp_targets",
+    "dm_mlp_loss_grad", "dm_mlp_adam_step", "dm_mlp_train",
 ]
 
 
@@ -92,6 +94,19 @@ def lib():
     L.dm_strerror.argtypes = [ctypes.c_int]
     L.dm_last_error.restype = ctypes.c_char_p
     L.dm_last_error.argtypes = []
+    for name, args in (
+        ("dm_features", [vp, vp, vp]),
+        ("dm_mlp_init", [vp, ctypes.c_uint64, vp]),
+        ("dm_mlp_fit_normalizer", [vp, vp, i64, vp]),
+        ("dm_mlp_forward", [vp, vp, i64, vp, vp]),
+        ("dm_mlp_targets", [vp, i64, vp, vp]),
+        ("dm_mlp_loss_grad", [vp, vp, vp, i64, vp, ctypes.POINTER(ctypes.c_float), vp]),
+        ("dm_mlp_adam_step", [vp, vp, vp, vp, i64, ctypes.c_float, vp]),
+        ("dm_mlp_train", [vp, vp, vp, i64, ctypes.c_int, ctypes.c_int, ctypes.c_float, ctypes.c_uint64, vp, vp]),
+    ):
+        f = getattr(L, name)
+        f.restype = ctypes.c_int
+        f.argtypes = args
     _lib = L
     return L
 
@@ -252,6 +267,73 @@ def batch(graphs: Sequence[DMGraph], op: int, k: int, **opt) -> np.ndarray:
     _check(lib().dm_batch(arr, len(graphs), op, k, out.ctypes.data, out.size, ctypes.byref(o)))
     del keep
     return out
+
+
+# ------------------------------------------------------------------ learned ordering
+# Device buffers are torch CUDA tensors: features int64 [n, 4], parameters
+# float32 [DM_MLP_NPARAMS], predictions / targets float32 [n].
+
+def _cur_stream(stream):
+    if stream is not None:
+        return _stream(stream)
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def features(g: DMGraph, stream=None):
+    import torch
+    out = torch.empty((g.n, 4), dtype=torch.int64, device="cuda")
+    _check(lib().dm_features(g.handle, out.data_ptr(), _cur_stream(stream)))
+    return out
+
+
+def mlp_new(seed: int = 0, stream=None):
+    import torch
+    p = torch.empty(DM_MLP_NPARAMS, dtype=torch.float32, device="cuda")
+    _check(lib().dm_mlp_init(p.data_ptr(), seed, _cur_stream(stream)))
+    return p
+
+
+def mlp_fit_normalizer(params, feats, stream=None):
+    _check(lib().dm_mlp_fit_normalizer(params.data_ptr(), feats.data_ptr(), feats.shape[0], _cur_stream(stream)))
+
+
+def mlp_forward(params, feats, stream=None):
+    import torch
+    out = torch.empty(feats.shape[0], dtype=torch.float32, device="cuda")
+    _check(lib().dm_mlp_forward(params.data_ptr(), feats.data_ptr(), feats.shape[0], out.data_ptr(),
+                                _cur_stream(stream)))
+    return out
+
+
+def mlp_targets(root_stats, stream=None):
+    import torch
+    n = root_stats.shape[0]
+    out = torch.empty(n, dtype=torch.float32, device="cuda")
+    _check(lib().dm_mlp_targets(root_stats.data_ptr(), n, out.data_ptr(), _cur_stream(stream)))
+    return out
+
+
+def mlp_loss_grad(params, feats, targets, stream=None):
+    import torch
+    grad = torch.empty(DM_MLP_NET, dtype=torch.float32, device="cuda")
+    loss = ctypes.c_float(0.0)
+    _check(lib().dm_mlp_loss_grad(params.data_ptr(), feats.data_ptr(), targets.data_ptr(), feats.shape[0],
+                                  grad.data_ptr(), ctypes.byref(loss), _cur_stream(stream)))
+    return float(loss.value), grad
+
+
+def mlp_adam_step(params, grad, m, v, t: int, lr: float, stream=None):
+    _check(lib().dm_mlp_adam_step(params.data_ptr(), grad.data_ptr(), m.data_ptr(), v.data_ptr(), t, lr,
+                                  _cur_stream(stream)))
+
+
+def mlp_train(params, feats, targets, epochs: int, batch: int = 4096, lr: float = 1e-3, seed: int = 0,
+              stream=None) -> np.ndarray:
+    hist = np.zeros(max(epochs, 1), dtype=np.float32)
+    _check(lib().dm_mlp_train(params.data_ptr(), feats.data_ptr(), targets.data_ptr(), feats.shape[0], epochs,
+                              batch, lr, seed, hist.ctypes.data, _cur_stream(stream)))
+    return hist[:epochs]
 
 
 # C names re-exported for callers that want the raw ABI

@@ -1,0 +1,145 @@
+"""GPU: learned root ordering.  Feature kernels equal the oracle exactly; MLP
+forward / gradient / Adam equal the FP64 oracle within FP32 rounding bounds;
+training lowers the loss; learned ordering never changes a count."""
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import mlp as M
+from paper_2212_04551_amd import dm
+from paper_2212_04551_amd import graphgen as gg
+
+pytestmark = pytest.mark.gpu
+
+EPS32 = 2.0 ** -24
+
+
+@pytest.mark.parametrize("name,make", [
+    ("ba", lambda: gg.barabasi_albert(3000, 4, 1)),
+    ("cl", lambda: gg.chung_lu(5000, 30000, 2.2, 400.0, 2)[0]),
+    ("er", lambda: gg.erdos_renyi(1500, 12000, 3)),
+    ("sbm", lambda: gg.sbm(20, 50, 0.4, 0.002, 4)),
+    ("star", lambda: gg.star(500)),
+    ("empty", lambda: gg.empty(30)),
+])
+def test_features_exact(name, make):
+    g = make()
+    h = dm.load_graph(g)
+    F = dm.features(h).cpu().numpy()
+    assert np.array_equal(F, O.features(g).astype(np.int64)), name
+
+
+def test_init_and_normaliser():
+    import torch
+    p = dm.mlp_new(7).cpu().numpy().astype(np.float64)
+    d = M.unpack(p)
+    assert np.all(np.abs(d["W1"]) <= np.sqrt(6 / 4)) and np.all(np.abs(d["W2"]) <= np.sqrt(6 / 64))
+    assert d["W1"].std() > 0.3 and not d["b1"].any() and not d["b2"].any() and d["b3"] == 0
+    assert np.all(d["mean"] == 0) and np.all(d["std"] == 1)
+    g = gg.barabasi_albert(4000, 3, 9)
+    h = dm.load_graph(g)
+    F = dm.features(h)
+    pt = dm.mlp_new(7)
+    dm.mlp_fit_normalizer(pt, F)
+    q = M.unpack(pt.cpu().numpy().astype(np.float64))
+    L = np.log1p(F.cpu().numpy().astype(np.float64))
+    assert np.allclose(q["mean"], L.mean(0), rtol=1e-6, atol=1e-6)
+    sd = L.std(0)
+    sd[sd < 1e-6] = 1.0  # a constant feature (BA graphs: core number = m0) keeps unit scale
+    assert np.allclose(q["std"], sd, rtol=1e-5, atol=1e-6)
+
+
+def _setup(seed, n=4096):
+    import torch
+    g = gg.chung_lu(n, 6 * n, 2.2, 200.0, seed)[0]
+    h = dm.load_graph(g)
+    F = dm.features(h)
+    p = dm.mlp_new(seed)
+    dm.mlp_fit_normalizer(p, F)
+    rng = np.random.default_rng(seed)
+    T = torch.from_numpy(rng.normal(3.0, 1.5, g.n).astype(np.float32)).cuda()
+    return g, h, F, p, T
+
+
+def test_forward_matches_oracle():
+    """|y - y_ref| <= 200 eps32 |net|(x): about 4 + 64 + 64 rounded operations
+    along each path, scaled by the all-absolute-value network."""
+    _, _, F, p, _ = _setup(1)
+    y = dm.mlp_forward(p, F).cpu().numpy().astype(np.float64)
+    pn = p.cpu().numpy().astype(np.float64)
+    Fn = F.cpu().numpy()
+    ref, _ = M.forward(pn, Fn)
+    bound = 200 * EPS32 * M.abs_output(pn, Fn) + 1e-7
+    assert np.all(np.abs(y - ref) <= bound)
+
+
+def test_gradient_matches_oracle():
+    """Per entry: sum over rows of |row term| x (accumulated-rounding factor +
+    relative error of (y - t) inherited from the forward pass)."""
+    _, _, F, p, T = _setup(2)
+    loss, g = dm.mlp_loss_grad(p, F, T)
+    pn = p.cpu().numpy().astype(np.float64)
+    Fn = F.cpu().numpy()
+    Tn = T.cpu().numpy().astype(np.float64)
+    n = Fn.shape[0]
+    y, _ = M.forward(pn, Fn)
+    dy_err = 200 * EPS32 * M.abs_output(pn, Fn) / np.maximum(np.abs(y - Tn), 1e-30)
+    w = (400 + n / 64 + 64) * EPS32 + dy_err
+    ref_loss, ref_g, A = M.loss_grad(pn, Fn, Tn, row_weight=w)
+    g = g.cpu().numpy().astype(np.float64)
+    bound = A + 1e-9
+    assert np.all(np.abs(g - ref_g) <= bound), float(np.max(np.abs(g - ref_g) / bound))
+    assert abs(loss - ref_loss) <= 1e-4 * ref_loss + 1e-6
+
+
+def test_adam_matches_oracle():
+    import torch
+    _, _, F, p, T = _setup(3)
+    _, g = dm.mlp_loss_grad(p, F, T)
+    m = torch.zeros(dm.DM_MLP_NET, device="cuda")
+    v = torch.zeros(dm.DM_MLP_NET, device="cuda")
+    pn = p.cpu().numpy().astype(np.float64)
+    norm0 = p.cpu().numpy()[M.NET:].copy()
+    mn = np.zeros(M.NET)
+    vn = np.zeros(M.NET)
+    for t in range(1, 4):
+        gn = g.cpu().numpy().astype(np.float64)
+        dm.mlp_adam_step(p, g, m, v, t, 1e-3)
+        pn, mn, vn = M.adam(pn, gn, mn, vn, t, 1e-3)
+    got = p.cpu().numpy().astype(np.float64)
+    assert np.allclose(got[:M.NET], pn[:M.NET], rtol=1e-5, atol=1e-6)
+    assert np.array_equal(p.cpu().numpy()[M.NET:], norm0)
+
+
+def test_targets_kernel():
+    import torch
+    stats = torch.from_numpy(np.array([[0, 1, 2], [10, 0, 0], [12345678901, 5, 5]], dtype=np.int64)).cuda()
+    t = dm.mlp_targets(stats).cpu().numpy()
+    assert np.allclose(t, np.log1p([0, 10, 12345678901]).astype(np.float32), rtol=1e-6)
+
+
+def test_training_lowers_loss_and_learned_counts_are_exact():
+    import torch
+    g = gg.chung_lu(6000, 30000, 2.2, 300.0, 21)[0]
+    h = dm.load_graph(g)
+    stats = torch.zeros((g.n, 3), dtype=torch.int64, device="cuda")
+    ref = dm.count_motifs(h, 4, root_stats=stats)
+    T = dm.mlp_targets(stats)
+    F = dm.features(h)
+    p = dm.mlp_new(0)
+    dm.mlp_fit_normalizer(p, F)
+    hist = dm.mlp_train(p, F, T, epochs=40, batch=512, lr=3e-3, seed=1)
+    assert np.all(np.isfinite(hist))
+    assert hist[-1] < 0.5 * hist[0], hist
+    pred = dm.mlp_forward(p, F).cpu().numpy()
+    tgt = T.cpu().numpy()
+    assert np.corrcoef(pred, tgt)[0, 1] > 0.8
+    # learned ordering: identical counts, cliques and motifs
+    assert np.array_equal(dm.count_motifs(h, 4, sched=dm.DM_SCHED_LEARNED, mlp=p), ref)
+    assert np.array_equal(dm.count_motifs(h, 5, sched=dm.DM_SCHED_LEARNED, mlp=p), dm.count_motifs(h, 5))
+    for k in (3, 4, 5, 6):
+        assert dm.count_cliques(h, k, sched=dm.DM_SCHED_LEARNED, mlp=p) == O.clique_count(g, k, threads=8)
+    assert dm.count_cliques(h, 5, sched=dm.DM_SCHED_LEARNED | dm.DM_NO_DONATION, mlp=p) == dm.count_cliques(h, 5)
+    with pytest.raises(dm.DMError) as e:
+        dm.count_cliques(h, 4, sched=dm.DM_SCHED_LEARNED, mlp=p, roots=np.arange(10))
+    assert e.value.status == dm.DM_E_ARG

@@ -354,18 +354,25 @@ def test_l1_vs_l2_random(seed):
 
 
 def test_motif_tree_nodes_are_connected_sets():
-    """nodes(r) = number of connected j-sets (j<k) with minimum r (brute force)."""
+    """nodes(r) = number of connected j-sets (j<k) whose lowest (degree, id)
+    vertex is r; leaves(r) the same for k-sets (brute force)."""
     g = gg.erdos_renyi(12, 24, 5)
     G = to_nx(g)
+    deg = g.degrees()
+    key = lambda v: (deg[v], v)
     k = 5
     exp_nodes = np.zeros(g.n, np.int64)
-    exp_reads = np.zeros(g.n, np.int64)
-    for j in range(1, k):
+    exp_leaves = np.zeros(g.n, np.int64)
+    for j in range(1, k + 1):
         for S in itertools.combinations(range(g.n), j):
             if nx.is_connected(G.subgraph(S)):
-                exp_nodes[min(S)] += 1
+                if j < k:
+                    exp_nodes[min(S, key=key)] += 1
+                else:
+                    exp_leaves[min(S, key=key)] += 1
     _, leaves, nodes, reads = O.motif_count(g, k, per_root=True)
     assert np.array_equal(nodes.astype(np.int64), exp_nodes)
+    assert np.array_equal(leaves.astype(np.int64), exp_leaves)
     # reads: each node adds the degree of its newest vertex, so at least the root's
     assert (reads >= 0).all()
 
