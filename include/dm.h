@@ -155,7 +155,11 @@ dm_status dm_count_motifs(dm_graph* g, int k, uint64_t* out_counts, size_t out_l
  * per graph) or DM_OP_MOTIF (ncls(k) counts per graph).  out_counts is
  * row-major [num_graphs][per-graph width].  The graphs are concatenated as a
  * disjoint union (no traversal crosses graphs), so each row equals the count
- * of the corresponding single-graph call.
+ * of the corresponding single-graph call.  The union, its orientation and the
+ * launch (clears, persistent kernel, copy-back) are built on the first call
+ * for a given list of handles and options, captured into a hipGraph, and
+ * replayed by later calls (batch calls are serialised by a library lock; the
+ * cached union of a list of handles lives until the process ends).
  * Errors: as the single-graph calls, plus DM_E_BUFSZ.
  */
 dm_status dm_batch(dm_graph* const* gs, int32_t num_graphs, int op, int k, uint64_t* out_counts,
@@ -206,6 +210,25 @@ dm_status dm_mlp_adam_step(float* params, const float* grad, float* m, float* v,
  * mean batch loss of each epoch. */
 dm_status dm_mlp_train(float* params, const int64_t* feats, const float* targets, int64_t n, int epochs,
                        int batch, float lr, uint64_t seed, float* loss_history, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Autotuning of the scheduling knobs (never changes a count).  The load
+ * balancer's threshold was picked by a sensitivity analysis in the paper
+ * (Section V-A2); here a coordinate search times one launch per candidate of
+ * roots per queue grab (1..128), donation threshold (idle-wave fraction 0 ..
+ * 0.4) and resident waves per CU, on the given graph (num_graphs == 1) or batch,
+ * and remembers the best setting per (op, k).  Later calls with
+ * DM_SCHED_AUTOTUNE use it for every knob they leave at 0.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    uint32_t chunk;
+    float rebalance;
+    uint32_t waves_per_cu;  /* 0 = occupancy maximum */
+    float ms;               /* best measured launch time */
+} dm_tuning;
+
+dm_status dm_autotune(dm_graph* const* gs, int32_t num_graphs, int op, int k, const dm_options* opt,
+                      dm_tuning* out);
 
 /* Static text for a status code. */
 const char* dm_strerror(dm_status s);

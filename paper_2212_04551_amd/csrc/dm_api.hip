@@ -492,13 +492,29 @@ int* ctrl_flags(dm_graph* g) { return reinterpret_cast<int*>(g->ctrl.as<char>() 
 
 namespace {
 
-// Common tail: copy counters and flags, synchronise, map flags to a status.
-dm_status finish(dm_graph* g, hipStream_t s, uint64_t* host_out, size_t count) {
-  int flags[2] = {0, 0};
-  hipError_t e = hipMemcpyAsync(host_out, g->out.p, sizeof(uint64_t) * count, hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(flags, ctrl_flags(g), sizeof flags, hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (e != hipSuccess) return hip_fail(e, "kernel / copy-back");
+// One counting launch, fully prepared: every buffer allocated, the root queue
+// built.  enqueue() only issues the clears, the kernel and the copy-back, so a
+// prepared launch can be timed repeatedly (autotuner) or captured once into a
+// hipGraph and replayed (batches).
+struct Prepared {
+  bool clique = true;
+  CliqueArgs ca;
+  MotifArgs ma;
+  int grid = 0;
+  bool rows_lds = true;
+  size_t lds = 0;
+  int64_t nq = 0;
+  size_t out_count = 0;
+  unsigned long long bias = 0;
+  unsigned long long* out_dev = nullptr;
+  unsigned long long* ctrl = nullptr;
+  int64_t ctrl_words = 0;
+  unsigned long long* stats = nullptr;
+  int64_t stats_words = 0;
+  int* flags_dev = nullptr;
+};
+
+dm_status check_flags(const int* flags) {
   if (flags[1]) {
     char buf[96];
     std::snprintf(buf, sizeof buf, "internal capacity check failed (0x%x)", flags[1]);
@@ -506,6 +522,28 @@ dm_status finish(dm_graph* g, hipStream_t s, uint64_t* host_out, size_t count) {
   }
   if (flags[0]) return fail(DM_E_OVERFLOW, "a uint64 counter wrapped");
   return DM_OK;
+}
+
+// Clears (fill kernels only: the sequence may be captured into a graph),
+// kernel, copy of counters and flags to host memory.
+hipError_t enqueue(const Prepared& P, hipStream_t s, uint64_t* host_out, int* host_flags) {
+  hipError_t e = launch_fill_u64(P.ctrl, P.ctrl_words, 0ull, s);
+  if (e == hipSuccess) e = launch_fill_u64(P.out_dev, static_cast<int64_t>(P.out_count), P.bias, s);
+  if (e == hipSuccess && P.stats) e = launch_fill_u64(P.stats, P.stats_words, 0ull, s);
+  if (e == hipSuccess && P.nq > 0)
+    e = P.clique ? launch_clique(P.ca, P.grid, P.rows_lds, P.lds, s) : launch_motif(P.ma, P.grid, P.lds, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(host_out, P.out_dev, sizeof(uint64_t) * P.out_count, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(host_flags, P.flags_dev, 2 * sizeof(int), hipMemcpyDeviceToHost, s);
+  return e;
+}
+
+dm_status run_prepared(const Prepared& P, hipStream_t s, uint64_t* host_out) {
+  int flags[2] = {0, 0};
+  hipError_t e = enqueue(P, s, host_out, flags);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "kernel / copy-back");
+  return check_flags(flags);
 }
 
 // queue of explicit roots (original ids), optionally mapped into rank space
@@ -556,8 +594,47 @@ dm_status learned_queue(dm_graph* g, const Opt& o, int grid, hipStream_t s, int6
   return DM_OK;
 }
 
-dm_status clique_run(dm_graph* g, int k, const Opt& o, hipStream_t s, const int32_t* root_graph, int ngraphs,
-                     uint64_t* host_out) {
+// Root queue shared by both kernels (roots in rank space): explicit list,
+// learned LPT order, or all ranks in order.  qstat maps entries to root_stats
+// rows (original vertex id, or position in the explicit list).
+dm_status build_queue(dm_graph* g, const Opt& o, int grid, hipStream_t s, Sched* S) {
+  S->nq = g->n;
+  S->qroot = nullptr;
+  S->qstat = g->order.as<int32_t>();
+  if (o.roots) {
+    dm_status st = upload_roots(g, o, true, s);
+    if (st != DM_OK) return st;
+    S->nq = o.num_roots;
+    S->qroot = g->qroot.as<int32_t>();
+    S->qstat = nullptr;
+  } else if (o.sched & DM_SCHED_LEARNED) {
+    int64_t nchunks = 0;
+    dm_status st = learned_queue(g, o, grid, s, &nchunks);
+    if (st != DM_OK) return st;
+    HIP_OR_RETURN(g->qroot.ensure(sizeof(int32_t) * static_cast<size_t>(g->n > 0 ? g->n : 1)), "workspace");
+    HIP_OR_RETURN(launch_gather_i32(g->rank.as<int32_t>(), g->lorder.as<int32_t>(), g->qroot.as<int32_t>(), g->n, s),
+                  "learned: rank map");
+    S->qroot = g->qroot.as<int32_t>();
+    S->qstat = g->lorder.as<int32_t>();
+    S->qbounds = g->qbounds.as<int64_t>();
+    S->nchunks = nchunks;
+  }
+  return DM_OK;
+}
+
+void common_prepare(dm_graph* g, const Opt& o, Prepared* P, size_t out_count) {
+  P->out_count = out_count;
+  P->bias = o.bias;
+  P->out_dev = g->out.as<unsigned long long>();
+  P->ctrl = g->ctrl.as<unsigned long long>();
+  P->ctrl_words = static_cast<int64_t>(ctrl_bytes() / 8);
+  P->stats = reinterpret_cast<unsigned long long*>(o.root_stats);
+  P->stats_words = o.root_stats ? 3 * (o.roots ? o.num_roots : g->n) : 0;
+  P->flags_dev = ctrl_flags(g);
+}
+
+dm_status prepare_clique(dm_graph* g, int k, const Opt& o, hipStream_t s, const int32_t* root_graph, int ngraphs,
+                         Prepared* P) {
   dm_status st = ensure_dag(g, s);
   if (st != DM_OK) return st;
   const int dmax = g->ddmax > 0 ? g->ddmax : 1;
@@ -574,38 +651,14 @@ dm_status clique_run(dm_graph* g, int k, const Opt& o, hipStream_t s, const int3
   if (per_cu < 1) per_cu = 1;
   if (o.waves_per_cu && static_cast<int>(o.waves_per_cu) < per_cu) per_cu = static_cast<int>(o.waves_per_cu);
   const int grid = per_cu * cu_count();
-  // queue
-  int64_t nq = g->n;
-  const int32_t* qroot = nullptr;
-  const int32_t* qstat = g->order.as<int32_t>();
-  int64_t nchunks = 0;
-  const bool learned = (o.sched & DM_SCHED_LEARNED) && !o.roots;
-  if (o.roots) {
-    st = upload_roots(g, o, true, s);
-    if (st != DM_OK) return st;
-    nq = o.num_roots;
-    qroot = g->qroot.as<int32_t>();
-    qstat = nullptr;
-  } else if (learned) {
-    st = learned_queue(g, o, grid, s, &nchunks);
-    if (st != DM_OK) return st;
-    HIP_OR_RETURN(g->qroot.ensure(sizeof(int32_t) * static_cast<size_t>(g->n > 0 ? g->n : 1)), "workspace");
-    HIP_OR_RETURN(launch_gather_i32(g->rank.as<int32_t>(), g->lorder.as<int32_t>(), g->qroot.as<int32_t>(), g->n, s),
-                  "learned: rank map");
-    qroot = g->qroot.as<int32_t>();
-    qstat = g->lorder.as<int32_t>();
-  }
   HIP_OR_RETURN(g->ctrl.ensure(ctrl_bytes()), "workspace");
   HIP_OR_RETURN(g->out.ensure(sizeof(uint64_t) * ngraphs), "workspace");
   if (!rows_lds) HIP_OR_RETURN(g->rows.ensure(sizeof(uint64_t) * static_cast<size_t>(grid) * W * dmax), "workspace");
-  HIP_OR_RETURN(launch_fill_u64(g->ctrl.as<unsigned long long>(), static_cast<int64_t>(ctrl_bytes() / 8), 0ull, s),
-                "clear");
-  HIP_OR_RETURN(launch_fill_u64(g->out.as<unsigned long long>(), ngraphs, o.bias, s), "clear");
-  if (o.root_stats)
-    HIP_OR_RETURN(launch_fill_u64(reinterpret_cast<unsigned long long*>(o.root_stats), 3 * (o.roots ? o.num_roots : g->n),
-                                  0ull, s),
-                  "clear");
-  CliqueArgs A{};
+  Sched S = make_sched(g, o, grid, g->n, nullptr, nullptr);
+  st = build_queue(g, o, grid, s, &S);
+  if (st != DM_OK) return st;
+  std::memset(&P->ca, 0, sizeof(P->ca));
+  CliqueArgs& A = P->ca;
   A.rp = g->drp.as<int64_t>();
   A.col = g->dcol.as<int32_t>();
   A.n = g->n;
@@ -620,24 +673,23 @@ dm_status clique_run(dm_graph* g, int k, const Opt& o, hipStream_t s, const int3
   A.wave_stats_len = static_cast<int>(o.wave_stats_len);
   A.rows_global = rows_lds ? nullptr : g->rows.as<unsigned long long>();
   A.prune = o.root_stats ? 0 : 1;
-  A.S = make_sched(g, o, grid, nq, qroot, qstat);
-  if (learned) {
-    A.S.qbounds = g->qbounds.as<int64_t>();
-    A.S.nchunks = nchunks;
-  }
-  if (nq > 0) HIP_OR_RETURN(launch_clique(A, grid, rows_lds, lds, s), "clique kernel launch");
-  return finish(g, s, host_out, static_cast<size_t>(ngraphs));
+  A.S = S;
+  P->clique = true;
+  P->grid = grid;
+  P->rows_lds = rows_lds;
+  P->lds = lds;
+  P->nq = S.nq;
+  common_prepare(g, o, P, static_cast<size_t>(ngraphs));
+  return DM_OK;
 }
 
-dm_status motif_run(dm_graph* g, int k, const Opt& o, hipStream_t s, const int32_t* root_graph, int ngraphs,
-                    uint64_t* host_out) {
+dm_status prepare_motif(dm_graph* g, int k, const Opt& o, hipStream_t s, const int32_t* root_graph, int ngraphs,
+                        Prepared* P) {
   const ClassTables* T = tables(k);
   uint8_t* dtab = nullptr;
   HIP_OR_RETURN(device_table(k, &dtab), "class table upload");
-  {
-    dm_status st = ensure_ranked(g, s);
-    if (st != DM_OK) return st;
-  }
+  dm_status st = ensure_ranked(g, s);
+  if (st != DM_OK) return st;
   const int dmax = g->dmax > 0 ? g->dmax : 1;
   const size_t lds = motif_lds_bytes(k, T->ncls);
   int per_cu = 0;
@@ -646,47 +698,22 @@ dm_status motif_run(dm_graph* g, int k, const Opt& o, hipStream_t s, const int32
   if (per_cu > 16) per_cu = 16;  // the extension stacks live in global memory; bound the footprint
   if (o.waves_per_cu && static_cast<int>(o.waves_per_cu) < per_cu) per_cu = static_cast<int>(o.waves_per_cu);
   const int grid = per_cu * cu_count();
-  MotifArgs A{};
+  std::memset(&P->ma, 0, sizeof(P->ma));
+  MotifArgs& A = P->ma;
   int64_t cap_total = 0;
   for (int s2 = 1; s2 <= k - 2 && s2 < 8; ++s2) {
     A.level_off[s2] = cap_total;
     A.level_cap[s2] = static_cast<int64_t>(s2) * dmax;
     cap_total += A.level_cap[s2];
   }
-  // queue in rank space; root_stats rows by original vertex id (or list position)
-  int64_t nq = g->n;
-  const int32_t* qroot = nullptr;
-  const int32_t* qstat = g->order.as<int32_t>();
-  int64_t nchunks = 0;
-  const bool learned = (o.sched & DM_SCHED_LEARNED) && !o.roots;
-  if (o.roots) {
-    dm_status st = upload_roots(g, o, true, s);
-    if (st != DM_OK) return st;
-    nq = o.num_roots;
-    qroot = g->qroot.as<int32_t>();
-    qstat = nullptr;
-  } else if (learned) {
-    dm_status st = learned_queue(g, o, grid, s, &nchunks);
-    if (st != DM_OK) return st;
-    HIP_OR_RETURN(g->qroot.ensure(sizeof(int32_t) * static_cast<size_t>(g->n > 0 ? g->n : 1)), "workspace");
-    HIP_OR_RETURN(launch_gather_i32(g->rank.as<int32_t>(), g->lorder.as<int32_t>(), g->qroot.as<int32_t>(), g->n, s),
-                  "learned: rank map");
-    qroot = g->qroot.as<int32_t>();
-    qstat = g->lorder.as<int32_t>();
-  }
   HIP_OR_RETURN(g->ctrl.ensure(ctrl_bytes()), "workspace");
   HIP_OR_RETURN(g->out.ensure(sizeof(uint64_t) * static_cast<size_t>(ngraphs) * T->ncls), "workspace");
   HIP_OR_RETURN(g->ext_vert.ensure(sizeof(int32_t) * static_cast<size_t>(grid) * cap_total), "workspace");
   HIP_OR_RETURN(g->ext_mask.ensure(static_cast<size_t>(grid) * cap_total), "workspace");
   HIP_OR_RETURN(g->newbuf.ensure(sizeof(int32_t) * static_cast<size_t>(grid) * dmax), "workspace");
-  HIP_OR_RETURN(launch_fill_u64(g->ctrl.as<unsigned long long>(), static_cast<int64_t>(ctrl_bytes() / 8), 0ull, s),
-                "clear");
-  HIP_OR_RETURN(launch_fill_u64(g->out.as<unsigned long long>(), static_cast<int64_t>(ngraphs) * T->ncls, o.bias, s),
-                "clear");
-  if (o.root_stats)
-    HIP_OR_RETURN(launch_fill_u64(reinterpret_cast<unsigned long long*>(o.root_stats), 3 * (o.roots ? o.num_roots : g->n),
-                                  0ull, s),
-                  "clear");
+  Sched S = make_sched(g, o, grid, g->n, nullptr, nullptr);
+  st = build_queue(g, o, grid, s, &S);
+  if (st != DM_OK) return st;
   A.rp = g->urp.as<int64_t>();
   A.col = g->ucol.as<int32_t>();
   A.n = g->n;
@@ -704,13 +731,122 @@ dm_status motif_run(dm_graph* g, int k, const Opt& o, hipStream_t s, const int32
   A.ext_mask = g->ext_mask.as<uint8_t>();
   A.new_buf = g->newbuf.as<int32_t>();
   A.wave_ext_cap = cap_total;
-  A.S = make_sched(g, o, grid, nq, qroot, qstat);
-  if (learned) {
-    A.S.qbounds = g->qbounds.as<int64_t>();
-    A.S.nchunks = nchunks;
+  A.S = S;
+  P->clique = false;
+  P->grid = grid;
+  P->lds = lds;
+  P->nq = S.nq;
+  common_prepare(g, o, P, static_cast<size_t>(ngraphs) * T->ncls);
+  return DM_OK;
+}
+
+dm_status prepare(dm_graph* g, int op, int k, const Opt& o, hipStream_t s, const int32_t* root_graph, int ngraphs,
+                  Prepared* P) {
+  return op == DM_OP_CLIQUE ? prepare_clique(g, k, o, s, root_graph, ngraphs, P)
+                            : prepare_motif(g, k, o, s, root_graph, ngraphs, P);
+}
+
+// ---------------------------------------------------------------- autotuning
+//
+// Coordinate search over the scheduling knobs that never change a count:
+// roots per queue grab, the idle fraction that enables donation, and resident
+// waves per CU.  Each candidate is one timed launch of the prepared work.  The
+// best setting is cached per (operation, k) for DM_SCHED_AUTOTUNE callers.
+
+struct Tuning {
+  uint32_t chunk = 0;
+  float rebalance = 0.f;
+  uint32_t waves_per_cu = 0;
+  float ms = 0.f;
+};
+
+std::mutex g_tune_lock;
+std::map<std::pair<int, int>, Tuning> g_tune;
+
+void apply_tuning(int op, int k, Opt* o) {
+  if (!(o->sched & DM_SCHED_AUTOTUNE)) return;
+  std::lock_guard<std::mutex> lk(g_tune_lock);
+  auto it = g_tune.find(std::make_pair(op, k));
+  if (it == g_tune.end()) return;
+  if (!o->chunk) o->chunk = it->second.chunk;
+  if (o->rebalance <= 0.f) o->rebalance = it->second.rebalance;
+  if (!o->waves_per_cu) o->waves_per_cu = it->second.waves_per_cu;
+}
+
+dm_status time_launch(dm_graph* g, int op, int k, const Opt& o, hipStream_t s, const int32_t* root_graph, int ngraphs,
+                      float* ms) {
+  Prepared P;
+  dm_status st = prepare(g, op, k, o, s, root_graph, ngraphs, &P);
+  if (st != DM_OK) return st;
+  std::vector<uint64_t> out(P.out_count);
+  int flags[2];
+  hipEvent_t a, b;
+  HIP_OR_RETURN(hipEventCreate(&a), "tune: event");
+  HIP_OR_RETURN(hipEventCreate(&b), "tune: event");
+  hipError_t e = hipEventRecord(a, s);
+  if (e == hipSuccess) e = enqueue(P, s, out.data(), flags);
+  if (e == hipSuccess) e = hipEventRecord(b, s);
+  if (e == hipSuccess) e = hipEventSynchronize(b);
+  if (e == hipSuccess) e = hipEventElapsedTime(ms, a, b);
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (e != hipSuccess) return hip_fail(e, "tune: launch");
+  return check_flags(flags);
+}
+
+dm_status autotune(dm_graph* g, int op, int k, const Opt& base, hipStream_t s, const int32_t* root_graph, int ngraphs,
+                   Tuning* best) {
+  Opt o = base;
+  o.sched &= ~static_cast<uint32_t>(DM_SCHED_AUTOTUNE | DM_RECORD_ROOTS);
+  o.root_stats = nullptr;
+  o.wave_stats = nullptr;
+  o.chunk = 1;
+  o.rebalance = 0.f;
+  o.waves_per_cu = 0;
+  float ms = 0.f;
+  dm_status st = time_launch(g, op, k, o, s, root_graph, ngraphs, &ms);  // warm-up (allocations, caches)
+  if (st != DM_OK) return st;
+  auto measure = [&](const Opt& c, float* out_ms) -> dm_status {
+    float m1 = 0.f, m2 = 0.f;
+    dm_status r = time_launch(g, op, k, c, s, root_graph, ngraphs, &m1);
+    if (r == DM_OK) r = time_launch(g, op, k, c, s, root_graph, ngraphs, &m2);
+    *out_ms = std::min(m1, m2);
+    return r;
+  };
+  float best_ms = 0.f;
+  st = measure(o, &best_ms);
+  if (st != DM_OK) return st;
+  for (uint32_t c : {2u, 4u, 8u, 16u, 32u, 64u, 128u}) {
+    Opt t = o;
+    t.chunk = c;
+    float m = 0.f;
+    st = measure(t, &m);
+    if (st != DM_OK) return st;
+    if (m < best_ms) { best_ms = m; o.chunk = c; }
   }
-  if (nq > 0) HIP_OR_RETURN(launch_motif(A, grid, lds, s), "motif kernel launch");
-  return finish(g, s, host_out, static_cast<size_t>(ngraphs) * T->ncls);
+  for (float r : {0.02f, 0.05f, 0.1f, 0.2f, 0.4f}) {
+    Opt t = o;
+    t.rebalance = r;
+    float m = 0.f;
+    st = measure(t, &m);
+    if (st != DM_OK) return st;
+    if (m < best_ms) { best_ms = m; o.rebalance = r; }
+  }
+  for (uint32_t w : {1u, 2u, 4u, 8u}) {
+    Opt t = o;
+    t.waves_per_cu = w;
+    float m = 0.f;
+    st = measure(t, &m);
+    if (st != DM_OK) return st;
+    if (m < best_ms) { best_ms = m; o.waves_per_cu = w; }
+  }
+  best->chunk = o.chunk;
+  best->rebalance = o.rebalance;
+  best->waves_per_cu = o.waves_per_cu;
+  best->ms = best_ms;
+  std::lock_guard<std::mutex> lk(g_tune_lock);
+  g_tune[std::make_pair(op, k)] = *best;
+  return DM_OK;
 }
 
 }  // namespace
@@ -723,8 +859,11 @@ extern "C" dm_status dm_count_cliques(dm_graph* g, int k, uint64_t* out_count, c
   if (st != DM_OK) return st;
   if ((o.sched & DM_SCHED_LEARNED) && !o.mlp) return fail(DM_E_MODEL, "DM_SCHED_LEARNED needs mlp parameters");
   hipStream_t s = pick_stream(g, o.stream);
+  apply_tuning(DM_OP_CLIQUE, k, &o);
+  Prepared P;
+  st = prepare(g, DM_OP_CLIQUE, k, o, s, nullptr, 1, &P);
   uint64_t c = 0;
-  st = clique_run(g, k, o, s, nullptr, 1, &c);
+  if (st == DM_OK) st = run_prepared(P, s, &c);
   if (st == DM_OK) *out_count = c;
   return st;
 }
@@ -739,8 +878,11 @@ extern "C" dm_status dm_count_motifs(dm_graph* g, int k, uint64_t* out_counts, s
   if (st != DM_OK) return st;
   if ((o.sched & DM_SCHED_LEARNED) && !o.mlp) return fail(DM_E_MODEL, "DM_SCHED_LEARNED needs mlp parameters");
   hipStream_t s = pick_stream(g, o.stream);
+  apply_tuning(DM_OP_MOTIF, k, &o);
   std::vector<uint64_t> tmp(T->ncls);
-  st = motif_run(g, k, o, s, nullptr, 1, tmp.data());
+  Prepared P;
+  st = prepare(g, DM_OP_MOTIF, k, o, s, nullptr, 1, &P);
+  if (st == DM_OK) st = run_prepared(P, s, tmp.data());
   if (st == DM_OK) std::memcpy(out_counts, tmp.data(), sizeof(uint64_t) * T->ncls);
   return st;
 }
@@ -752,13 +894,76 @@ namespace {
 // A batch is the disjoint union of its graphs: vertex ids of graph i are
 // shifted by the vertex count of graphs 0..i-1, so no traversal crosses
 // graphs and per-graph counters can be kept by mapping each root to its graph.
+// A captured launch: the clears, the persistent kernel and the copy-back of
+// one prepared batch, replayed with hipGraphLaunch.  It is keyed by the exact
+// bytes of the prepared launch, so it is only replayed while every buffer it
+// names is the one currently allocated.
+struct CapturedLaunch {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  uint64_t* host_out = nullptr;  // pinned
+  int* host_flags = nullptr;     // pinned
+  size_t out_count = 0;
+  ~CapturedLaunch() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (host_out) (void)hipHostFree(host_out);
+    if (host_flags) (void)hipHostFree(host_flags);
+  }
+};
+
 struct BatchCache {
   dm_graph* uni = nullptr;
   Buf gov;  // graph index of every union vertex
   Buf gor;  // graph index of every union vertex in rank order
   bool gor_ready = false;
-  ~BatchCache() { dm_free(uni); }
+  hipStream_t stream = nullptr;  // capture stream (never the legacy default stream)
+  std::map<std::string, CapturedLaunch*> graphs;
+  ~BatchCache() {
+    for (auto& kv : graphs) delete kv.second;
+    if (stream) (void)hipStreamDestroy(stream);
+    dm_free(uni);
+  }
 };
+
+std::string launch_key(const Prepared& P) {
+  std::string key(reinterpret_cast<const char*>(&P.clique), sizeof(P.clique));
+  if (P.clique) key.append(reinterpret_cast<const char*>(&P.ca), sizeof(P.ca));
+  else key.append(reinterpret_cast<const char*>(&P.ma), sizeof(P.ma));
+  const int64_t tail[] = {P.grid, P.rows_lds, static_cast<int64_t>(P.lds), P.nq, static_cast<int64_t>(P.out_count),
+                          static_cast<int64_t>(P.bias), reinterpret_cast<int64_t>(P.stats), P.stats_words};
+  key.append(reinterpret_cast<const char*>(tail), sizeof(tail));
+  return key;
+}
+
+dm_status run_captured(BatchCache* B, const Prepared& P, uint64_t* out) {
+  const std::string key = launch_key(P);
+  CapturedLaunch*& C = B->graphs[key];
+  if (!C) {
+    C = new CapturedLaunch();
+    C->out_count = P.out_count;
+    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&C->host_out), sizeof(uint64_t) * (P.out_count ? P.out_count : 1));
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&C->host_flags), 2 * sizeof(int));
+    if (e == hipSuccess) e = hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      hipError_t e2 = enqueue(P, B->stream, C->host_out, C->host_flags);
+      e = hipStreamEndCapture(B->stream, &C->graph);
+      if (e2 != hipSuccess) e = e2;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&C->exec, C->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      delete C;
+      B->graphs.erase(key);
+      return hip_fail(e, "batch: graph capture");
+    }
+  }
+  hipError_t e = hipGraphLaunch(C->exec, B->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(B->stream);
+  if (e != hipSuccess) return hip_fail(e, "batch: graph launch");
+  dm_status st = check_flags(C->host_flags);
+  if (st == DM_OK) std::memcpy(out, C->host_out, sizeof(uint64_t) * C->out_count);
+  return st;
+}
 
 std::mutex g_batch_lock;
 std::map<std::vector<uint64_t>, BatchCache*> g_batches;
@@ -798,22 +1003,37 @@ dm_status build_union(dm_graph* const* gs, int32_t num, hipStream_t s, BatchCach
   return DM_OK;
 }
 
-dm_status batch_run(dm_graph* const* gs, int32_t num, int op, int k, int width, const Opt& o, uint64_t* out) {
+BatchCache* batch_cache(dm_graph* const* gs, int32_t num, hipStream_t caller, dm_status* st) {
   std::vector<uint64_t> key(static_cast<size_t>(num));
   for (int32_t i = 0; i < num; ++i) key[i] = gs[i]->uid;
-  std::lock_guard<std::mutex> lk(g_batch_lock);
   BatchCache*& B = g_batches[key];
-  hipStream_t s = o.stream ? o.stream : pick_stream(gs[0], nullptr);
+  *st = DM_OK;
   if (!B) {
     B = new BatchCache();
-    dm_status st = build_union(gs, num, s, B);
-    if (st != DM_OK) {
+    hipError_t e = hipStreamCreateWithFlags(&B->stream, hipStreamNonBlocking);
+    if (e == hipSuccess && caller) e = hipStreamSynchronize(caller);
+    *st = e == hipSuccess ? build_union(gs, num, B->stream, B) : hip_fail(e, "batch: stream");
+    if (*st != DM_OK) {
       delete B;
       B = nullptr;
       g_batches.erase(key);
-      return st;
+      return nullptr;
     }
   }
+  return B;
+}
+
+dm_status batch_run(dm_graph* const* gs, int32_t num, int op, int k, int width, const Opt& o_in, uint64_t* out) {
+  std::lock_guard<std::mutex> lk(g_batch_lock);
+  dm_status st0;
+  // work on the batch's own stream (captures cannot use the legacy default
+  // stream); the caller's stream is drained first
+  if (o_in.stream) HIP_OR_RETURN(hipStreamSynchronize(o_in.stream), "batch: caller stream");
+  BatchCache* B = batch_cache(gs, num, o_in.stream, &st0);
+  if (!B) return st0;
+  Opt o = o_in;
+  apply_tuning(op, k, &o);
+  hipStream_t s = B->stream;
   std::vector<uint64_t> tmp(static_cast<size_t>(num) * width);
   // both kernels take roots in rank space: graph index of every rank
   dm_status st = ensure_dag(B->uni, s);
@@ -825,12 +1045,33 @@ dm_status batch_run(dm_graph* const* gs, int32_t num, int op, int k, int width, 
                   "batch: rank map");
     B->gor_ready = true;
   }
-  if (op == DM_OP_CLIQUE)
-    st = clique_run(B->uni, k, o, s, B->gor.as<int32_t>(), num, tmp.data());
-  else
-    st = motif_run(B->uni, k, o, s, B->gor.as<int32_t>(), num, tmp.data());
+  Prepared P;
+  st = prepare(B->uni, op, k, o, s, B->gor.as<int32_t>(), num, &P);
+  if (st != DM_OK) return st;
+  // one persistent launch per batch, captured once and replayed; per-root
+  // records and wave statistics take the direct path
+  if (!o.root_stats && !o.wave_stats) return run_captured(B, P, out);
+  st = run_prepared(P, s, tmp.data());
   if (st == DM_OK) std::memcpy(out, tmp.data(), sizeof(uint64_t) * tmp.size());
   return st;
+}
+
+dm_status batch_tune(dm_graph* const* gs, int32_t num, int op, int k, const Opt& o, Tuning* best) {
+  std::lock_guard<std::mutex> lk(g_batch_lock);
+  dm_status st0;
+  if (o.stream) HIP_OR_RETURN(hipStreamSynchronize(o.stream), "tune: caller stream");
+  BatchCache* B = batch_cache(gs, num, o.stream, &st0);
+  if (!B) return st0;
+  dm_status st = ensure_dag(B->uni, B->stream);
+  if (st != DM_OK) return st;
+  if (!B->gor_ready) {
+    HIP_OR_RETURN(B->gor.ensure(sizeof(int32_t) * (B->uni->n > 0 ? B->uni->n : 1)), "batch: allocate");
+    HIP_OR_RETURN(launch_gather_i32(B->gov.as<int32_t>(), B->uni->order.as<int32_t>(), B->gor.as<int32_t>(),
+                                    B->uni->n, B->stream),
+                  "batch: rank map");
+    B->gor_ready = true;
+  }
+  return autotune(B->uni, op, k, o, B->stream, B->gor.as<int32_t>(), num, best);
 }
 
 }  // namespace
@@ -971,5 +1212,34 @@ extern "C" dm_status dm_mlp_train(float* params, const int64_t* feats, const flo
     }
   }
   HIP_OR_RETURN(hipStreamSynchronize(s), "train");
+  return DM_OK;
+}
+
+// ====================================================================== autotuning ABI
+
+extern "C" dm_status dm_autotune(dm_graph* const* gs, int32_t num_graphs, int op, int k, const dm_options* opt,
+                                 dm_tuning* out) {
+  if (!gs || num_graphs <= 0 || !out) return fail(DM_E_ARG, "null graphs / output or num_graphs <= 0");
+  if (op != DM_OP_CLIQUE && op != DM_OP_MOTIF) return fail(DM_E_ARG, "unknown op");
+  if (op == DM_OP_CLIQUE ? (k < 1 || k > kMaxK) : !tables(k)) return fail(DM_E_K, "k out of range");
+  for (int32_t i = 0; i < num_graphs; ++i)
+    if (!gs[i]) return fail(DM_E_ARG, "null graph");
+  Opt o;
+  dm_status st = read_opt(opt, &o);
+  if (st != DM_OK) return st;
+  if (o.roots) return fail(DM_E_ARG, "tuning runs over every root");
+  if ((o.sched & DM_SCHED_LEARNED) && !o.mlp) return fail(DM_E_MODEL, "DM_SCHED_LEARNED needs mlp parameters");
+  Tuning t;
+  if (num_graphs == 1) {
+    hipStream_t s = pick_stream(gs[0], o.stream);
+    st = autotune(gs[0], op, k, o, s, nullptr, 1, &t);
+  } else {
+    st = batch_tune(gs, num_graphs, op, k, o, &t);
+  }
+  if (st != DM_OK) return st;
+  out->chunk = t.chunk;
+  out->rebalance = t.rebalance;
+  out->waves_per_cu = t.waves_per_cu;
+  out->ms = t.ms;
   return DM_OK;
 }

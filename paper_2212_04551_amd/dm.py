@@ -31,8 +31,13 @@ EXPORTS = [
     "dm_load_csr", "dm_free", "dm_graph_info", "dm_count_cliques", "dm_motif_num_classes",
     "dm_motif_class_mask", "dm_motif_class_table", "dm_count_motifs", "dm_batch", "dm_strerror",
     "dm_last_error", "dm_features", "dm_mlp_init", "dm_mlp_fit_normalizer", "dm_mlp_forward", "dm_mlp_targets",
-    "dm_mlp_loss_grad", "dm_mlp_adam_step", "dm_mlp_train",
+    "dm_mlp_loss_grad", "dm_mlp_adam_step", "dm_mlp_train", "dm_autotune",
 ]
+
+
+class dm_tuning(ctypes.Structure):
+    _fields_ = [("chunk", ctypes.c_uint32), ("rebalance", ctypes.c_float), ("waves_per_cu", ctypes.c_uint32),
+                ("ms", ctypes.c_float)]
 
 
 class dm_options(ctypes.Structure):
@@ -103,6 +108,8 @@ def lib():
         ("dm_mlp_loss_grad", [vp, vp, vp, i64, vp, ctypes.POINTER(ctypes.c_float), vp]),
         ("dm_mlp_adam_step", [vp, vp, vp, vp, i64, ctypes.c_float, vp]),
         ("dm_mlp_train", [vp, vp, vp, i64, ctypes.c_int, ctypes.c_int, ctypes.c_float, ctypes.c_uint64, vp, vp]),
+        ("dm_autotune", [ctypes.POINTER(vp), i32, ctypes.c_int, ctypes.c_int, ctypes.POINTER(dm_options),
+                         ctypes.POINTER(dm_tuning)]),
     ):
         f = getattr(L, name)
         f.restype = ctypes.c_int
@@ -267,6 +274,16 @@ def batch(graphs: Sequence[DMGraph], op: int, k: int, **opt) -> np.ndarray:
     _check(lib().dm_batch(arr, len(graphs), op, k, out.ctypes.data, out.size, ctypes.byref(o)))
     del keep
     return out
+
+
+def autotune(graphs: Sequence[DMGraph], op: int, k: int, **opt) -> dict:
+    """dm_autotune over one graph or a batch; returns the chosen knobs."""
+    arr = (ctypes.c_void_p * len(graphs))(*[g.handle.value for g in graphs])
+    o, keep = make_options(**opt)
+    t = dm_tuning()
+    _check(lib().dm_autotune(arr, len(graphs), op, k, ctypes.byref(o), ctypes.byref(t)))
+    del keep
+    return {"chunk": t.chunk, "rebalance": float(t.rebalance), "waves_per_cu": t.waves_per_cu, "ms": float(t.ms)}
 
 
 # ------------------------------------------------------------------ learned ordering

@@ -308,3 +308,35 @@ def test_overflow_detected():
     with pytest.raises(dm.DMError) as e:
         dm.count_motifs(h, 4, counter_bias=2**64 - int(m))
     assert e.value.status == dm.DM_E_OVERFLOW
+
+
+# ------------------------------------------------------------------ graph replay and autotuning
+
+def test_batch_graph_replays_match_eager():
+    """The batch launch is captured once and replayed; eager single-graph calls
+    run between replays, and every replay equals the eager per-graph counts."""
+    graphs = [gg.batch_graph(i, nhi=400) for i in range(40)]
+    hs = [dm.load_graph(g) for g in graphs]
+    eager5 = np.stack([dm.count_motifs(h, 5) for h in hs])
+    eager4c = np.array([dm.count_cliques(h, 4) for h in hs], np.uint64)
+    for rep in range(4):
+        assert np.array_equal(dm.batch(hs, dm.DM_OP_MOTIF, 5), eager5), rep
+        assert np.array_equal(dm.batch(hs, dm.DM_OP_CLIQUE, 4)[:, 0], eager4c), rep
+        # eager work between replays
+        assert dm.count_cliques(hs[rep], 3) == O.clique_count(graphs[rep], 3)
+    assert np.array_equal(eager5[7], O.motif_count(graphs[7], 5))
+
+
+def test_autotune_picks_valid_knobs_and_keeps_counts():
+    graphs = [gg.batch_graph(i, nhi=300) for i in range(16)]
+    hs = [dm.load_graph(g) for g in graphs]
+    ref = dm.batch(hs, dm.DM_OP_MOTIF, 4)
+    t = dm.autotune(hs, dm.DM_OP_MOTIF, 4)
+    assert t["chunk"] in (1, 2, 4, 8, 16, 32, 64, 128)
+    assert 0.0 <= t["rebalance"] <= 0.4 + 1e-6 and t["waves_per_cu"] in (0, 1, 2, 4, 8) and t["ms"] > 0
+    assert np.array_equal(dm.batch(hs, dm.DM_OP_MOTIF, 4, sched=dm.DM_SCHED_AUTOTUNE), ref)
+    g = gg.chung_lu(3000, 15000, 2.2, 200.0, 4)[0]
+    h = dm.load_graph(g)
+    t1 = dm.autotune([h], dm.DM_OP_CLIQUE, 5)
+    assert t1["ms"] > 0
+    assert dm.count_cliques(h, 5, sched=dm.DM_SCHED_AUTOTUNE) == O.clique_count(g, 5, threads=8)
