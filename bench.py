@@ -73,28 +73,85 @@ def cpu_baseline(g, budget_s: float, seed: int = 0):
     }
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--copy-probe", action="store_true",
-                    help="also run one device copy of 1 GiB (counter calibration for profiles)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU design is described "
-              f"in DESIGN.md and is not implemented", file=sys.stderr)
-        sys.exit(2)
+def base_record(metric_value, ms_per_step, steps, warmup, workload, extra_config, dtype="u64"):
+    return {
+        "metric": "enumerated subgraphs/s (k-clique, k-motif), learned+batched vs plain, exact",
+        "value": metric_value,
+        "unit": "subgraphs/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic",
+        "config": dict({"workload": workload}, **extra_config),
+    }
 
+
+def timed_steps(fn, steps, warmup, label):
+    import torch
+    for w in range(warmup):
+        t = time.perf_counter()
+        fn()
+        log(f"{label} warmup {w}: {time.perf_counter() - t:.3f}s")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        r = fn()
+        log(f"{label} step {s} done")
+    torch.cuda.synchronize()
+    return r, (time.perf_counter() - t0) * 1e3 / steps
+
+
+def idle_fraction(ws):
+    w = ws.view(-1, 4).cpu().numpy().astype(np.float64)
+    w = w[w[:, 0] + w[:, 1] > 0]
+    tot = w[:, 0].sum() + w[:, 1].sum()
+    return float(w[:, 1].sum() / tot) if tot > 0 else 0.0
+
+
+def train_model(make_graph, seeds, op, k, epochs, batch=4096, lr=1e-3):
+    """Record per-root tree sizes with the plain kernel on `seeds`, train the MLP on the GPU."""
+    import torch
+    from paper_2212_04551_amd import dm
+    feats, targets = [], []
+    t0 = time.perf_counter()
+    for sd in seeds:
+        g = make_graph(sd)
+        h = dm.load_graph(g)
+        stats = torch.zeros((g.n, 3), dtype=torch.int64, device="cuda")
+        if op == "motif":
+            dm.count_motifs(h, k, root_stats=stats)
+        else:
+            dm.count_cliques(h, k, root_stats=stats)
+        feats.append(dm.features(h))
+        targets.append(dm.mlp_targets(stats))
+        log(f"recorded seed {sd}: n={g.n}")
+    t_rec = time.perf_counter() - t0
+    F = torch.cat(feats)
+    T = torch.cat(targets)
+    p = dm.mlp_new(0)
+    dm.mlp_fit_normalizer(p, F)
+    t1 = time.perf_counter()
+    hist = dm.mlp_train(p, F, T, epochs=epochs, batch=batch, lr=lr, seed=0)
+    t_train = time.perf_counter() - t1
+    pred = dm.mlp_forward(p, F).cpu().numpy()
+    corr = float(np.corrcoef(pred, T.cpu().numpy())[0, 1])
+    log(f"trained: rows={F.shape[0]} loss {hist[0]:.3f} -> {hist[-1]:.3f} corr={corr:.3f}")
+    return p, {"rows": int(F.shape[0]), "record_s": t_rec, "train_s": t_train, "epochs": epochs,
+               "loss_first": float(hist[0]), "loss_last": float(hist[-1]), "train_corr": corr}
+
+
+# ---------------------------------------------------------------- workloads
+
+def wl_cl1m_clique(args):
     import torch
     from paper_2212_04551_amd import dm
     from paper_2212_04551_amd import graphgen as gg
 
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    torch.cuda.set_device(0)
     t0 = time.perf_counter()
     g, i0 = gg.chung_lu(1_000_000, 20_000_000, 2.1, 1.0e4, args.seed)
     log(f"graph generated in {time.perf_counter() - t0:.1f}s: n={g.n} m={g.m} max_deg={int(g.degrees().max())}")
@@ -150,38 +207,201 @@ def main():
     nodes = g.m + sum(counts[j] for j in range(3, kmax))
     ops = 4.0 * nodes
     achieved = ops / (per_k_ms[kmax] / 1e3) / 1e12
-    out = {
-        "metric": "enumerated subgraphs/s (k-clique, k-motif), learned+batched vs plain, exact",
-        "value": value,
-        "unit": "subgraphs/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u64",
-        "data": "synthetic",
-        "config": {
-            "workload": "k-clique counting k=3..8, Chung-Lu n=1e6 m=2e7 gamma=2.1 wmax=1e4 seed 0, "
-                        "degree-ordered DAG, plain persistent kernel",
-            "n": g.n, "m": g.m, "k": list(KS), "counts": {str(k): int(v) for k, v in counts.items()},
-            "per_k_ms": per_k_ms, "schedule": "plain",
-        },
-        "roofline": {
-            "bound": "alu",
-            "kernel": "clique_kernel (k=8 launch)",
-            "achieved": achieved,
-            "peak": ALU_PEAK_TOPS,
-            "unit": "TOP/s",
-            "frac": achieved / ALU_PEAK_TOPS,
-            "traffic": TRAFFIC["bytes_per_launch"] if kernel_source_sha() == TRAFFIC["source_sha"] else None,
-            "work": f"4 int32 ops x {nodes} tree nodes",
-        },
+    out = base_record(value, ms_per_step, args.steps, args.warmup,
+                      "k-clique counting k=3..8, Chung-Lu n=1e6 m=2e7 gamma=2.1 wmax=1e4 seed 0, "
+                      "degree-ordered DAG, plain persistent kernel",
+                      {"n": g.n, "m": g.m, "k": list(KS), "counts": {str(k): int(v) for k, v in counts.items()},
+                       "per_k_ms": per_k_ms, "schedule": "plain"})
+    out["roofline"] = {
+        "bound": "alu",
+        "kernel": "clique_kernel (k=8 launch)",
+        "achieved": achieved,
+        "peak": ALU_PEAK_TOPS,
+        "unit": "TOP/s",
+        "frac": achieved / ALU_PEAK_TOPS,
+        "traffic": TRAFFIC["bytes_per_launch"] if kernel_source_sha() == TRAFFIC["source_sha"] else None,
+        "work": f"4 int32 ops x {nodes} tree nodes",
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, args.cpu_budget)
+    return out
+
+
+def wl_er516_motif(args):
+    import torch
+    from paper_2212_04551_amd import dm
+    from paper_2212_04551_amd import graphgen as gg
+
+    g = gg.workload_graph("er516", args.seed)
+    rp = torch.from_numpy(g.row_ptr).cuda()
+    col = torch.from_numpy(g.col).cuda()
+
+    def step():
+        h = dm.load_csr(g.n, rp, col, device=True)
+        c = dm.count_motifs(h, 4)
+        h.close()
+        return c
+
+    c, ms = timed_steps(step, max(args.steps, 20), args.warmup, "er516")
+    return base_record(int(c.sum()) / (ms / 1e3), ms, max(args.steps, 20), args.warmup,
+                       "induced 4-motif counting, G(n=516, m=1200) seed 0, plain",
+                       {"counts": [int(x) for x in c], "note": "launch-latency bound: 35k subgraphs per step"})
+
+
+def wl_cl100k_learned(args):
+    import torch
+    from paper_2212_04551_amd import dm
+    from paper_2212_04551_amd import graphgen as gg
+
+    caps = {5: 200.0, 6: 80.0}
+    results = {}
+    total_plain = total_learned = 0.0
+    subgraphs = 0
+    for k, cap in caps.items():
+        make = lambda sd, cap=cap: gg.chung_lu(100_000, 1_000_000, 2.3, cap, sd)[0]
+        model, tinfo = train_model(make, range(1, 11), "motif", k, epochs=args.epochs)
+        g = make(0)
+        rp = torch.from_numpy(g.row_ptr).cuda()
+        col = torch.from_numpy(g.col).cuda()
+        ws = torch.zeros(256 * 32 * 4, dtype=torch.int64, device="cuda")
+
+        def run(sched, mlp=None, ws=None):
+            def step():
+                h = dm.load_csr(g.n, rp, col, device=True)
+                c = dm.count_motifs(h, k, sched=sched, mlp=mlp, wave_stats=ws)
+                h.close()
+                return c
+            return step
+
+        cp, ms_plain = timed_steps(run(dm.DM_SCHED_PLAIN), args.steps, args.warmup, f"motif k={k} plain")
+        cl, ms_learned = timed_steps(run(dm.DM_SCHED_LEARNED, model), args.steps, args.warmup, f"motif k={k} learned")
+        assert np.array_equal(cp, cl), "learned ordering changed a count"
+        ws.zero_()
+        run(dm.DM_SCHED_PLAIN, ws=ws)()
+        idle_plain = idle_fraction(ws)
+        ws.zero_()
+        run(dm.DM_SCHED_LEARNED, model, ws)()
+        idle_learned = idle_fraction(ws)
+        ws.zero_()
+        run(dm.DM_SCHED_PLAIN | dm.DM_NO_DONATION, ws=ws)()
+        idle_static = idle_fraction(ws)
+        n_sub = int(cp.sum())
+        results[str(k)] = {"weight_cap": cap, "subgraphs": n_sub, "plain_ms": ms_plain, "learned_ms": ms_learned,
+                           "speedup": ms_plain / ms_learned, "idle_plain": idle_plain,
+                           "idle_learned": idle_learned, "idle_no_donation": idle_static, "training": tinfo}
+        total_plain += ms_plain
+        total_learned += ms_learned
+        subgraphs += n_sub
+    out = base_record(subgraphs / (total_learned / 1e3), total_learned, args.steps, args.warmup,
+                      "induced k-motif counting k=5 (cap 200) and k=6 (cap 80), Chung-Lu n=1e5 m=1e6 gamma=2.3 "
+                      "seed 0, learned ordering (MLP trained on seeds 1..10) vs plain",
+                      {"per_k": results, "plain_value": subgraphs / (total_plain / 1e3),
+                       "speedup_learned_vs_plain": total_plain / total_learned})
+    return out
+
+
+def wl_batch4096(args):
+    import torch
+    from paper_2212_04551_amd import dm
+    from paper_2212_04551_amd import graphgen as gg
+
+    t0 = time.perf_counter()
+    graphs = [gg.batch_graph(i) for i in range(4096)]
+    calib = [gg.batch_graph(4096 + i) for i in range(512)]
+    hs = [dm.load_graph(g) for g in graphs]
+    hc = [dm.load_graph(g) for g in calib]
+    log(f"4096 + 512 graphs generated and loaded in {time.perf_counter() - t0:.1f}s; "
+        f"n total {sum(g.n for g in graphs)}, m total {sum(g.m for g in graphs)}")
+    t1 = time.perf_counter()
+    tune = dm.autotune(hc, dm.DM_OP_MOTIF, 5)
+    t_tune = time.perf_counter() - t1
+    log(f"autotuned on 512 calibration graphs in {t_tune:.1f}s: {tune}")
+
+    def plain():
+        return np.stack([dm.count_motifs(h, 5) for h in hs])
+
+    t2 = time.perf_counter()
+    first = dm.batch(hs, dm.DM_OP_MOTIF, 5, sched=dm.DM_SCHED_AUTOTUNE)  # builds union + captures the graph
+    t_setup = time.perf_counter() - t2
+    cb, ms_batch = timed_steps(lambda: dm.batch(hs, dm.DM_OP_MOTIF, 5, sched=dm.DM_SCHED_AUTOTUNE),
+                               args.steps, args.warmup, "batch autotuned")
+    cpl, ms_plain = timed_steps(plain, 1, 0, "plain per-graph")
+    assert np.array_equal(cb, cpl) and np.array_equal(first, cb), "batch counts differ from per-graph counts"
+    cbu, ms_batch_untuned = timed_steps(lambda: dm.batch(hs, dm.DM_OP_MOTIF, 5), args.steps, args.warmup,
+                                        "batch untuned")
+    n_sub = int(cb.sum())
+    return base_record(n_sub / (ms_batch / 1e3), ms_batch, args.steps, args.warmup,
+                       "batched induced 5-motif counting over 4096 graphs (n~U{20..2000}; even: G(n,m) d~U[4,16); "
+                       "odd: BA m0~U{2..6}), one hipGraph-captured persistent launch, autotuned vs plain per-graph",
+                       {"subgraphs": n_sub, "plain_per_graph_ms": ms_plain, "batched_untuned_ms": ms_batch_untuned,
+                        "speedup_vs_plain": ms_plain / ms_batch, "tuning": tune, "tune_s": t_tune,
+                        "first_call_setup_s": t_setup})
+
+
+def wl_sbm_largek(args):
+    import torch
+    from paper_2212_04551_amd import dm
+    from paper_2212_04551_amd import graphgen as gg
+
+    make = lambda sd: gg.sbm(200, 60, 0.45, 0.0005, sd)
+    model, tinfo = train_model(make, range(1, 11), "clique", 12, epochs=args.epochs, batch=1024)
+    g = make(0)
+    h = dm.load_graph(g)
+    tune = dm.autotune([h], dm.DM_OP_CLIQUE, 12, sched=dm.DM_SCHED_LEARNED, mlp=model)
+    per = {}
+    tot_plain = tot_learned = 0.0
+    nodes_total = 0
+    for k in (10, 11, 12):
+        # tree nodes below k: every j-clique, j = 1..k-1
+        nodes = sum(dm.count_cliques(h, j) for j in range(1, k))
+        cp, msp = timed_steps(lambda: dm.count_cliques(h, k), args.steps, args.warmup, f"sbm k={k} plain")
+        cl, msl = timed_steps(lambda: dm.count_cliques(h, k, sched=dm.DM_SCHED_LEARNED | dm.DM_SCHED_AUTOTUNE,
+                                                       mlp=model), args.steps, args.warmup, f"sbm k={k} learned")
+        assert cp == cl
+        per[str(k)] = {"count": int(cp), "tree_nodes": int(nodes), "plain_ms": msp, "learned_autotuned_ms": msl}
+        tot_plain += msp
+        tot_learned += msl
+        nodes_total += nodes
+    out = base_record(nodes_total / (tot_learned / 1e3), tot_learned, args.steps, args.warmup,
+                      "k-clique counting k=10..12, SBM 200 blocks x 60, p_in 0.45, p_out 0.0005, seed 0; "
+                      "learned + autotuned vs plain; value is tree nodes/s (the counts are 0 or near 0)",
+                      {"per_k": per, "tuning": tune, "training": tinfo,
+                       "plain_value_nodes_per_s": nodes_total / (tot_plain / 1e3),
+                       "speedup_vs_plain": tot_plain / tot_learned})
+    out["unit"] = "tree nodes/s"
+    return out
+
+
+WORKLOADS = {
+    "cl1m-clique": wl_cl1m_clique,
+    "er516-motif4": wl_er516_motif,
+    "cl100k-motif-learned": wl_cl100k_learned,
+    "batch4096-motif5": wl_batch4096,
+    "sbm-clique-largek": wl_sbm_largek,
+}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--workload", default="cl1m-clique", choices=sorted(WORKLOADS))
+    ap.add_argument("--epochs", type=int, default=20, help="MLP training epochs (learned workloads)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one device copy of 1 GiB (counter calibration for profiles)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU design is described "
+              f"in DESIGN.md and is not implemented", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    out = WORKLOADS[args.workload](args)
     print(json.dumps(out), flush=True)
 
 

@@ -480,7 +480,7 @@ Sched make_sched(dm_graph* g, const Opt& o, int grid, int64_t nq, const int32_t*
   const float r = o.rebalance > 0.f ? o.rebalance : 0.0f;
   int trig = static_cast<int>(r * grid);
   S.idle_trigger = trig < 1 ? 1 : trig;
-  S.period = 8;
+  S.period = 64;
   return S;
 }
 

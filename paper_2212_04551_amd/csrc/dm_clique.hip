@@ -36,16 +36,19 @@ namespace {
 struct CliqueLds {
   uint64_t* rows;   // [W][dmax] (word-major) when in LDS
   uint64_t* stk;    // [(k+1)][W] candidate bitsets per traversal size
-  int64_t* start;   // [dmax] DAG offset of N+(nbr[i])
   int* nbr;         // [dmax] N+(root)
   int* offs;        // [dmax+1] exclusive prefix of |N+(nbr[i])|
   int* cur;         // [kMaxK+2] chosen position per depth
   int* hiv;         // [kMaxK+2] iteration end per depth
-  uint64_t* lr;     // [64] rows of a candidate set of <= 64 members, in local ids
-  int* pos;         // [64] positions (in N+(root)) of those members
+  uint64_t* lr;     // [2][128] re-indexed rows (word-major) of a set of <= 128 members
+  uint64_t* cset;   // [4] the set handed to the dense solver
+  int* pos;         // [128] positions (in N+(root)) of re-indexed members
 };
 
 __device__ __forceinline__ size_t align16(size_t x) { return (x + 15) & ~static_cast<size_t>(15); }
+
+constexpr int kLocalMax = 128;    // roots with at most this many out-neighbours use their rows in place
+constexpr int kReindexMax = 128;  // larger roots re-index candidate sets of at most this many members
 
 __device__ CliqueLds carve(unsigned char* smem, int dmax, int W, int k, bool rows_lds) {
   CliqueLds L;
@@ -55,9 +58,6 @@ __device__ CliqueLds carve(unsigned char* smem, int dmax, int W, int k, bool row
   off = align16(off);
   L.stk = reinterpret_cast<uint64_t*>(smem + off);
   off += static_cast<size_t>(k + 1) * W * 8;
-  off = align16(off);
-  L.start = reinterpret_cast<int64_t*>(smem + off);
-  off += static_cast<size_t>(dmax) * 8;
   off = align16(off);
   L.nbr = reinterpret_cast<int*>(smem + off);
   off += static_cast<size_t>(dmax) * 4;
@@ -71,45 +71,76 @@ __device__ CliqueLds carve(unsigned char* smem, int dmax, int W, int k, bool row
   off += (kMaxK + 2) * 4;
   off = align16(off);
   L.lr = reinterpret_cast<uint64_t*>(smem + off);
-  off += 64 * 8;
+  off += kReindexMax / 64 * kReindexMax * 8;
+  L.cset = reinterpret_cast<uint64_t*>(smem + off);
+  off += 4 * 8;
   L.pos = reinterpret_cast<int*>(smem + off);
   return L;
 }
 
 // ---------------------------------------------------------------- small dense solver
 //
-// Once a candidate set has at most 64 members, the remaining q levels of the
-// enumeration tree are counted inside registers: members get local ids
-// 0..m-1 (rank order), row lr[i] holds the members adjacent to member i with
-// a larger id, and a q-clique count is a nested loop of AND + popcount.  The
-// wave walks the first member i; lane j takes the second member j in
-// C & lr[i] and counts the (q-2)-cliques of C & lr[i] & lr[j] on its own.
+// Once a candidate set is small (<= 128 members: in place for roots with <= 128
+// out-neighbours, else after re-indexing), the remaining q
+// levels of the enumeration tree are counted with per-lane bitset recursion:
+// a member set is NW 64-bit words, row word q of member i sits at
+// lr[q * stride + i] (word-major, so lanes reading consecutive members hit
+// distinct banks), rows hold only members with a larger id, and a q-clique
+// count is a nested loop of AND + popcount.  The wave walks the first member
+// i; lane l takes the second member j = 64 w + l in C & row(i) and counts the
+// (q-2)-cliques of C & row(i) & row(j) on its own.  Word loops are not
+// unrolled around the recursion (code size stays linear in the depth); `pick`
+// selects a word of a register array without dynamic register indexing.
 
 constexpr int kSolverMaxQ = 8;
 
-template <int D>
-__device__ __forceinline__ uint64_t count_in(uint64_t C, const uint64_t* lr) {
+// rows the solver reads always live in LDS: an address-space-3 pointer makes
+// every load a ds_read (no flat-address dispatch)
+typedef __attribute__((address_space(3))) const uint64_t LdsU64;
+
+__device__ __forceinline__ LdsU64* as_lds(const uint64_t* p) { return (LdsU64*)(p); }
+
+template <int NW>
+__device__ __forceinline__ uint64_t pick(const uint64_t (&c)[NW], int w) {
+  uint64_t r = c[0];
+#pragma unroll
+  for (int q = 1; q < NW; ++q) r = (w == q) ? c[q] : r;
+  return r;
+}
+
+template <int D, int NW>
+__device__ __forceinline__ uint64_t count_in(const uint64_t (&C)[NW], LdsU64* lr, int stride) {
   if constexpr (D == 1) {
-    return static_cast<uint64_t>(__popcll(C));
+    uint64_t s = 0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) s += static_cast<uint64_t>(__popcll(C[q]));
+    return s;
   } else {
     uint64_t s = 0;
-    while (C) {
-      const int x = __builtin_ctzll(C);
-      C &= C - 1;
-      s += count_in<D - 1>(C & lr[x], lr);
+    for (int w = 0; w < NW; ++w) {
+      uint64_t x = pick<NW>(C, w);
+      while (x) {
+        const int id = w * 64 + __builtin_ctzll(x);
+        x &= x - 1;
+        uint64_t Cn[NW];
+#pragma unroll
+        for (int q = 0; q < NW; ++q) Cn[q] = C[q] & lr[q * stride + id];
+        s += count_in<D - 1, NW>(Cn, lr, stride);
+      }
     }
     return s;
   }
 }
 
-__device__ __forceinline__ uint64_t count_in_depth(int D, uint64_t C, const uint64_t* lr) {
+template <int NW>
+__device__ __forceinline__ uint64_t count_in_depth(int D, const uint64_t (&C)[NW], LdsU64* lr, int stride) {
   switch (D) {
-    case 1: return count_in<1>(C, lr);
-    case 2: return count_in<2>(C, lr);
-    case 3: return count_in<3>(C, lr);
-    case 4: return count_in<4>(C, lr);
-    case 5: return count_in<5>(C, lr);
-    case 6: return count_in<6>(C, lr);
+    case 1: return count_in<1, NW>(C, lr, stride);
+    case 2: return count_in<2, NW>(C, lr, stride);
+    case 3: return count_in<3, NW>(C, lr, stride);
+    case 4: return count_in<4, NW>(C, lr, stride);
+    case 5: return count_in<5, NW>(C, lr, stride);
+    case 6: return count_in<6, NW>(C, lr, stride);
     default: return 0;
   }
 }
@@ -122,52 +153,97 @@ __device__ __forceinline__ uint64_t range_mask64(int lo, int hi) {
   return upper & (~0ull << lo);
 }
 
-// q-cliques (1 <= q <= kSolverMaxQ) inside C whose first member lies in
-// [lo, hi); returns this lane's share.
-__device__ __forceinline__ uint64_t small_solve(uint64_t C, int q, const uint64_t* lr, int lo, int hi) {
+// q-cliques (1 <= q <= kSolverMaxQ) inside the set Cl (NW words) whose first
+// member lies in [lo, hi); returns this lane's share.
+template <int NW>
+__device__ uint64_t small_solve(LdsU64* Cl, int q, LdsU64* lr, int stride, int lo, int hi) {
   const int lane = lane_id();
-  C = uniu64(C);
-  uint64_t first = C & range_mask64(lo, hi);
+  uint64_t C[NW], first[NW];
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    C[w] = uniu64(Cl[w]);
+    first[w] = C[w] & range_mask64(lo - 64 * w, hi - 64 * w);
+  }
   uint64_t add = 0;
   if (q == 1) {
-    if (lane == 0) add = static_cast<uint64_t>(__popcll(first));
+    if (lane == 0)
+#pragma unroll
+      for (int w = 0; w < NW; ++w) add += static_cast<uint64_t>(__popcll(first[w]));
   } else if (q == 2) {
-    if ((first >> lane) & 1ull) add = static_cast<uint64_t>(__popcll(C & lr[lane]));
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      if ((first[w] >> lane) & 1ull) {
+        const int i = w * 64 + lane;
+#pragma unroll
+        for (int q2 = 0; q2 < NW; ++q2) add += static_cast<uint64_t>(__popcll(C[q2] & lr[q2 * stride + i]));
+      }
+    }
   } else {
-    while (first) {
-      const int i = __builtin_ctzll(first);
-      first &= first - 1;
-      const uint64_t Ci = uniu64(C & lr[i]);
-      if ((Ci >> lane) & 1ull) add += count_in_depth(q - 2, Ci & lr[lane], lr);
+    for (int w = 0; w < NW; ++w) {
+      uint64_t x = pick<NW>(first, w);
+      while (x) {
+        const int i = w * 64 + __builtin_ctzll(x);
+        x &= x - 1;
+        uint64_t Ci[NW];
+#pragma unroll
+        for (int q2 = 0; q2 < NW; ++q2) Ci[q2] = uniu64(C[q2] & lr[q2 * stride + i]);
+        for (int w2 = w; w2 < NW; ++w2) {
+          if ((pick<NW>(Ci, w2) >> lane) & 1ull) {
+            const int j = w2 * 64 + lane;
+            uint64_t Cj[NW];
+#pragma unroll
+            for (int q2 = 0; q2 < NW; ++q2) Cj[q2] = Ci[q2] & lr[q2 * stride + j];
+            add += count_in_depth<NW>(q - 2, Cj, lr, stride);
+          }
+        }
+      }
     }
   }
   return add;
 }
 
-// Local ids for the members of the multi-word set C: positions into L.pos,
-// rows into L.lr.  Returns the member count (<= 64 by the caller's check).
+__device__ __forceinline__ uint64_t small_solve_any(int nw, const uint64_t* Cg, int q, const uint64_t* lrg, int stride,
+                                                    int lo, int hi) {
+  LdsU64* C = as_lds(Cg);
+  LdsU64* lr = as_lds(lrg);
+  return nw == 1 ? small_solve<1>(C, q, lr, stride, lo, hi) : small_solve<2>(C, q, lr, stride, lo, hi);
+}
+
+// Local ids for the members of the multi-word set C (at most kReindexMax, by
+// the caller's check): positions into L.pos, rows (nw words, word-major with
+// stride kReindexMax) into L.lr, and the full local set into L.cset.
+// Returns nw.
 __device__ __forceinline__ int reindex(const uint64_t* C, int Wd, const uint64_t* rows, int dmax, const CliqueLds& L) {
   const int lane = lane_id();
   int base = 0;
   for (int w = 0; w < Wd; ++w) {
     const bool bit = (C[w] >> lane) & 1ull;
     const uint64_t b = ballot(bit);
-    if (bit && base + mbcnt(b) < 64) L.pos[base + mbcnt(b)] = w * 64 + lane;
+    if (bit && base + mbcnt(b) < kReindexMax) L.pos[base + mbcnt(b)] = w * 64 + lane;
     base += __popcll(b);
   }
-  const int m = uni(base < 64 ? base : 64);
+  const int m = uni(base < kReindexMax ? base : kReindexMax);
+  const int nw = m <= 64 ? 1 : 2;
   wave_sync();
-  if (lane < m) {
-    const int pa = L.pos[lane];
-    uint64_t row = 0;
-    for (int b = lane + 1; b < m; ++b) {
-      const int pb = L.pos[b];
-      if ((rows[static_cast<size_t>(pb >> 6) * dmax + pa] >> (pb & 63)) & 1ull) row |= 1ull << b;
+  for (int a = lane; a < m; a += kWave) {
+    const int pa = L.pos[a];
+    uint64_t r0 = 0, r1 = 0;
+    for (int bb = a + 1; bb < m; ++bb) {
+      const int pb = L.pos[bb];
+      if ((rows[static_cast<size_t>(pb >> 6) * dmax + pa] >> (pb & 63)) & 1ull) {
+        if (bb < 64) r0 |= 1ull << bb;
+        else r1 |= 1ull << (bb - 64);
+      }
     }
-    L.lr[lane] = row;
+    L.lr[a] = r0;
+    L.lr[kReindexMax + a] = r1;
+  }
+  if (lane < 2) {
+    const int rem = m - 64 * lane;
+    L.cset[lane] = rem >= 64 ? ~0ull : (rem > 0 ? ((1ull << rem) - 1) : 0ull);
   }
   wave_sync();
-  return m;
+  return nw;
 }
 
 // smallest set bit of C within [from, to), or -1 (wave-uniform)
@@ -264,9 +340,7 @@ __device__ void run_task(const CliqueArgs& A, const CliqueLds& L, uint64_t* rows
       if (i < d) {
         const int u = A.col[base + i];
         L.nbr[i] = u;
-        const int64_t s = A.rp[u];
-        od = static_cast<int>(A.rp[u + 1] - s);
-        L.start[i] = s;
+        od = static_cast<int>(A.rp[u + 1] - A.rp[u]);
       }
       int incl = od;
 #pragma unroll
@@ -293,7 +367,7 @@ __device__ void run_task(const CliqueArgs& A, const CliqueLds& L, uint64_t* rows
         if (L.offs[mid] <= tt) lo = mid; else hi = mid;
       }
       const int i = lo;
-      const int e = A.col[L.start[i] + (tt - L.offs[i])];
+      const int e = A.col[A.rp[L.nbr[i]] + (tt - L.offs[i])];
       int a = i + 1, b = d;  // e > nbr[i], so search above i
       while (a < b) {
         const int mid = (a + b) >> 1;
@@ -312,12 +386,10 @@ __device__ void run_task(const CliqueArgs& A, const CliqueLds& L, uint64_t* rows
       for (int w = lane; w < Wd; w += kWave) L.stk[(s + 1) * W + w] = L.stk[s * W + w] & rows[static_cast<size_t>(w) * dmax + p];
       wave_sync();
     }
-    // one-word roots: their rows already are local rows
+    // roots with at most 128 out-neighbours: their rows already are local rows
+    // (positions = local ids, Wd <= 2 words, stride dmax)
     const bool solver = A.prune != 0;
-    if (solver && Wd == 1) {
-      if (lane < d) L.lr[lane] = rows[lane];
-      wave_sync();
-    }
+    const bool root_local = ROWS_LDS && solver && d <= kLocalMax;
     auto add_acc = [&](uint64_t x) {
       const uint64_t before = WA.acc;
       WA.acc += x;
@@ -345,67 +417,139 @@ __device__ void run_task(const CliqueArgs& A, const CliqueLds& L, uint64_t* rows
     };
 
     const int s0 = t.depth;
-    if (solver && Wd == 1 && k - s0 <= kSolverMaxQ) {
-      add_acc(small_solve(L.stk[s0 * W], k - s0, L.lr, t.lo, hi_t));
+    // The dense solver has a single call site (so it is inlined once): the
+    // DFS records a pending job and the loop head runs it.  Jobs are bounded
+    // (one-word sets, or at most 4 remaining levels on two-word sets) because
+    // a job cannot be donated.
+    bool job = false, job_last = false;
+    int job_nw = 1, job_q = 0, job_stride = 0, job_lo = 0, job_hi = 0;
+    const uint64_t* job_C = nullptr;
+    const uint64_t* job_R = nullptr;
+    // Fast path (at most 64 words): lane w keeps word w of the current level's
+    // candidate set in a register, so choosing the next extension is a ballot
+    // and extending it is one row read per lane.  cur / hiv entries are
+    // written by every lane with the same value, so no barrier is needed to
+    // read them back.
+    const bool fast = Wd <= kWave;
+    uint64_t cw = 0;
+    int depth = s0;
+    if (root_local && k - s0 <= kSolverMaxQ && (k - s0 <= 3 || d <= 64)) {
+      job = job_last = true;
+      job_nw = Wd;
+      job_C = L.stk + s0 * W;
+      job_q = k - s0;
+      job_R = rows;
+      job_stride = dmax;
+      job_lo = t.lo;
+      job_hi = hi_t;
     } else if (s0 == k - 2) {
       leaf_parent(s0, t.lo, hi_t);
+      depth = -1;
     } else {
-      int depth = s0;
-      if (lane == 0) { L.cur[depth] = t.lo - 1; L.hiv[depth] = hi_t; }
+      L.cur[depth] = t.lo - 1;
+      L.hiv[depth] = hi_t;
+      if (fast && lane < Wd) cw = L.stk[depth * W + lane];
       wave_sync();
-      int steps = 0;
-      for (;;) {
-        const int u = next_bit(L.stk + depth * W, L.cur[depth] + 1, L.hiv[depth]);
-        if (u < 0) {
-          if (depth == s0) break;
-          --depth;
-          continue;
+    }
+    int steps = 0;
+    while (depth >= 0) {
+      if (job) {
+        add_acc(small_solve_any(job_nw, job_C, job_q, job_R, job_stride, job_lo, job_hi));
+        job = false;
+        if (job_last) break;
+      }
+      int u;
+      if (fast) {
+        const int from = L.cur[depth] + 1, to = L.hiv[depth];
+        const uint64_t m = lane < Wd ? (cw & range_mask64(from - 64 * lane, to - 64 * lane)) : 0ull;
+        const uint64_t bl = ballot(m != 0ull);
+        if (!bl) {
+          u = -1;
+        } else {
+          const int l = __ffsll(static_cast<long long>(bl)) - 1;
+          const uint64_t wm = __shfl(m, l, kWave);
+          u = uni(64 * l + __builtin_ctzll(wm));
         }
-        if (lane == 0) {
-          L.cur[depth] = u;
-          nodes_l += 1;
-          reads_l += static_cast<uint64_t>(L.offs[u + 1] - L.offs[u]);
-        }
-        int cnt = 0;
+      } else {
+        u = next_bit(L.stk + depth * W, L.cur[depth] + 1, L.hiv[depth]);
+      }
+      if (u < 0) {
+        if (depth == s0) break;
+        --depth;
+        if (fast && lane < Wd) cw = L.stk[depth * W + lane];
+        continue;
+      }
+      L.cur[depth] = u;
+      if (lane == 0) {
+        nodes_l += 1;
+        reads_l += static_cast<uint64_t>(L.offs[u + 1] - L.offs[u]);
+      }
+      int cnt = 0;
+      uint64_t x = 0;
+      if (fast) {
+        if (lane < Wd) x = cw & rows[static_cast<size_t>(lane) * dmax + u];
+        cnt = uni(wave_sum_i32(__popcll(x)));
+      } else {
         for (int w = lane; w < Wd; w += kWave) {
-          const uint64_t x = L.stk[depth * W + w] & rows[static_cast<size_t>(w) * dmax + u];
-          L.stk[(depth + 1) * W + w] = x;
-          cnt += __popcll(x);
+          const uint64_t y = L.stk[depth * W + w] & rows[static_cast<size_t>(w) * dmax + u];
+          L.stk[(depth + 1) * W + w] = y;
+          cnt += __popcll(y);
         }
         cnt = uni(wave_sum_i32(cnt));
         wave_sync();
-        const int q = k - depth - 1;  // vertices still to add below the child
-        if (!A.prune || cnt >= q) {
-          if (solver && cnt <= 64 && q <= kSolverMaxQ) {
-            if (Wd == 1) {
-              add_acc(small_solve(L.stk[(depth + 1) * W], q, L.lr, 0, 64));
-            } else {
-              const int m = reindex(L.stk + (depth + 1) * W, Wd, rows, dmax, L);
-              add_acc(small_solve(m == 64 ? ~0ull : ((1ull << m) - 1), q, L.lr, 0, 64));
-            }
-          } else if (depth + 1 == k - 2) {
-            leaf_parent(depth + 1, 0, d);
-          } else {
-            ++depth;
-            if (lane == 0) { L.cur[depth] = -1; L.hiv[depth] = d; }
-            wave_sync();
-          }
+      }
+      const int q = k - depth - 1;  // vertices still to add below the child
+      if (!A.prune || cnt >= q) {
+        const bool bounded = q <= kSolverMaxQ && (cnt <= 64 || q <= 4);
+        const bool need_lds = (solver && bounded && (root_local || cnt <= kReindexMax)) || depth + 1 == k - 2;
+        if (fast && need_lds) {
+          if (lane < Wd) L.stk[(depth + 1) * W + lane] = x;
+          wave_sync();
         }
-        // ---- donation (Section IV-D redistribute, done by the busy wave)
-        if (A.S.donate && (++steps % A.S.period) == 0 && sched_want_donation(A.S)) {
-          for (int s = s0; s <= depth; ++s) {
-            const int from = L.cur[s] + 1, to = L.hiv[s];
-            const int c = count_bits(L.stk + s * W, from, to);
-            if (c >= 2) {
-              const int keep = c - c / 2;
-              const int mid = select_bit(L.stk + s * W, from, to, keep + 1);
-              const int pay = task_payload(v, t.stat, s, mid, to, L.cur);
-              if (sched_publish(A.S, pay, wave_gid)) {
-                if (lane == 0) L.hiv[s] = mid;
-              }
-              wave_sync();
-              break;
-            }
+        if (root_local && bounded) {
+          job = true;
+          job_nw = Wd;
+          job_C = L.stk + (depth + 1) * W;
+          job_q = q;
+          job_R = rows;
+          job_stride = dmax;
+          job_lo = 0;
+          job_hi = d;
+        } else if (solver && bounded && cnt <= kReindexMax) {
+          job_nw = reindex(L.stk + (depth + 1) * W, Wd, rows, dmax, L);
+          job = true;
+          job_C = L.cset;
+          job_q = q;
+          job_R = L.lr;
+          job_stride = kReindexMax;
+          job_lo = 0;
+          job_hi = kReindexMax;
+        } else if (depth + 1 == k - 2) {
+          leaf_parent(depth + 1, 0, d);
+        } else {
+          if (fast) {
+            if (lane < Wd) L.stk[(depth + 1) * W + lane] = x;
+            cw = x;
+          }
+          ++depth;
+          L.cur[depth] = -1;
+          L.hiv[depth] = d;
+          if (!fast) wave_sync();
+        }
+      }
+      // ---- donation (Section IV-D redistribute, done by the busy wave)
+      if (A.S.donate && (++steps % A.S.period) == 0 && sched_want_donation(A.S)) {
+        wave_sync();
+        for (int s = s0; s <= depth; ++s) {
+          const int from = L.cur[s] + 1, to = L.hiv[s];
+          const int c = count_bits(L.stk + s * W, from, to);
+          if (c >= 2) {
+            const int keep = c - c / 2;
+            const int mid = select_bit(L.stk + s * W, from, to, keep + 1);
+            const int pay = task_payload(v, t.stat, s, mid, to, L.cur);
+            if (sched_publish(A.S, pay, wave_gid)) L.hiv[s] = mid;
+            wave_sync();
+            break;
           }
         }
       }
@@ -499,11 +643,10 @@ size_t clique_lds_bytes(int dmax, int W, int k, bool rows_in_lds) {
   auto a16 = [](size_t x) { return (x + 15) & ~static_cast<size_t>(15); };
   size_t off = rows_in_lds ? static_cast<size_t>(W) * dmax * 8 : 0;
   off = a16(off) + static_cast<size_t>(k + 1) * W * 8;
-  off = a16(off) + static_cast<size_t>(dmax) * 8;
   off = a16(off) + static_cast<size_t>(dmax) * 4;
   off = a16(off) + static_cast<size_t>(dmax + 1) * 4;
   off = a16(off) + 2 * (kMaxK + 2) * 4;
-  off = a16(off) + 64 * 8 + 64 * 4;
+  off = a16(off) + kReindexMax / 64 * kReindexMax * 8 + 4 * 8 + kReindexMax * 4;
   return a16(off);
 }
 
