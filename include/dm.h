@@ -63,7 +63,7 @@ enum {
 
 /* dm_options.sched bits */
 enum {
-    DM_SCHED_PLAIN = 0,    /* roots in natural order (rank order for cliques, id order for motifs) */
+    DM_SCHED_PLAIN = 0,    /* roots in (degree, id) rank order */
     DM_SCHED_LEARNED = 1,  /* order and chunk roots by the MLP's predicted subtree size */
     DM_SCHED_AUTOTUNE = 2, /* pick chunk / rebalance / waves-per-CU from the tuner cache */
     DM_RECORD_ROOTS = 4,   /* write per-root {tree nodes, leaves, adjacency reads} */
@@ -80,7 +80,8 @@ typedef struct {
     uint32_t size;
     uint32_t sched;          /* DM_SCHED_* | DM_RECORD_ROOTS | DM_NO_DONATION */
     void* stream;            /* hipStream_t or NULL */
-    uint32_t chunk;          /* roots per queue grab; 0 = default */
+    uint32_t chunk;          /* plain queue: roots per grab (0 = 1); learned queue:
+                                chunks of equal predicted cost per wave (0 = 8) */
     float rebalance;         /* donate once at least this fraction of waves is idle; 0 = default */
     uint32_t waves_per_cu;   /* resident waves per CU for the persistent grid; 0 = occupancy maximum */
     const float* mlp;        /* DM_SCHED_LEARNED: device pointer to DM_MLP_NPARAMS floats */

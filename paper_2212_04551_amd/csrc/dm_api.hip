@@ -576,7 +576,9 @@ dm_status ensure_features(dm_graph* g, hipStream_t s) {
 }
 
 // Learned queue: MLP prediction of every root's tree size, longest first,
-// chunks of about equal predicted cost (about `per_wave` chunks per wave).
+// chunks of about equal predicted cost (`chunk` chunks per wave, default 8).
+// A wave hands the untried part of a chunk to idle waves, so a mispredicted
+// chunk does not stall the launch.
 // On return g->lorder holds vertex ids in queue order and g->qbounds the chunk
 // starts (+ n).
 dm_status learned_queue(dm_graph* g, const Opt& o, int grid, hipStream_t s, int64_t* nchunks) {
@@ -587,7 +589,7 @@ dm_status learned_queue(dm_graph* g, const Opt& o, int grid, hipStream_t s, int6
   HIP_OR_RETURN(g->lorder.ensure(sizeof(int32_t) * n), "learned: allocate");
   HIP_OR_RETURN(g->qbounds.ensure(sizeof(int64_t) * (n + 1)), "learned: allocate");
   HIP_OR_RETURN(mlp_forward(o.mlp, g->feat.as<int64_t>(), g->n, g->pred.as<float>(), s), "learned: forward");
-  const int per_wave = 4;
+  const int per_wave = o.chunk ? static_cast<int>(o.chunk) : 8;
   HIP_OR_RETURN(lpt_order(g->pred.as<float>(), g->n, grid * per_wave, g->lorder.as<int32_t>(), g->qbounds.as<int64_t>(),
                           nchunks, s),
                 "learned: order");

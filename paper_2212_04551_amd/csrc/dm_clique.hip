@@ -585,46 +585,15 @@ __global__ void __launch_bounds__(64) clique_kernel(CliqueArgs A) {
   WA.nodes = 0;
   WA.tasks = 0;
   const uint64_t t_begin = wall_clock64();
-  uint64_t t_idle = 0;
-  if (lane == 0) add_u64(A.S.state, kActiveOne);
-  int64_t b, e;
-  while (sched_grab(A.S, &b, &e)) {
-    for (int64_t q = b; q < e; ++q) {
-      Task t = sched_entry(A.S, q, INT_MAX);
-      run_task<ROWS_LDS>(A, L, rows, t, WA, wave_gid);
-      WA.tasks++;
-    }
+  SchedIter it;
+  sched_begin(A.S, it);
+  Task t;
+  while (sched_next(A.S, it, wave_gid, L.cur, &t)) {
+    run_task<ROWS_LDS>(A, L, rows, t, WA, wave_gid);
+    WA.tasks++;
   }
-  if (lane == 0) {
-    add_i32(A.S.idle, 1);
-    add_u64(A.S.state, 0ull - kActiveOne);
-  }
-  if (A.S.donate) {
-    uint64_t t0 = wall_clock64();
-    for (;;) {
-      unsigned long long st = 0;
-      if (lane == 0) st = ld_relaxed_u64(A.S.state);
-      st = uniu64(st);
-      if (st == 0) break;
-      int data = 0;
-      if ((st & 0xffffffffull) != 0 && sched_take(A.S, &data, wave_gid)) {
-        t_idle += wall_clock64() - t0;
-        if (lane == 0) add_i32(A.S.idle, -1);
-        Task t = task_unpack(data, L.cur);
-        run_task<ROWS_LDS>(A, L, rows, t, WA, wave_gid);
-        WA.tasks++;
-        if (lane == 0) {
-          add_i32(A.S.idle, 1);
-          add_u64(A.S.state, 0ull - kActiveOne);
-        }
-        t0 = wall_clock64();
-        continue;
-      }
-      __builtin_amdgcn_s_sleep(16);
-    }
-    t_idle += wall_clock64() - t0;
-  }
-  if (lane == 0) add_i32(A.S.idle, -1);
+  sched_end(A.S);
+  const uint64_t t_idle = it.t_idle;
   flush_graph(A, WA);
   if (lane == 0 && WA.ovf) atomicOr(A.flags, 1);
   if (A.wave_stats && wave_gid < A.wave_stats_len && lane == 0) {

@@ -60,6 +60,17 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t x, int* ovf) {
   return x;
 }
 
+// Inclusive prefix sum over the wave's lanes.
+__device__ __forceinline__ int64_t wave_incl_scan_i64(int64_t x) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const int64_t y = __shfl_up(static_cast<long long>(x), d, kWave);
+    if (lane >= d) x += y;
+  }
+  return x;
+}
+
 __device__ __forceinline__ int wave_sum_i32(int x) {
 #pragma unroll
   for (int sh = 32; sh >= 1; sh >>= 1) x += __shfl_xor(x, sh, kWave);
@@ -259,6 +270,16 @@ __device__ __forceinline__ int task_payload(int root, int64_t stat, int depth, i
   return v;
 }
 
+// A range task hands over queue entries [lo, hi) that a wave has not started
+// yet (depth 0 marks it; the root field is unused).
+__device__ __forceinline__ int task_range_payload(int64_t lo, int64_t hi) {
+  const int lane = lane_id();
+  int v = 0;
+  if (lane == 4) v = static_cast<int>(lo);
+  else if (lane == 5) v = static_cast<int>(hi);
+  return v;
+}
+
 __device__ __forceinline__ Task task_unpack(int data_lane, int* prefix_lds) {
   Task t;
   t.root = uni(read_lane(data_lane, 0));
@@ -273,6 +294,92 @@ __device__ __forceinline__ Task task_unpack(int data_lane, int* prefix_lds) {
   if (lane >= 6 && lane < 6 + t.depth - 1) prefix_lds[lane - 6 + 1] = data_lane;
   wave_sync();
   return t;
+}
+
+// The persistent wave's work source (Section IV-B Move, with the Section IV-D
+// rebalancing done inside the kernel).  A wave takes queue chunks while the
+// queue lasts, then waits for donated work until no wave is active and no task
+// is pending.  Between two entries of a chunk (or of a donated entry range)
+// the wave hands the untried upper half of the range to waiting waves.
+// Usage: SchedIter it; sched_begin(S, it); while (sched_next(S, it, ...)) run;
+// sched_end(S, it).
+struct SchedIter {
+  int mode;  // 0: taking queue chunks, 1: waiting, 2: running donated work
+  int64_t q, e;
+  uint64_t t0, t_idle;
+};
+
+__device__ __forceinline__ void sched_begin(const Sched& S, SchedIter& it) {
+  it.mode = 0;
+  it.q = it.e = 0;
+  it.t0 = it.t_idle = 0;
+  if (lane_id() == 0) add_u64(S.state, kActiveOne);
+}
+
+__device__ __forceinline__ void sched_go_idle(const Sched& S, SchedIter& it) {
+  if (lane_id() == 0) {
+    add_i32(S.idle, 1);
+    add_u64(S.state, 0ull - kActiveOne);
+  }
+  it.mode = 1;
+  it.t0 = wall_clock64();
+}
+
+// Next unit of work into *t; false when the whole launch has drained.
+__device__ __forceinline__ bool sched_next(const Sched& S, SchedIter& it, int wave_gid, int* prefix_lds, Task* t) {
+  for (;;) {
+    if (it.q < it.e) {
+      if (S.donate && it.e - it.q >= 2 && sched_want_donation(S)) {
+        const int64_t mid = it.q + (it.e - it.q + 1) / 2;
+        if (sched_publish(S, task_range_payload(mid, it.e), wave_gid)) it.e = mid;
+      }
+      *t = sched_entry(S, it.q, INT_MAX);
+      ++it.q;
+      return true;
+    }
+    if (it.mode == 0) {
+      int64_t b, e;
+      if (sched_grab(S, &b, &e)) {
+        it.q = b;
+        it.e = e;
+        continue;
+      }
+      sched_go_idle(S, it);
+      if (!S.donate) return false;
+      continue;
+    }
+    if (it.mode == 2) {
+      sched_go_idle(S, it);
+      continue;
+    }
+    unsigned long long st = 0;
+    if (lane_id() == 0) st = ld_relaxed_u64(S.state);
+    st = uniu64(st);
+    if (st == 0) {
+      it.t_idle += wall_clock64() - it.t0;
+      return false;
+    }
+    int data = 0;
+    if ((st & 0xffffffffull) == 0 || !sched_take(S, &data, wave_gid)) {
+      __builtin_amdgcn_s_sleep(16);
+      continue;
+    }
+    it.t_idle += wall_clock64() - it.t0;
+    if (lane_id() == 0) add_i32(S.idle, -1);
+    it.mode = 2;
+    *t = task_unpack(data, prefix_lds);
+    if (t->depth == 0) {
+      it.q = t->lo;
+      it.e = t->hi;
+      continue;
+    }
+    return true;
+  }
+}
+
+// Leave the loop: the wave counted itself idle when the work ran out.
+__device__ __forceinline__ void sched_end(const Sched& S) {
+  if (lane_id() == 0) add_i32(S.idle, -1);
 }
 
 }  // namespace dm

@@ -31,12 +31,25 @@
 //     (coalesced read) and binary-searches it in the level list: found entries
 //     get bit s; the rest are new and are compacted with ballot/mbcnt
 //     (Compact); then a wave-parallel merge writes level s+1.
-//   - The last two levels are fused: for a traversal of size k-2 and each
-//     canonical extension x, the leaves tr+x+y are the canonical entries y > x
-//     of the same list (their mask gains bit k-2 when y ~ x) plus the new
-//     neighbours of x above v_0.  Leaves are histogrammed by mask inside the
-//     wave (ballot match loop), and each non-empty mask bin is relabelled once
-//     through the dictionary into per-wave LDS class counters.
+//   - Entries at or below v_0 can never join a canonical traversal, so level
+//     lists hold only vertices above v_0.
+//   - The last two levels are counted without visiting the leaves one by one
+//     (Aggregate, Section IV-C, for a whole level at once).  For a traversal
+//     tr of size k-2 with list E, the canonical k-traversals tr+x+y are
+//       (a) x < y, both canonical entries of E (y keeps its first neighbour in
+//           tr, and x now sits after it), and
+//       (b) x canonical, y a neighbour of x above v_0 that is neither in E nor
+//           in tr (first neighbour x).
+//     The pattern of (a) depends only on {mask x, mask y, x ~ y} and is
+//     symmetric in x and y, so per mask pair the count is C(c_a, 2) or
+//     c_a * c_b (c = canonical entries per mask) split into adjacent and
+//     non-adjacent pairs; the adjacent pairs, and the pairs of (b), come from
+//     one load-balanced pass over the neighbour lists of all canonical x
+//     (lanes take consecutive (x, neighbour) items of a wave prefix sum of
+//     degrees).  Each non-empty (mask pair, adjacency) bin is relabelled once
+//     through the dictionary into per-wave LDS class counters.  A range
+//     [lo, hi) of x (a donated task) takes the pairs whose smaller member lies
+//     in the range: P([lo, |E|)) - P([hi, |E|)).
 #include <climits>
 
 #include "dm_internal.hpp"
@@ -48,40 +61,47 @@ namespace {
 constexpr int kMotifMaxK = 7;
 constexpr int kSuf = kMotifMaxK + 1;
 
+constexpr int kBins = 16;  // masks of a (k-2)-traversal entry, k <= 6
+
 struct MotifLds {
   unsigned long long* cnt;  // [ncls] class counters of the current graph
-  unsigned* hist;           // [2^(k-1)] leaf masks
+  unsigned long long* adj;  // [kBins * kBins] adjacent canonical pairs (mask of smaller, mask of larger)
+  unsigned long long* nw;   // [kBins] pairs (b): by mask of x
+  unsigned* ccount;         // [2][kBins] canonical entries by mask: in [lo, hi), in [hi, |E|)
+  int64_t* sl_start;        // [kWave + 1] slice: prefix sum of the degrees of canonical entries
+  int64_t* sl_base;         // [kWave] slice: row_ptr of the entry's vertex
+  int* sl_mask;             // [kWave] slice: entry mask over tr
   int* tr;                  // [kSuf] traversal
   int* code;                // [kSuf] dictionary code per traversal size
   int* sufmax;              // [kSuf][kSuf] max of tr[f+1..s-1] per size s
   int* cursor;              // [kSuf]
   int* endv;                // [kSuf]
   int* esize;               // [kSuf]
-  int* misc;                // [4]
 };
 
 __device__ __forceinline__ int off_of(int i) { return i * (i - 1) / 2 - 1; }  // bitmap field of v_i, i >= 2
 
-__device__ MotifLds carve(unsigned char* smem, int ncls, int k) {
+__device__ MotifLds carve(unsigned char* smem, int ncls) {
   MotifLds L;
   size_t off = 0;
-  L.cnt = reinterpret_cast<unsigned long long*>(smem);
-  off += static_cast<size_t>(ncls) * 8;
-  L.hist = reinterpret_cast<unsigned*>(smem + off);
-  off += static_cast<size_t>(1 << (k - 1)) * 4;
-  L.tr = reinterpret_cast<int*>(smem + off);
-  off += kSuf * 4;
-  L.code = reinterpret_cast<int*>(smem + off);
-  off += kSuf * 4;
-  L.sufmax = reinterpret_cast<int*>(smem + off);
-  off += kSuf * kSuf * 4;
-  L.cursor = reinterpret_cast<int*>(smem + off);
-  off += kSuf * 4;
-  L.endv = reinterpret_cast<int*>(smem + off);
-  off += kSuf * 4;
-  L.esize = reinterpret_cast<int*>(smem + off);
-  off += kSuf * 4;
-  L.misc = reinterpret_cast<int*>(smem + off);
+  auto take = [&](size_t bytes) {
+    unsigned char* p = smem + off;
+    off += (bytes + 15) & ~static_cast<size_t>(15);
+    return p;
+  };
+  L.cnt = reinterpret_cast<unsigned long long*>(take(static_cast<size_t>(ncls) * 8));
+  L.adj = reinterpret_cast<unsigned long long*>(take(kBins * kBins * 8));
+  L.nw = reinterpret_cast<unsigned long long*>(take(kBins * 8));
+  L.ccount = reinterpret_cast<unsigned*>(take(2 * kBins * 4));
+  L.sl_start = reinterpret_cast<int64_t*>(take((kWave + 1) * 8));
+  L.sl_base = reinterpret_cast<int64_t*>(take(kWave * 8));
+  L.sl_mask = reinterpret_cast<int*>(take(kWave * 4));
+  L.tr = reinterpret_cast<int*>(take(kSuf * 4));
+  L.code = reinterpret_cast<int*>(take(kSuf * 4));
+  L.sufmax = reinterpret_cast<int*>(take(kSuf * kSuf * 4));
+  L.cursor = reinterpret_cast<int*>(take(kSuf * 4));
+  L.endv = reinterpret_cast<int*>(take(kSuf * 4));
+  L.esize = reinterpret_cast<int*>(take(kSuf * 4));
   return L;
 }
 
@@ -139,10 +159,11 @@ __device__ void extend_level(const MotifArgs& A, const MotifLds& L, MotifWave& M
   const int64_t cap = A.level_cap[s + 1];
   const int64_t xb = A.rp[x];
   const int dx = static_cast<int>(A.rp[x + 1] - xb);
+  const int v0 = L.tr[0];
   int nn = 0;
   for (int c = 0; c < dx; c += kWave) {
     const int i = c + lane;
-    const bool ok = i < dx;
+    const bool ok = i < dx && A.col[xb + i] > v0;
     const int w = ok ? A.col[xb + i] : 0;
     int j = ok ? lower_bound_g(Ev, ns, w) : ns;
     const bool found = ok && j < ns && Ev[j] == w;
@@ -203,68 +224,131 @@ __device__ void extend_level(const MotifArgs& A, const MotifLds& L, MotifWave& M
   wave_sync();
 }
 
-// Count the leaves below tr + x, where |tr| = s = k-2 and x is entry px.
-__device__ void leaf_count(const MotifArgs& A, const MotifLds& L, MotifWave& MW, int s, int px, int x,
-                           uint64_t& leaves_l) {
+// Count every leaf below the traversal tr (|tr| = s = k-2) whose x is an entry
+// of [lo, hi) of tr's list.  Between slices of 64 entries the untried part of
+// the range may be donated (a task at depth s).  Returns the final hi.
+__device__ __forceinline__ int leaf_level(const MotifArgs& A, const MotifLds& L, MotifWave& MW, int s, int lo, int hi,
+                          const Task& t, int wave_gid, uint64_t& nodes_l, uint64_t& leaves_l, uint64_t& reads_l) {
   const int lane = lane_id();
-  const int k = A.k;
-  int32_t* Ev = MW.vert + A.level_off[s];
-  uint8_t* Em = MW.mask + A.level_off[s];
+  const int32_t* Ev = MW.vert + A.level_off[s];
+  const uint8_t* Em = MW.mask + A.level_off[s];
   const int ns = L.esize[s];
-  const int nb = 1 << (k - 1);
-  for (int m = lane; m < nb; m += kWave) L.hist[m] = 0;
+  const int nm = 1 << s;
+  const unsigned low = static_cast<unsigned>(nm - 1);
   const int v0 = L.tr[0];
-  const int64_t xb = A.rp[x];
-  const int dx = static_cast<int>(A.rp[x + 1] - xb);
-  int newcnt = 0;
-  for (int c = 0; c < dx; c += kWave) {
-    const int i = c + lane;
-    const bool ok = i < dx;
-    const int w = ok ? A.col[xb + i] : 0;
-    const int j = ok ? lower_bound_g(Ev, ns, w) : ns;
-    const bool found = ok && j < ns && Ev[j] == w;
-    if (found && j > px) Em[j] = static_cast<uint8_t>(Em[j] | 0x80u);
-    const bool isnew = ok && !found && w > v0 && !in_tr(L, s, w);
-    newcnt += __popcll(ballot(isnew));
-  }
+  for (int i = lane; i < kBins * kBins; i += kWave) L.adj[i] = 0;
+  if (lane < kBins) L.nw[lane] = 0;
+  if (lane < 2 * kBins) L.ccount[lane] = 0;
   wave_sync();
-  const unsigned low = (1u << s) - 1u;
-  for (int c = px + 1; c < ns; c += kWave) {
+  for (int c = lo; c < hi; c += kWave) {
+    // ---- slice: canonical entries and a prefix sum of their degrees
     const int j = c + lane;
-    const bool in = j < ns;
+    const bool in = j < hi;
+    const int x = in ? Ev[j] : 0;
     const unsigned m = in ? Em[j] : 0u;
-    const int y = in ? Ev[j] : 0;
-    if (m & 0x80u) Em[j] = static_cast<uint8_t>(m & 0x7fu);
-    const bool valid = in && canonical(L, s, y, m);
-    const unsigned lm = (m & low) | ((m & 0x80u) ? (1u << s) : 0u);
-    uint64_t act = ballot(valid);
+    const bool ok = in && canonical(L, s, x, m);
+    const int64_t xb = ok ? A.rp[x] : 0;
+    const int64_t dx = ok ? A.rp[x + 1] - xb : 0;
+    const int64_t incl = wave_incl_scan_i64(dx);
+    const int64_t total = static_cast<int64_t>(__shfl(static_cast<long long>(incl), kWave - 1, kWave));
+    L.sl_start[lane] = incl - dx;
+    L.sl_base[lane] = xb;
+    L.sl_mask[lane] = static_cast<int>(m & low);
+    const uint64_t okb = ballot(ok);
+    if (lane == 0) {
+      L.sl_start[kWave] = total;
+      nodes_l += static_cast<uint64_t>(__popcll(okb));
+      reads_l += static_cast<uint64_t>(total);
+    }
+    wave_sync();
+    // ---- every (x, neighbour) item of the slice, 64 at a time
+    for (int64_t f0 = 0; f0 < total; f0 += kWave) {
+      const int64_t f = f0 + lane;
+      int key = -1;
+      if (f < total) {
+        int o = 0;  // last slice lane whose start is <= f
+        for (int step = kWave / 2; step >= 1; step >>= 1)
+          if (L.sl_start[o + step] <= f) o += step;
+        const int w = A.col[L.sl_base[o] + (f - L.sl_start[o])];
+        if (w > v0) {
+          const int jj = lower_bound_g(Ev, ns, w);
+          if (jj < ns && Ev[jj] == w) {
+            if (jj > c + o && canonical(L, s, w, Em[jj])) key = L.sl_mask[o] * kBins + static_cast<int>(Em[jj] & low);
+          } else if (!in_tr(L, s, w)) {
+            key = kBins * kBins + L.sl_mask[o];
+          }
+        }
+      }
+      uint64_t act = ballot(key >= 0);
+      while (act) {
+        const int l = __ffsll(static_cast<long long>(act)) - 1;
+        const int kk = read_lane(key, l);
+        const uint64_t same = ballot(key == kk);
+        if (lane == 0) {
+          if (kk < kBins * kBins) L.adj[kk] += static_cast<unsigned long long>(__popcll(same));
+          else L.nw[kk - kBins * kBins] += static_cast<unsigned long long>(__popcll(same));
+        }
+        act &= ~same;
+      }
+    }
+    wave_sync();
+    // ---- donation of the untried x range
+    const int next = c + kWave;
+    if (A.S.donate && hi - next >= 2 && sched_want_donation(A.S)) {
+      const int mid = next + (hi - next + 1) / 2;
+      const int pay = task_payload(t.root, t.stat, s, mid, hi, L.tr);
+      if (sched_publish(A.S, pay, wave_gid)) hi = mid;
+      wave_sync();
+    }
+  }
+  // ---- canonical entries per mask over [lo, hi) and [hi, |E|)
+  for (int c = lo; c < ns; c += kWave) {
+    const int j = c + lane;
+    const bool ok = j < ns && canonical(L, s, Ev[j], Em[j]);
+    const int key = ok ? static_cast<int>(Em[j] & low) + (j >= hi ? kBins : 0) : -1;
+    uint64_t act = ballot(ok);
     while (act) {
       const int l = __ffsll(static_cast<long long>(act)) - 1;
-      const unsigned key = static_cast<unsigned>(read_lane(static_cast<int>(lm), l));
-      const uint64_t same = ballot(valid && lm == key);
-      if (lane == 0) L.hist[key] += static_cast<unsigned>(__popcll(same));
+      const int kk = read_lane(key, l);
+      const uint64_t same = ballot(key == kk);
+      if (lane == 0) L.ccount[kk] += static_cast<unsigned>(__popcll(same));
       act &= ~same;
     }
   }
-  if (lane == 0) L.hist[1u << s] += static_cast<unsigned>(newcnt);
   wave_sync();
-  const unsigned mx = Em[px] & low;
-  const int codex = L.code[s] | (s >= 2 ? static_cast<int>(mx << off_of(s)) : 0);
-  const int offl = off_of(k - 1);
-  for (int m = lane; m < nb; m += kWave) {
-    const unsigned h = L.hist[m];
-    if (h) {
-      const int cls = A.table[codex | (m << offl)];
-      if (cls == 0xFF) {
-        atomicOr(A.flags + 1, 2);
-      } else {
-        const unsigned long long old = atomicAdd(&L.cnt[cls], static_cast<unsigned long long>(h));
-        if (old + h < old) MW.ovf = 1;
-      }
-      leaves_l += h;
+  // ---- one dictionary lookup per non-empty bin
+  const int code_tr = L.code[s];
+  const int fx = s >= 2 ? off_of(s) : 0;  // v_1's field is implied
+  const int fy = off_of(s + 1);
+  auto add_class = [&](int code, uint64_t h) {
+    const int cls = A.table[code];
+    if (cls == 0xFF) {
+      atomicOr(A.flags + 1, 2);
+    } else {
+      const unsigned long long old = atomicAdd(&L.cnt[cls], static_cast<unsigned long long>(h));
+      if (old + h < old) MW.ovf = 1;
+    }
+    leaves_l += h;
+  };
+  for (int idx = lane; idx < nm * nm + nm; idx += kWave) {
+    if (idx < nm * nm) {
+      const int a = idx / nm, b = idx % nm;
+      if (a == 0 || a > b) continue;
+      const uint64_t hia = L.ccount[kBins + a], hib = L.ccount[kBins + b];
+      const uint64_t ca = L.ccount[a] + hia, cb = L.ccount[b] + hib;
+      const uint64_t pairs = a == b ? ca * (ca - 1) / 2 - hia * (hia - 1) / 2 : ca * cb - hia * hib;
+      const uint64_t adj = a == b ? L.adj[a * kBins + a] : L.adj[a * kBins + b] + L.adj[b * kBins + a];
+      const int base = code_tr | (s >= 2 ? a << fx : 0);
+      if (pairs - adj) add_class(base | (b << fy), pairs - adj);
+      if (adj) add_class(base | ((b | nm) << fy), adj);
+    } else {
+      const int a = idx - nm * nm;
+      const uint64_t h = a ? static_cast<uint64_t>(L.nw[a]) : 0;
+      if (h) add_class(code_tr | (s >= 2 ? a << fx : 0) | (nm << fy), h);
     }
   }
   wave_sync();
+  return hi;
 }
 
 // index of the first canonical entry of level s in [from, to), or -1
@@ -282,7 +366,7 @@ __device__ __forceinline__ int next_canonical(const MotifArgs& A, const MotifLds
   return -1;
 }
 
-__device__ void run_task(const MotifArgs& A, const MotifLds& L, MotifWave& MW, const Task& t, int wave_gid) {
+__device__ __forceinline__ void run_task(const MotifArgs& A, const MotifLds& L, MotifWave& MW, const Task& t, int wave_gid) {
   const int lane = lane_id();
   const int k = A.k;
   const int v0 = t.root;
@@ -292,18 +376,19 @@ __device__ void run_task(const MotifArgs& A, const MotifLds& L, MotifWave& MW, c
     MW.cur_g = g;
   }
   uint64_t nodes_l = 0, leaves_l = 0, reads_l = 0;
-  // ---- level 1: N(v0), every entry adjacent to v_0
+  // ---- level 1: the neighbours of v0 above v0 (a suffix of its sorted list)
   const int64_t b0 = A.rp[v0];
   const int d0 = static_cast<int>(A.rp[v0 + 1] - b0);
+  const int skip = uni(lower_bound_g(A.col + b0, d0, v0 + 1));
   {
     int32_t* E1 = MW.vert + A.level_off[1];
     uint8_t* M1 = MW.mask + A.level_off[1];
-    for (int i = lane; i < d0; i += kWave) {
-      E1[i] = A.col[b0 + i];
+    for (int i = lane; i < d0 - skip; i += kWave) {
+      E1[i] = A.col[b0 + skip + i];
       M1[i] = 1;
     }
     if (lane == 0) {
-      L.esize[1] = d0;
+      L.esize[1] = d0 - skip;
       L.tr[0] = v0;
       L.code[1] = 0;
       L.sufmax[1 * kSuf + 0] = -1;
@@ -328,23 +413,8 @@ __device__ void run_task(const MotifArgs& A, const MotifLds& L, MotifWave& MW, c
   const int s0 = t.depth;
   const int hi0 = t.hi < L.esize[s0] ? t.hi : L.esize[s0];
 
-  auto leaf_parent = [&](int s, int from, int to) {
-    int c = from;
-    while (true) {
-      const int idx = next_canonical(A, L, MW, s, c, to);
-      if (idx < 0) break;
-      const int x = MW.vert[A.level_off[s] + idx];
-      if (lane == 0) {
-        nodes_l += 1;
-        reads_l += static_cast<uint64_t>(A.rp[x + 1] - A.rp[x]);
-      }
-      leaf_count(A, L, MW, s, idx, x, leaves_l);
-      c = idx + 1;
-    }
-  };
-
   if (s0 == k - 2) {
-    leaf_parent(s0, t.lo, hi0);
+    leaf_level(A, L, MW, s0, t.lo, hi0, t, wave_gid, nodes_l, leaves_l, reads_l);
   } else if (hi0 > t.lo) {
     int s = s0;
     if (lane == 0) { L.cursor[s] = t.lo; L.endv[s] = hi0; }
@@ -365,7 +435,7 @@ __device__ void run_task(const MotifArgs& A, const MotifLds& L, MotifWave& MW, c
       }
       extend_level(A, L, MW, s, idx, x);
       if (s + 1 == k - 2) {
-        leaf_parent(s + 1, 0, L.esize[s + 1]);
+        leaf_level(A, L, MW, s + 1, 0, L.esize[s + 1], t, wave_gid, nodes_l, leaves_l, reads_l);
       } else {
         ++s;
         if (lane == 0) { L.cursor[s] = 0; L.endv[s] = L.esize[s]; }
@@ -408,7 +478,7 @@ __global__ void __launch_bounds__(64) motif_kernel(MotifArgs A) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int lane = lane_id();
   const int wave_gid = blockIdx.x;
-  MotifLds L = carve(smem, A.ncls, A.k);
+  MotifLds L = carve(smem, A.ncls);
   MotifWave MW;
   MW.cur_g = -1;
   MW.ovf = 0;
@@ -420,46 +490,15 @@ __global__ void __launch_bounds__(64) motif_kernel(MotifArgs A) {
   for (int c = lane; c < A.ncls; c += kWave) L.cnt[c] = 0;
   wave_sync();
   const uint64_t t_begin = wall_clock64();
-  uint64_t t_idle = 0;
-  if (lane == 0) add_u64(A.S.state, kActiveOne);
-  int64_t b, e;
-  while (sched_grab(A.S, &b, &e)) {
-    for (int64_t q = b; q < e; ++q) {
-      Task t = sched_entry(A.S, q, INT_MAX);
-      run_task(A, L, MW, t, wave_gid);
-      MW.tasks++;
-    }
+  SchedIter it;
+  sched_begin(A.S, it);
+  Task t;
+  while (sched_next(A.S, it, wave_gid, L.tr, &t)) {
+    run_task(A, L, MW, t, wave_gid);
+    MW.tasks++;
   }
-  if (lane == 0) {
-    add_i32(A.S.idle, 1);
-    add_u64(A.S.state, 0ull - kActiveOne);
-  }
-  if (A.S.donate) {
-    uint64_t t0 = wall_clock64();
-    for (;;) {
-      unsigned long long st = 0;
-      if (lane == 0) st = ld_relaxed_u64(A.S.state);
-      st = uniu64(st);
-      if (st == 0) break;
-      int data = 0;
-      if ((st & 0xffffffffull) != 0 && sched_take(A.S, &data, wave_gid)) {
-        t_idle += wall_clock64() - t0;
-        if (lane == 0) add_i32(A.S.idle, -1);
-        Task t = task_unpack(data, L.tr);
-        run_task(A, L, MW, t, wave_gid);
-        MW.tasks++;
-        if (lane == 0) {
-          add_i32(A.S.idle, 1);
-          add_u64(A.S.state, 0ull - kActiveOne);
-        }
-        t0 = wall_clock64();
-        continue;
-      }
-      __builtin_amdgcn_s_sleep(16);
-    }
-    t_idle += wall_clock64() - t0;
-  }
-  if (lane == 0) add_i32(A.S.idle, -1);
+  sched_end(A.S);
+  const uint64_t t_idle = it.t_idle;
   flush_counts(A, L, MW);
   if (lane == 0 && MW.ovf) atomicOr(A.flags, 1);
   if (A.wave_stats && wave_gid < A.wave_stats_len && lane == 0) {
@@ -475,9 +514,12 @@ __global__ void __launch_bounds__(64) motif_kernel(MotifArgs A) {
 }  // namespace
 
 size_t motif_lds_bytes(int k, int ncls) {
-  size_t off = static_cast<size_t>(ncls) * 8 + static_cast<size_t>(1 << (k - 1)) * 4;
-  off += kSuf * 4 * 2 + kSuf * kSuf * 4 + kSuf * 4 * 3 + 16;
-  return (off + 15) & ~static_cast<size_t>(15);
+  (void)k;
+  auto a16 = [](size_t x) { return (x + 15) & ~static_cast<size_t>(15); };
+  size_t off = a16(static_cast<size_t>(ncls) * 8) + a16(kBins * kBins * 8) + a16(kBins * 8) + a16(2 * kBins * 4);
+  off += a16((kWave + 1) * 8) + a16(kWave * 8) + a16(kWave * 4);
+  off += 2 * a16(kSuf * 4) + a16(kSuf * kSuf * 4) + 3 * a16(kSuf * 4);
+  return off;
 }
 
 hipError_t motif_occupancy(size_t lds_bytes, int* blocks_per_cu) {

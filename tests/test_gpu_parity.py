@@ -235,6 +235,31 @@ def test_schedule_invariance_motifs():
             assert np.array_equal(dm.count_motifs(h, k, **s), ref), (k, s)
 
 
+def test_range_donation_runs_every_root_once():
+    """Chunks far larger than n / waves: a few waves take the whole queue and
+    hand untried entry ranges to idle waves.  Counts and per-root records equal
+    the oracle's, so every root ran exactly once."""
+    import torch
+    g = gg.chung_lu(6000, 36000, 2.2, 300.0, 13)[0]
+    h = dm.load_graph(g)
+    for k in (3, 5):
+        tot, leaves, nodes, reads = O.clique_count(g, k, per_root=True, threads=8)
+        for chunk in (1500, 6000):
+            ws = torch.zeros(256 * 32 * 4, dtype=torch.int64, device="cuda")
+            stats = torch.zeros((g.n, 3), dtype=torch.int64, device="cuda")
+            assert dm.count_cliques(h, k, chunk=chunk, root_stats=stats, wave_stats=ws) == tot, (k, chunk)
+            st = stats.cpu().numpy().astype(np.uint64)
+            assert np.array_equal(st[:, 0], nodes) and np.array_equal(st[:, 1], leaves) and np.array_equal(st[:, 2], reads)
+            w = ws.view(-1, 4).cpu().numpy()
+            assert (w[:, 3] > 0).sum() > 4, "no entry range was handed over"
+    ref, ml, mn, _ = O.motif_count(g, 4, per_root=True, threads=8)
+    for chunk in (1500, 6000):
+        stats = torch.zeros((g.n, 3), dtype=torch.int64, device="cuda")
+        assert np.array_equal(dm.count_motifs(h, 4, chunk=chunk, root_stats=stats), ref), chunk
+        st = stats.cpu().numpy().astype(np.uint64)
+        assert np.array_equal(st[:, 0], mn) and np.array_equal(st[:, 1], ml)
+
+
 def test_root_lists_partition_the_count():
     g = gg.chung_lu(4000, 16000, 2.2, 80.0, 11)[0]
     h = dm.load_graph(g)
