@@ -113,8 +113,9 @@ def idle_fraction(ws):
     return float(w[:, 1].sum() / tot) if tot > 0 else 0.0
 
 
-def train_model(make_graph, seeds, op, k, epochs, batch=4096, lr=1e-3):
-    """Record per-root tree sizes with the plain kernel on `seeds`, train the MLP on the GPU."""
+def train_model(make_graph, seeds, op, k, epochs, batch=4096, lr=1e-3, sample=1.0):
+    """Record per-root tree sizes with the plain kernel on `seeds` (on a seeded
+    `sample` fraction of each graph's roots), then train the MLP on the GPU."""
     import torch
     from paper_2212_04551_amd import dm
     feats, targets = [], []
@@ -122,14 +123,22 @@ def train_model(make_graph, seeds, op, k, epochs, batch=4096, lr=1e-3):
     for sd in seeds:
         g = make_graph(sd)
         h = dm.load_graph(g)
-        stats = torch.zeros((g.n, 3), dtype=torch.int64, device="cuda")
+        roots = None
+        if sample < 1.0:
+            roots = np.sort(np.random.default_rng(1000 + sd).choice(g.n, max(1, int(g.n * sample)),
+                                                                     replace=False)).astype(np.int32)
+        rows = g.n if roots is None else len(roots)
+        stats = torch.zeros((rows, 3), dtype=torch.int64, device="cuda")
         if op == "motif":
-            dm.count_motifs(h, k, root_stats=stats)
+            dm.count_motifs(h, k, root_stats=stats, roots=roots)
         else:
-            dm.count_cliques(h, k, root_stats=stats)
-        feats.append(dm.features(h))
+            dm.count_cliques(h, k, root_stats=stats, roots=roots)
+        F = dm.features(h)
+        if roots is not None:
+            F = F[torch.from_numpy(roots.astype(np.int64)).cuda()].contiguous()
+        feats.append(F)
         targets.append(dm.mlp_targets(stats))
-        log(f"recorded seed {sd}: n={g.n}")
+        log(f"recorded seed {sd}: n={g.n} roots={rows} ({time.perf_counter() - t0:.1f}s)")
     t_rec = time.perf_counter() - t0
     F = torch.cat(feats)
     T = torch.cat(targets)
@@ -141,8 +150,8 @@ def train_model(make_graph, seeds, op, k, epochs, batch=4096, lr=1e-3):
     pred = dm.mlp_forward(p, F).cpu().numpy()
     corr = float(np.corrcoef(pred, T.cpu().numpy())[0, 1])
     log(f"trained: rows={F.shape[0]} loss {hist[0]:.3f} -> {hist[-1]:.3f} corr={corr:.3f}")
-    return p, {"rows": int(F.shape[0]), "record_s": t_rec, "train_s": t_train, "epochs": epochs,
-               "loss_first": float(hist[0]), "loss_last": float(hist[-1]), "train_corr": corr}
+    return p, {"rows": int(F.shape[0]), "root_sample": sample, "record_s": t_rec, "train_s": t_train,
+               "epochs": epochs, "loss_first": float(hist[0]), "loss_last": float(hist[-1]), "train_corr": corr}
 
 
 # ---------------------------------------------------------------- workloads
@@ -253,48 +262,51 @@ def wl_cl100k_learned(args):
     from paper_2212_04551_amd import dm
     from paper_2212_04551_amd import graphgen as gg
 
-    caps = {5: 200.0, 6: 80.0}
+    # weight caps: sqrt(2m) for k = 5; for k = 6 a cap that keeps the total near 1e13
+    caps = {5: 1414.0, 6: 120.0}
     results = {}
     total_plain = total_learned = 0.0
     subgraphs = 0
     for k, cap in caps.items():
         make = lambda sd, cap=cap: gg.chung_lu(100_000, 1_000_000, 2.3, cap, sd)[0]
-        model, tinfo = train_model(make, range(1, 11), "motif", k, epochs=args.epochs)
+        model, tinfo = train_model(make, range(1, 11), "motif", k, epochs=args.epochs, sample=0.1)
         g = make(0)
         rp = torch.from_numpy(g.row_ptr).cuda()
         col = torch.from_numpy(g.col).cuda()
         ws = torch.zeros(256 * 32 * 4, dtype=torch.int64, device="cuda")
+        warm_roots = np.arange(0, g.n, 100, dtype=np.int32)
 
-        def run(sched, mlp=None, ws=None):
+        def run(sched, mlp=None, roots=None):
             def step():
                 h = dm.load_csr(g.n, rp, col, device=True)
-                c = dm.count_motifs(h, k, sched=sched, mlp=mlp, wave_stats=ws)
+                c = dm.count_motifs(h, k, sched=sched, mlp=mlp, wave_stats=ws, roots=roots)
                 h.close()
                 return c
             return step
 
-        cp, ms_plain = timed_steps(run(dm.DM_SCHED_PLAIN), args.steps, args.warmup, f"motif k={k} plain")
-        cl, ms_learned = timed_steps(run(dm.DM_SCHED_LEARNED, model), args.steps, args.warmup, f"motif k={k} learned")
-        assert np.array_equal(cp, cl), "learned ordering changed a count"
+        # each full run takes about a minute or more: one warm-up on a 1% root
+        # sample, then single timed runs (idle fractions from the same runs)
+        run(dm.DM_SCHED_PLAIN, roots=warm_roots)()
         ws.zero_()
-        run(dm.DM_SCHED_PLAIN, ws=ws)()
+        cp, ms_plain = timed_steps(run(dm.DM_SCHED_PLAIN), 1, 0, f"motif k={k} plain")
         idle_plain = idle_fraction(ws)
         ws.zero_()
-        run(dm.DM_SCHED_LEARNED, model, ws)()
+        cl, ms_learned = timed_steps(run(dm.DM_SCHED_LEARNED, model), 1, 0, f"motif k={k} learned")
         idle_learned = idle_fraction(ws)
-        ws.zero_()
-        run(dm.DM_SCHED_PLAIN | dm.DM_NO_DONATION, ws=ws)()
-        idle_static = idle_fraction(ws)
+        assert np.array_equal(cp, cl), "learned ordering changed a count"
         n_sub = int(cp.sum())
-        results[str(k)] = {"weight_cap": cap, "subgraphs": n_sub, "plain_ms": ms_plain, "learned_ms": ms_learned,
-                           "speedup": ms_plain / ms_learned, "idle_plain": idle_plain,
-                           "idle_learned": idle_learned, "idle_no_donation": idle_static, "training": tinfo}
+        results[str(k)] = {"weight_cap": cap, "max_degree": int(g.degrees().max()), "subgraphs": n_sub,
+                           "plain_ms": ms_plain, "learned_ms": ms_learned, "speedup": ms_plain / ms_learned,
+                           "idle_plain": idle_plain, "idle_learned": idle_learned, "training": tinfo,
+                           "counts": [int(x) for x in cp]}
+        log(f"k={k}: {n_sub} subgraphs, plain {ms_plain:.0f} ms, learned {ms_learned:.0f} ms")
         total_plain += ms_plain
         total_learned += ms_learned
         subgraphs += n_sub
-    out = base_record(subgraphs / (total_learned / 1e3), total_learned, args.steps, args.warmup,
-                      "induced k-motif counting k=5 (cap 200) and k=6 (cap 80), Chung-Lu n=1e5 m=1e6 gamma=2.3 "
-                      "seed 0, learned ordering (MLP trained on seeds 1..10) vs plain",
+    out = base_record(subgraphs / (total_learned / 1e3), total_learned, 1, 0,
+                      "induced k-motif counting k=5 (weight cap 1414) and k=6 (weight cap 120), Chung-Lu n=1e5 m=1e6 "
+                      "gamma=2.3 seed 0, learned ordering (MLP trained on 10% root samples of seeds 1..10) vs plain; "
+                      "single timed runs",
                       {"per_k": results, "plain_value": subgraphs / (total_plain / 1e3),
                        "speedup_learned_vs_plain": total_plain / total_learned})
     return out

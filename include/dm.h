@@ -174,6 +174,11 @@ dm_status dm_batch(dm_graph* const* gs, int32_t num_graphs, int op, int k, uint6
  * count) to log(1 + enumeration-tree nodes of the root).  Parameter blob
  * (device, DM_MLP_NPARAMS floats): W1[64][4], b1[64], W2[64][64], b2[64],
  * w3[64], b3, then feature mean[4] and std[4] of log1p(feature).
+ * With DM_SCHED_LEARNED the queue is sorted by predicted size, longest
+ * first, and cut into chunks of about equal predicted cost (exp of the
+ * prediction per root).  The queue is cached on the graph handle and rebuilt
+ * when a 64-bit fingerprint of the parameter blob (computed on the device at
+ * every call), the grid or the chunk count changes.
  * All pointers below are device pointers unless stated; calls synchronise
  * `stream` before returning.
  * ------------------------------------------------------------------------- */

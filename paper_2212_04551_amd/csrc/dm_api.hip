@@ -266,10 +266,16 @@ struct dm_graph {
   bool ranked = false;
   Buf urp, ucol;
   // workspace reused across calls
-  Buf ctrl, out, rows, ext_vert, ext_mask, newbuf, qroot, qstat, qlo, qhi, qbounds, rgraph;
-  // learned ordering: features (cached), predictions, LPT order
+  Buf ctrl, out, rows, ext_vert, ext_mask, newbuf, qroot, qstat, qlo, qhi, rgraph;
+  // learned ordering: features (cached), predictions, LPT order, chunk starts
+  // and the order in rank space; the queue is reused while the parameter
+  // fingerprint, grid and chunks per wave stay the same
   bool feat_ready = false;
-  Buf feat, pred, lorder;
+  Buf feat, pred, lorder, lqroot, lqbounds, lqkey;
+  bool lq_valid = false;
+  unsigned long long lq_key = 0;
+  int lq_grid = 0, lq_per_wave = 0;
+  int64_t lq_nchunks = 0;
   hipStream_t own = nullptr;
 };
 
@@ -576,23 +582,43 @@ dm_status ensure_features(dm_graph* g, hipStream_t s) {
 }
 
 // Learned queue: MLP prediction of every root's tree size, longest first,
-// chunks of about equal predicted cost (`chunk` chunks per wave, default 8).
-// A wave hands the untried part of a chunk to idle waves, so a mispredicted
-// chunk does not stall the launch.
-// On return g->lorder holds vertex ids in queue order and g->qbounds the chunk
-// starts (+ n).
+// chunks of about equal predicted cost (`chunk` chunks per wave, default 8),
+// each of at most ceil(n / chunks) roots.  A wave hands the untried part of a
+// chunk to idle waves, so a mispredicted chunk does not stall the launch.
+// On return g->lqroot holds the queue in rank space, g->lorder the original
+// ids (root_stats rows) and g->lqbounds the chunk starts (+ n).  The queue is
+// cached on the handle and rebuilt when the parameters' fingerprint, the grid
+// or the chunk count change.
 dm_status learned_queue(dm_graph* g, const Opt& o, int grid, hipStream_t s, int64_t* nchunks) {
   dm_status st = ensure_features(g, s);
   if (st != DM_OK) return st;
   const size_t n = static_cast<size_t>(g->n > 0 ? g->n : 1);
+  HIP_OR_RETURN(g->lqkey.ensure(sizeof(unsigned long long)), "learned: allocate");
+  HIP_OR_RETURN(param_fingerprint(o.mlp, kMlpBlob, g->lqkey.as<unsigned long long>(), s), "learned: fingerprint");
+  unsigned long long key = 0;
+  HIP_OR_RETURN(hipMemcpyAsync(&key, g->lqkey.p, sizeof(key), hipMemcpyDeviceToHost, s), "learned: fingerprint");
+  HIP_OR_RETURN(hipStreamSynchronize(s), "learned: fingerprint");
+  const int per_wave = o.chunk ? static_cast<int>(o.chunk) : 8;
+  if (g->lq_valid && key == g->lq_key && grid == g->lq_grid && per_wave == g->lq_per_wave) {
+    *nchunks = g->lq_nchunks;
+    return DM_OK;
+  }
+  g->lq_valid = false;
   HIP_OR_RETURN(g->pred.ensure(sizeof(float) * n), "learned: allocate");
   HIP_OR_RETURN(g->lorder.ensure(sizeof(int32_t) * n), "learned: allocate");
-  HIP_OR_RETURN(g->qbounds.ensure(sizeof(int64_t) * (n + 1)), "learned: allocate");
+  HIP_OR_RETURN(g->lqroot.ensure(sizeof(int32_t) * n), "learned: allocate");
+  HIP_OR_RETURN(g->lqbounds.ensure(sizeof(int64_t) * (n + 1)), "learned: allocate");
   HIP_OR_RETURN(mlp_forward(o.mlp, g->feat.as<int64_t>(), g->n, g->pred.as<float>(), s), "learned: forward");
-  const int per_wave = o.chunk ? static_cast<int>(o.chunk) : 8;
-  HIP_OR_RETURN(lpt_order(g->pred.as<float>(), g->n, grid * per_wave, g->lorder.as<int32_t>(), g->qbounds.as<int64_t>(),
-                          nchunks, s),
+  HIP_OR_RETURN(lpt_order(g->pred.as<float>(), g->n, grid * per_wave, g->lorder.as<int32_t>(),
+                          g->lqbounds.as<int64_t>(), nchunks, s),
                 "learned: order");
+  HIP_OR_RETURN(launch_gather_i32(g->rank.as<int32_t>(), g->lorder.as<int32_t>(), g->lqroot.as<int32_t>(), g->n, s),
+                "learned: rank map");
+  g->lq_valid = true;
+  g->lq_key = key;
+  g->lq_grid = grid;
+  g->lq_per_wave = per_wave;
+  g->lq_nchunks = *nchunks;
   return DM_OK;
 }
 
@@ -613,12 +639,9 @@ dm_status build_queue(dm_graph* g, const Opt& o, int grid, hipStream_t s, Sched*
     int64_t nchunks = 0;
     dm_status st = learned_queue(g, o, grid, s, &nchunks);
     if (st != DM_OK) return st;
-    HIP_OR_RETURN(g->qroot.ensure(sizeof(int32_t) * static_cast<size_t>(g->n > 0 ? g->n : 1)), "workspace");
-    HIP_OR_RETURN(launch_gather_i32(g->rank.as<int32_t>(), g->lorder.as<int32_t>(), g->qroot.as<int32_t>(), g->n, s),
-                  "learned: rank map");
-    S->qroot = g->qroot.as<int32_t>();
+    S->qroot = g->lqroot.as<int32_t>();
     S->qstat = g->lorder.as<int32_t>();
-    S->qbounds = g->qbounds.as<int64_t>();
+    S->qbounds = g->lqbounds.as<int64_t>();
     S->nchunks = nchunks;
   }
   return DM_OK;

@@ -98,6 +98,7 @@ hipError_t mlp_adam(float* P, const float* g, float* m, float* v, int64_t t, flo
 hipError_t mlp_shuffle(uint64_t seed, int64_t n, unsigned long long* keys, unsigned long long* keys_out,
                        int32_t* vals, int32_t* vals_out, void* temp, size_t temp_bytes, hipStream_t s);
 size_t mlp_shuffle_temp_bytes(int64_t n);
+hipError_t param_fingerprint(const float* P, int n, unsigned long long* dev_out, hipStream_t s);
 hipError_t lpt_order(const float* pred, int64_t n, int chunks_wanted, int32_t* order_out, int64_t* bounds_out,
                      int64_t* nchunks, hipStream_t s);
 

@@ -345,14 +345,17 @@ __global__ void iota_kernel(int32_t* out, int64_t n) {
 __global__ void cost_kernel(const float* pred_sorted, int64_t n, double* cost) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) {
-    const double c = expm1(static_cast<double>(pred_sorted[i]));
-    cost[i] = c > 0.0 ? c : 0.0;
+    // predicted tree nodes + the root itself: exp(log1p(nodes))
+    cost[i] = exp(static_cast<double>(pred_sorted[i]));
   }
 }
 
 // chunk id of entry i = floor(exclusive prefix / target); entry i starts a
-// chunk when its id differs from entry i-1 (ids are non-decreasing)
-__global__ void chunk_flag_kernel(const double* incl, const double* cost, int64_t n, double target, int32_t* flag) {
+// chunk when its id differs from entry i-1 (ids are non-decreasing), and every
+// `max_roots` entries, so the many light roots at the end of the order never
+// form one long chunk
+__global__ void chunk_flag_kernel(const double* incl, const double* cost, int64_t n, double target,
+                                  int64_t max_roots, int32_t* flag) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   if (i == 0) {
@@ -361,7 +364,7 @@ __global__ void chunk_flag_kernel(const double* incl, const double* cost, int64_
   }
   const double a = floor((incl[i - 1] - cost[i - 1]) / target);
   const double b = floor((incl[i] - cost[i]) / target);
-  flag[i] = b > a ? 1 : 0;
+  flag[i] = (b > a || i % max_roots == 0) ? 1 : 0;
 }
 
 __global__ void to_i64_kernel(const int32_t* in, int64_t n, int64_t* out, int64_t tail) {
@@ -480,6 +483,34 @@ size_t mlp_shuffle_temp_bytes(int64_t n) {
   return need;
 }
 
+// Order-sensitive 64-bit fingerprint of a parameter blob (the cache key of a
+// graph's learned queue; not a cryptographic hash).  One block of 256.
+__global__ void param_hash_kernel(const float* P, int n, unsigned long long* out) {
+  __shared__ unsigned long long part[256];
+  unsigned long long h = 0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    uint64_t x = (static_cast<uint64_t>(__float_as_uint(P[i])) << 32) ^ (static_cast<uint64_t>(i) * 0x9E3779B97F4A7C15ull);
+    x ^= x >> 30;
+    x *= 0xBF58476D1CE4E5B9ull;
+    x ^= x >> 27;
+    x *= 0x94D049BB133111EBull;
+    x ^= x >> 31;
+    h += x;
+  }
+  part[threadIdx.x] = h;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (static_cast<int>(threadIdx.x) < st) part[threadIdx.x] += part[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = part[0];
+}
+
+hipError_t param_fingerprint(const float* P, int n, unsigned long long* dev_out, hipStream_t s) {
+  hipLaunchKernelGGL(param_hash_kernel, dim3(1), dim3(256), 0, s, P, n, dev_out);
+  return hipGetLastError();
+}
+
 // Longest-predicted-first order and equal-predicted-cost chunks.
 // order_out[i] = vertex at queue position i; bounds_out gets chunk starts and
 // a final n (size n+1 at most); returns the chunk count in *nchunks.
@@ -534,7 +565,9 @@ hipError_t lpt_order(const float* pred, int64_t n, int chunks_wanted, int32_t* o
     const int cw = chunks_wanted > 0 ? chunks_wanted : 1;
     double target = total / static_cast<double>(cw);
     if (!(target > 0.0)) target = 1e300;  // no predicted cost: one chunk
-    hipLaunchKernelGGL(chunk_flag_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, incl, cost, n, target, flag);
+    const int64_t max_roots = (n + cw - 1) / cw;
+    hipLaunchKernelGGL(chunk_flag_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, incl, cost, n, target,
+                       max_roots, flag);
     LPT_TRY(hipGetLastError());
   }
   hipLaunchKernelGGL(iota_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, ids, n);

@@ -62,6 +62,9 @@ constexpr int kMotifMaxK = 7;
 constexpr int kSuf = kMotifMaxK + 1;
 
 constexpr int kBins = 16;  // masks of a (k-2)-traversal entry, k <= 6
+// A leaf-level range is donated only when this many entries are untried: the
+// taker re-extends the whole prefix first.
+constexpr int kLeafDonateMin = 128;
 
 struct MotifLds {
   unsigned long long* cnt;  // [ncls] class counters of the current graph
@@ -294,7 +297,7 @@ __device__ __forceinline__ int leaf_level(const MotifArgs& A, const MotifLds& L,
     wave_sync();
     // ---- donation of the untried x range
     const int next = c + kWave;
-    if (A.S.donate && hi - next >= 2 && sched_want_donation(A.S)) {
+    if (A.S.donate && hi - next >= kLeafDonateMin && sched_want_donation(A.S)) {
       const int mid = next + (hi - next + 1) / 2;
       const int pay = task_payload(t.root, t.stat, s, mid, hi, L.tr);
       if (sched_publish(A.S, pay, wave_gid)) hi = mid;

@@ -143,3 +143,31 @@ def test_training_lowers_loss_and_learned_counts_are_exact():
     with pytest.raises(dm.DMError) as e:
         dm.count_cliques(h, 4, sched=dm.DM_SCHED_LEARNED, mlp=p, roots=np.arange(10))
     assert e.value.status == dm.DM_E_ARG
+
+
+def test_learned_queue_cache_follows_parameter_changes():
+    """The learned queue is cached on the handle; changing the parameters in
+    place, the grid or the chunk count rebuilds it.  Counts and per-root
+    records (indexed by vertex) stay exact every time."""
+    import torch
+    g = gg.chung_lu(3000, 15000, 2.2, 200.0, 31)[0]
+    h = dm.load_graph(g)
+    tot, leaves, nodes, reads = O.clique_count(g, 4, per_root=True, threads=8)
+    F = dm.features(h)
+    p = dm.mlp_new(1)
+    dm.mlp_fit_normalizer(p, F)
+
+    def check(**kw):
+        stats = torch.zeros((g.n, 3), dtype=torch.int64, device="cuda")
+        assert dm.count_cliques(h, 4, sched=dm.DM_SCHED_LEARNED, mlp=p, root_stats=stats, **kw) == tot, kw
+        st = stats.cpu().numpy().astype(np.uint64)
+        assert np.array_equal(st[:, 0], nodes) and np.array_equal(st[:, 1], leaves) and np.array_equal(st[:, 2], reads)
+
+    check()
+    check()                      # cached queue
+    p.copy_(dm.mlp_new(2))       # same pointer, new parameters
+    dm.mlp_fit_normalizer(p, F)
+    check()
+    check(chunk=3)
+    check(waves_per_cu=1)
+    assert np.array_equal(dm.count_motifs(h, 4, sched=dm.DM_SCHED_LEARNED, mlp=p), O.motif_count(g, 4, threads=8))
