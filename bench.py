@@ -27,7 +27,7 @@ KS = (3, 4, 5, 6, 7, 8)
 # HBM bytes of the k=8 clique_kernel launch from rocprofv3 (2.0 x FETCH_SIZE +
 # 1.0 x WRITE_SIZE, factors from a copy kernel of known size), valid only for
 # the kernel source they were taken on.
-TRAFFIC = {"source_sha": "5d8bbc1641203636", "bytes_per_launch": 2.0 * 4567693.9375 * 1024 + 57693.5625 * 1024}
+TRAFFIC = {"source_sha": "85891e85cfc5a20f", "bytes_per_launch": 2.0 * 4536160.1875 * 1024 + 61021.75 * 1024}
 
 
 def kernel_source_sha() -> str:
