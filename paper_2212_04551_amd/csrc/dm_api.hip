@@ -507,7 +507,6 @@ struct Prepared {
   CliqueArgs ca;
   MotifArgs ma;
   int grid = 0;
-  bool rows_lds = true;
   size_t lds = 0;
   int64_t nq = 0;
   size_t out_count = 0;
@@ -537,7 +536,7 @@ hipError_t enqueue(const Prepared& P, hipStream_t s, uint64_t* host_out, int* ho
   if (e == hipSuccess) e = launch_fill_u64(P.out_dev, static_cast<int64_t>(P.out_count), P.bias, s);
   if (e == hipSuccess && P.stats) e = launch_fill_u64(P.stats, P.stats_words, 0ull, s);
   if (e == hipSuccess && P.nq > 0)
-    e = P.clique ? launch_clique(P.ca, P.grid, P.rows_lds, P.lds, s) : launch_motif(P.ma, P.grid, P.lds, s);
+    e = P.clique ? launch_clique(P.ca, P.grid, P.lds, s) : launch_motif(P.ma, P.grid, P.lds, s);
   if (e == hipSuccess)
     e = hipMemcpyAsync(host_out, P.out_dev, sizeof(uint64_t) * P.out_count, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipMemcpyAsync(host_flags, P.flags_dev, 2 * sizeof(int), hipMemcpyDeviceToHost, s);
@@ -664,21 +663,17 @@ dm_status prepare_clique(dm_graph* g, int k, const Opt& o, hipStream_t s, const 
   if (st != DM_OK) return st;
   const int dmax = g->ddmax > 0 ? g->ddmax : 1;
   const int W = (dmax + 63) / 64;
-  bool rows_lds = true;
-  size_t lds = clique_lds_bytes(dmax, W, k, true);
-  if (lds > 64 * 1024) {
-    rows_lds = false;
-    lds = clique_lds_bytes(dmax, W, k, false);
-  }
+  const size_t lds = clique_lds_bytes(dmax, W, k);
   if (lds > 160 * 1024) return fail(DM_E_NOMEM, "maximum out-degree too large for the LDS stack");
   int per_cu = 0;
-  HIP_OR_RETURN(clique_occupancy(rows_lds, lds, &per_cu), "occupancy");
+  HIP_OR_RETURN(clique_occupancy(lds, &per_cu), "occupancy");
   if (per_cu < 1) per_cu = 1;
   if (o.waves_per_cu && static_cast<int>(o.waves_per_cu) < per_cu) per_cu = static_cast<int>(o.waves_per_cu);
   const int grid = per_cu * cu_count();
   HIP_OR_RETURN(g->ctrl.ensure(ctrl_bytes()), "workspace");
   HIP_OR_RETURN(g->out.ensure(sizeof(uint64_t) * ngraphs), "workspace");
-  if (!rows_lds) HIP_OR_RETURN(g->rows.ensure(sizeof(uint64_t) * static_cast<size_t>(grid) * W * dmax), "workspace");
+  // rows of roots with more than 128 out-neighbours: one region per wave
+  HIP_OR_RETURN(g->rows.ensure(sizeof(uint64_t) * static_cast<size_t>(grid) * W * dmax), "workspace");
   Sched S = make_sched(g, o, grid, g->n, nullptr, nullptr);
   st = build_queue(g, o, grid, s, &S);
   if (st != DM_OK) return st;
@@ -696,12 +691,11 @@ dm_status prepare_clique(dm_graph* g, int k, const Opt& o, hipStream_t s, const 
   A.root_stats = reinterpret_cast<unsigned long long*>(o.root_stats);
   A.wave_stats = reinterpret_cast<unsigned long long*>(o.wave_stats);
   A.wave_stats_len = static_cast<int>(o.wave_stats_len);
-  A.rows_global = rows_lds ? nullptr : g->rows.as<unsigned long long>();
+  A.rows_global = g->rows.as<unsigned long long>();
   A.prune = o.root_stats ? 0 : 1;
   A.S = S;
   P->clique = true;
   P->grid = grid;
-  P->rows_lds = rows_lds;
   P->lds = lds;
   P->nq = S.nq;
   common_prepare(g, o, P, static_cast<size_t>(ngraphs));
@@ -955,7 +949,7 @@ std::string launch_key(const Prepared& P) {
   std::string key(reinterpret_cast<const char*>(&P.clique), sizeof(P.clique));
   if (P.clique) key.append(reinterpret_cast<const char*>(&P.ca), sizeof(P.ca));
   else key.append(reinterpret_cast<const char*>(&P.ma), sizeof(P.ma));
-  const int64_t tail[] = {P.grid, P.rows_lds, static_cast<int64_t>(P.lds), P.nq, static_cast<int64_t>(P.out_count),
+  const int64_t tail[] = {P.grid, static_cast<int64_t>(P.lds), P.nq, static_cast<int64_t>(P.out_count),
                           static_cast<int64_t>(P.bias), reinterpret_cast<int64_t>(P.stats), P.stats_words};
   key.append(reinterpret_cast<const char*>(tail), sizeof(tail));
   return key;

@@ -34,7 +34,7 @@ namespace dm {
 namespace {
 
 struct CliqueLds {
-  uint64_t* rows;   // [W][dmax] (word-major) when in LDS
+  uint64_t* rows;   // [2][kLocalMax] rows (word-major) of a root with <= kLocalMax out-neighbours
   uint64_t* stk;    // [(k+1)][W] candidate bitsets per traversal size
   int* nbr;         // [dmax] N+(root)
   int* offs;        // [dmax+1] exclusive prefix of |N+(nbr[i])|
@@ -50,11 +50,11 @@ __device__ __forceinline__ size_t align16(size_t x) { return (x + 15) & ~static_
 constexpr int kLocalMax = 128;    // roots with at most this many out-neighbours use their rows in place
 constexpr int kReindexMax = 128;  // larger roots re-index candidate sets of at most this many members
 
-__device__ CliqueLds carve(unsigned char* smem, int dmax, int W, int k, bool rows_lds) {
+__device__ CliqueLds carve(unsigned char* smem, int dmax, int W, int k) {
   CliqueLds L;
   size_t off = 0;
   L.rows = reinterpret_cast<uint64_t*>(smem);
-  if (rows_lds) off += static_cast<size_t>(W) * dmax * 8;
+  off += static_cast<size_t>(2) * kLocalMax * 8;
   off = align16(off);
   L.stk = reinterpret_cast<uint64_t*>(smem + off);
   off += static_cast<size_t>(k + 1) * W * 8;
@@ -115,6 +115,27 @@ __device__ __forceinline__ uint64_t count_in(const uint64_t (&C)[NW], LdsU64* lr
 #pragma unroll
     for (int q = 0; q < NW; ++q) s += static_cast<uint64_t>(__popcll(C[q]));
     return s;
+  } else if constexpr (D == 2) {
+    // edges inside C: two members per iteration, so two row reads are in
+    // flight before their AND / popcount
+    uint32_t s = 0;
+    for (int w = 0; w < NW; ++w) {
+      uint64_t x = pick<NW>(C, w);
+      while (x) {
+        const int a = w * 64 + __builtin_ctzll(x);
+        x &= x - 1;
+        const int b = x ? w * 64 + __builtin_ctzll(x) : a;
+        const uint32_t two = x ? 1u : 0u;
+        x &= x - 1;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) {
+          const uint64_t ra = lr[q * stride + a];
+          const uint64_t rb = lr[q * stride + b];
+          s += static_cast<uint32_t>(__popcll(C[q] & ra)) + two * static_cast<uint32_t>(__popcll(C[q] & rb));
+        }
+      }
+    }
+    return s;
   } else {
     uint64_t s = 0;
     for (int w = 0; w < NW; ++w) {
@@ -132,19 +153,6 @@ __device__ __forceinline__ uint64_t count_in(const uint64_t (&C)[NW], LdsU64* lr
   }
 }
 
-template <int NW>
-__device__ __forceinline__ uint64_t count_in_depth(int D, const uint64_t (&C)[NW], LdsU64* lr, int stride) {
-  switch (D) {
-    case 1: return count_in<1, NW>(C, lr, stride);
-    case 2: return count_in<2, NW>(C, lr, stride);
-    case 3: return count_in<3, NW>(C, lr, stride);
-    case 4: return count_in<4, NW>(C, lr, stride);
-    case 5: return count_in<5, NW>(C, lr, stride);
-    case 6: return count_in<6, NW>(C, lr, stride);
-    default: return 0;
-  }
-}
-
 __device__ __forceinline__ uint64_t range_mask64(int lo, int hi) {
   if (lo < 0) lo = 0;
   if (hi > 64) hi = 64;
@@ -153,10 +161,152 @@ __device__ __forceinline__ uint64_t range_mask64(int lo, int hi) {
   return upper & (~0ull << lo);
 }
 
+typedef __attribute__((address_space(3))) int LdsI32;
+
+// position of the r-th (0-based) set bit of the NW-word set x (r < popcount)
+template <int NW>
+__device__ __forceinline__ int select_nth(const uint64_t (&x)[NW], int r) {
+  int base = 0;
+  uint64_t v = x[0];
+  if constexpr (NW == 2) {
+    const int c0 = __popcll(x[0]);
+    if (r >= c0) {
+      r -= c0;
+      v = x[1];
+      base = 64;
+    }
+  }
+  int pos = 0;
+#pragma unroll
+  for (int width = 32; width >= 1; width >>= 1) {
+    const uint64_t m = (width == 32) ? 0xffffffffull : ((1ull << width) - 1);
+    const int c = __popcll(v & m);
+    if (r >= c) {
+      r -= c;
+      v >>= width;
+      pos += width;
+    }
+  }
+  return base + pos;
+}
+
+// q-cliques, q >= 3, inside C (rows upper-triangular: row i holds members
+// above i) whose first member is in `first`.  The work is split into pair
+// tasks (i, j), j a member of C adjacent to i and above it, numbered by a
+// prefix sum over i (`pst`, 64 * NW ints of LDS).  Every lane runs its own
+// depth-first search below a pair and takes the next task from a wave-shared
+// counter when it is done, so all lanes run the same loop body until the
+// tasks run out.  Returns this lane's share.
+template <int NW>
+__device__ __forceinline__ uint64_t lane_solve(const uint64_t (&C)[NW], const uint64_t (&first)[NW], int q,
+                                               LdsU64* lr, int stride, LdsI32* pst) {
+  const int lane = lane_id();
+  int total = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    const int i = w * 64 + lane;
+    int c = 0;
+    if ((first[w] >> lane) & 1ull) {
+#pragma unroll
+      for (int q2 = 0; q2 < NW; ++q2) c += __popcll(C[q2] & lr[q2 * stride + i]);
+    }
+    const int incl = static_cast<int>(wave_incl_scan_i64(c));
+    pst[i] = total + incl - c;
+    total += uni(read_lane(incl, kWave - 1));
+  }
+  wave_sync();
+  const int r0 = q - 2;  // members still to choose below a pair
+  uint64_t acc = 0;
+  uint64_t cur[NW];
+#pragma unroll
+  for (int w = 0; w < NW; ++w) cur[w] = 0;
+  // per-lane stack of remaining candidate sets, up to 4 levels: four separate
+  // locals written and read through branches on the depth (an array or a
+  // struct would be placed in scratch memory)
+  uint64_t sa0 = 0, sa1 = 0, sb0 = 0, sb1 = 0, sc0 = 0, sc1 = 0, sd0 = 0, sd1 = 0;
+  int d = -1;  // depth below the pair; -1: needs a task
+  bool done = false;
+  int tbase = 0;
+  for (;;) {
+    const bool want = !done && d < 0;
+    const uint64_t wb = ballot(want);
+    // refill in batches: decoding a task costs a binary search and a select,
+    // so lanes wait until a quarter of the wave is free (or none is busy)
+    if (wb && (__popcll(wb) >= kWave / 4 || ballot(d >= 0) == 0)) {
+      if (want) {
+        const int t = tbase + mbcnt(wb);
+        if (t < total) {
+          int i = 0;  // last member whose task range starts at or before t
+#pragma unroll
+          for (int st = 32 * NW; st >= 1; st >>= 1)
+            if (pst[i + st] <= t) i += st;
+          uint64_t ci[NW];
+#pragma unroll
+          for (int q2 = 0; q2 < NW; ++q2) ci[q2] = C[q2] & lr[q2 * stride + i];
+          const int j = select_nth<NW>(ci, t - pst[i]);
+          int cnt = 0;
+#pragma unroll
+          for (int q2 = 0; q2 < NW; ++q2) {
+            cur[q2] = ci[q2] & lr[q2 * stride + j];
+            cnt += __popcll(cur[q2]);
+          }
+          if (r0 == 1) acc += static_cast<uint64_t>(cnt);
+          else if (cnt >= r0) d = 0;
+        } else {
+          done = true;
+        }
+      }
+      tbase += __popcll(wb);
+    }
+    if (ballot(!done) == 0) break;
+    if (d >= 0) {
+      int wsel = -1;
+#pragma unroll
+      for (int w = NW - 1; w >= 0; --w)
+        if (cur[w]) wsel = w;
+      if (wsel >= 0) {
+        const uint64_t cw = pick<NW>(cur, wsel);
+        const int i = wsel * 64 + __builtin_ctzll(cw);
+#pragma unroll
+        for (int w = 0; w < NW; ++w) cur[w] = (w == wsel) ? (cw & (cw - 1)) : cur[w];
+        uint64_t ch[NW];
+        int cnt = 0;
+#pragma unroll
+        for (int q2 = 0; q2 < NW; ++q2) {
+          ch[q2] = cur[q2] & lr[q2 * stride + i];
+          cnt += __popcll(ch[q2]);
+        }
+        const int r = r0 - d;  // members still to choose at this depth, i included
+        if (r == 2) {
+          acc += static_cast<uint64_t>(cnt);
+        } else if (cnt >= r - 1) {
+          const uint64_t c0 = cur[0], c1 = NW == 2 ? pick<NW>(cur, 1) : 0;
+          if (d == 0) { sa0 = c0; sa1 = c1; }
+          else if (d == 1) { sb0 = c0; sb1 = c1; }
+          else if (d == 2) { sc0 = c0; sc1 = c1; }
+          else { sd0 = c0; sd1 = c1; }
+#pragma unroll
+          for (int w = 0; w < NW; ++w) cur[w] = ch[w];
+          ++d;
+        }
+      } else if (d == 0) {
+        d = -1;
+      } else {
+        --d;
+        const uint64_t g0 = d == 0 ? sa0 : (d == 1 ? sb0 : (d == 2 ? sc0 : sd0));
+        const uint64_t g1 = d == 0 ? sa1 : (d == 1 ? sb1 : (d == 2 ? sc1 : sd1));
+        cur[0] = g0;
+        if constexpr (NW == 2) cur[NW - 1] = g1;
+      }
+    }
+  }
+  return acc;
+}
+
 // q-cliques (1 <= q <= kSolverMaxQ) inside the set Cl (NW words) whose first
 // member lies in [lo, hi); returns this lane's share.
 template <int NW>
-__device__ uint64_t small_solve(LdsU64* Cl, int q, LdsU64* lr, int stride, int lo, int hi) {
+__device__ uint64_t small_solve(LdsU64* Cl, int q, LdsU64* lr, int stride, int lo, int hi, LdsI32* pst) {
   const int lane = lane_id();
   uint64_t C[NW], first[NW];
 #pragma unroll
@@ -178,7 +328,8 @@ __device__ uint64_t small_solve(LdsU64* Cl, int q, LdsU64* lr, int stride, int l
         for (int q2 = 0; q2 < NW; ++q2) add += static_cast<uint64_t>(__popcll(C[q2] & lr[q2 * stride + i]));
       }
     }
-  } else {
+  } else if (q <= 4) {
+    // the wave walks the first member i, lane j takes the second member
     for (int w = 0; w < NW; ++w) {
       uint64_t x = pick<NW>(first, w);
       while (x) {
@@ -193,27 +344,30 @@ __device__ uint64_t small_solve(LdsU64* Cl, int q, LdsU64* lr, int stride, int l
             uint64_t Cj[NW];
 #pragma unroll
             for (int q2 = 0; q2 < NW; ++q2) Cj[q2] = Ci[q2] & lr[q2 * stride + j];
-            add += count_in_depth<NW>(q - 2, Cj, lr, stride);
+            add += q == 3 ? count_in<1, NW>(Cj, lr, stride) : count_in<2, NW>(Cj, lr, stride);
           }
         }
       }
     }
+  } else {
+    add = lane_solve<NW>(C, first, q, lr, stride, pst);
   }
   return add;
 }
 
 __device__ __forceinline__ uint64_t small_solve_any(int nw, const uint64_t* Cg, int q, const uint64_t* lrg, int stride,
-                                                    int lo, int hi) {
+                                                    int lo, int hi, int* pstg) {
   LdsU64* C = as_lds(Cg);
   LdsU64* lr = as_lds(lrg);
-  return nw == 1 ? small_solve<1>(C, q, lr, stride, lo, hi) : small_solve<2>(C, q, lr, stride, lo, hi);
+  LdsI32* pst = (LdsI32*)(pstg);
+  return nw == 1 ? small_solve<1>(C, q, lr, stride, lo, hi, pst) : small_solve<2>(C, q, lr, stride, lo, hi, pst);
 }
 
 // Local ids for the members of the multi-word set C (at most kReindexMax, by
 // the caller's check): positions into L.pos, rows (nw words, word-major with
 // stride kReindexMax) into L.lr, and the full local set into L.cset.
 // Returns nw.
-__device__ __forceinline__ int reindex(const uint64_t* C, int Wd, const uint64_t* rows, int dmax, const CliqueLds& L) {
+__device__ __forceinline__ int reindex(const uint64_t* C, int Wd, const uint64_t* rows, int stride, const CliqueLds& L) {
   const int lane = lane_id();
   int base = 0;
   for (int w = 0; w < Wd; ++w) {
@@ -230,7 +384,7 @@ __device__ __forceinline__ int reindex(const uint64_t* C, int Wd, const uint64_t
     uint64_t r0 = 0, r1 = 0;
     for (int bb = a + 1; bb < m; ++bb) {
       const int pb = L.pos[bb];
-      if ((rows[static_cast<size_t>(pb >> 6) * dmax + pa] >> (pb & 63)) & 1ull) {
+      if ((rows[static_cast<size_t>(pb >> 6) * stride + pa] >> (pb & 63)) & 1ull) {
         if (bb < 64) r0 |= 1ull << bb;
         else r1 |= 1ull << (bb - 64);
       }
@@ -304,8 +458,8 @@ __device__ __forceinline__ void flush_graph(const CliqueArgs& A, WaveAcc& W) {
   W.acc = 0;
 }
 
-template <bool ROWS_LDS>
-__device__ void run_task(const CliqueArgs& A, const CliqueLds& L, uint64_t* rows, const Task& t,
+// rows_g: this wave's global region for the rows of roots too wide for LDS
+__device__ void run_task(const CliqueArgs& A, const CliqueLds& L, uint64_t* rows_g, const Task& t,
                          WaveAcc& WA, int wave_gid) {
   const int lane = lane_id();
   const int k = A.k, dmax = A.dmax, W = A.W;
@@ -318,6 +472,11 @@ __device__ void run_task(const CliqueArgs& A, const CliqueLds& L, uint64_t* rows
   const int64_t base = A.rp[v];
   const int d = static_cast<int>(A.rp[v + 1] - base);
   const int hi_t = t.hi < d ? t.hi : d;
+  // rows of N+(v): in LDS (stride kLocalMax) when d <= kLocalMax, else in
+  // this wave's global region (stride dmax)
+  const bool lds_rows = d <= kLocalMax;
+  uint64_t* rows = lds_rows ? L.rows : rows_g;
+  const int rs = lds_rows ? kLocalMax : dmax;
   uint64_t nodes_l = 0, leaves_l = 0, reads_l = 0;  // per-lane partial stats
   if (t.full_root && lane == 0) {
     nodes_l += (k >= 2) ? 1 : 0;
@@ -356,7 +515,7 @@ __device__ void run_task(const CliqueArgs& A, const CliqueLds& L, uint64_t* rows
     const int Wd = (d + 63) >> 6;
     for (int idx = lane; idx < Wd * d; idx += kWave) {
       const int w = idx / d, p = idx - w * d;
-      rows[static_cast<size_t>(w) * dmax + p] = 0ull;
+      rows[static_cast<size_t>(w) * rs + p] = 0ull;
     }
     wave_sync();
     // ---- adjacency of N+(v) restricted to itself, as bitmap rows
@@ -373,7 +532,7 @@ __device__ void run_task(const CliqueArgs& A, const CliqueLds& L, uint64_t* rows
         const int mid = (a + b) >> 1;
         if (L.nbr[mid] < e) a = mid + 1; else b = mid;
       }
-      if (a < d && L.nbr[a] == e) atomicOr(reinterpret_cast<unsigned long long*>(&rows[static_cast<size_t>(a >> 6) * dmax + i]), 1ull << (a & 63));
+      if (a < d && L.nbr[a] == e) atomicOr(reinterpret_cast<unsigned long long*>(&rows[static_cast<size_t>(a >> 6) * rs + i]), 1ull << (a & 63));
     }
     // ---- level-1 candidate set and the task prefix
     for (int w = lane; w < Wd; w += kWave) {
@@ -383,13 +542,13 @@ __device__ void run_task(const CliqueArgs& A, const CliqueLds& L, uint64_t* rows
     wave_sync();
     for (int s = 1; s < t.depth; ++s) {
       const int p = L.cur[s];
-      for (int w = lane; w < Wd; w += kWave) L.stk[(s + 1) * W + w] = L.stk[s * W + w] & rows[static_cast<size_t>(w) * dmax + p];
+      for (int w = lane; w < Wd; w += kWave) L.stk[(s + 1) * W + w] = L.stk[s * W + w] & rows[static_cast<size_t>(w) * rs + p];
       wave_sync();
     }
     // roots with at most 128 out-neighbours: their rows already are local rows
-    // (positions = local ids, Wd <= 2 words, stride dmax)
+    // (positions = local ids, Wd <= 2 words, in LDS with stride kLocalMax)
     const bool solver = A.prune != 0;
-    const bool root_local = ROWS_LDS && solver && d <= kLocalMax;
+    const bool root_local = solver && lds_rows;
     auto add_acc = [&](uint64_t x) {
       const uint64_t before = WA.acc;
       WA.acc += x;
@@ -405,7 +564,7 @@ __device__ void run_task(const CliqueArgs& A, const CliqueLds& L, uint64_t* rows
         const bool on = p >= lo && p < hi && p < d && ((C[w0] >> lane) & 1ull);
         if (on) {
           uint64_t pc = 0;
-          for (int w = w0; w < Wd; ++w) pc += static_cast<uint64_t>(__popcll(C[w] & rows[static_cast<size_t>(w) * dmax + p]));
+          for (int w = w0; w < Wd; ++w) pc += static_cast<uint64_t>(__popcll(C[w] & rows[static_cast<size_t>(w) * rs + p]));
           const uint64_t before = WA.acc;
           WA.acc += pc;
           if (WA.acc < before) WA.ovf = 1;
@@ -438,8 +597,8 @@ __device__ void run_task(const CliqueArgs& A, const CliqueLds& L, uint64_t* rows
       job_nw = Wd;
       job_C = L.stk + s0 * W;
       job_q = k - s0;
-      job_R = rows;
-      job_stride = dmax;
+      job_R = L.rows;
+      job_stride = kLocalMax;
       job_lo = t.lo;
       job_hi = hi_t;
     } else if (s0 == k - 2) {
@@ -454,7 +613,7 @@ __device__ void run_task(const CliqueArgs& A, const CliqueLds& L, uint64_t* rows
     int steps = 0;
     while (depth >= 0) {
       if (job) {
-        add_acc(small_solve_any(job_nw, job_C, job_q, job_R, job_stride, job_lo, job_hi));
+        add_acc(small_solve_any(job_nw, job_C, job_q, job_R, job_stride, job_lo, job_hi, L.pos));
         job = false;
         if (job_last) break;
       }
@@ -487,11 +646,11 @@ __device__ void run_task(const CliqueArgs& A, const CliqueLds& L, uint64_t* rows
       int cnt = 0;
       uint64_t x = 0;
       if (fast) {
-        if (lane < Wd) x = cw & rows[static_cast<size_t>(lane) * dmax + u];
+        if (lane < Wd) x = cw & rows[static_cast<size_t>(lane) * rs + u];
         cnt = uni(wave_sum_i32(__popcll(x)));
       } else {
         for (int w = lane; w < Wd; w += kWave) {
-          const uint64_t y = L.stk[depth * W + w] & rows[static_cast<size_t>(w) * dmax + u];
+          const uint64_t y = L.stk[depth * W + w] & rows[static_cast<size_t>(w) * rs + u];
           L.stk[(depth + 1) * W + w] = y;
           cnt += __popcll(y);
         }
@@ -511,12 +670,12 @@ __device__ void run_task(const CliqueArgs& A, const CliqueLds& L, uint64_t* rows
           job_nw = Wd;
           job_C = L.stk + (depth + 1) * W;
           job_q = q;
-          job_R = rows;
-          job_stride = dmax;
+          job_R = L.rows;
+          job_stride = kLocalMax;
           job_lo = 0;
           job_hi = d;
         } else if (solver && bounded && cnt <= kReindexMax) {
-          job_nw = reindex(L.stk + (depth + 1) * W, Wd, rows, dmax, L);
+          job_nw = reindex(L.stk + (depth + 1) * W, Wd, rows, rs, L);
           job = true;
           job_C = L.cset;
           job_q = q;
@@ -571,13 +730,12 @@ __device__ void run_task(const CliqueArgs& A, const CliqueLds& L, uint64_t* rows
   }
 }
 
-template <bool ROWS_LDS>
 __global__ void __launch_bounds__(64) clique_kernel(CliqueArgs A) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int lane = lane_id();
   const int wave_gid = blockIdx.x;
-  CliqueLds L = carve(smem, A.dmax, A.W, A.k, ROWS_LDS);
-  uint64_t* rows = ROWS_LDS ? L.rows : reinterpret_cast<uint64_t*>(A.rows_global) + static_cast<size_t>(wave_gid) * A.W * A.dmax;
+  CliqueLds L = carve(smem, A.dmax, A.W, A.k);
+  uint64_t* rows_g = reinterpret_cast<uint64_t*>(A.rows_global) + static_cast<size_t>(wave_gid) * A.W * A.dmax;
   WaveAcc WA;
   WA.acc = 0;
   WA.cur_g = -1;
@@ -589,7 +747,7 @@ __global__ void __launch_bounds__(64) clique_kernel(CliqueArgs A) {
   sched_begin(A.S, it);
   Task t;
   while (sched_next(A.S, it, wave_gid, L.cur, &t)) {
-    run_task<ROWS_LDS>(A, L, rows, t, WA, wave_gid);
+    run_task(A, L, rows_g, t, WA, wave_gid);
     WA.tasks++;
   }
   sched_end(A.S);
@@ -608,9 +766,9 @@ __global__ void __launch_bounds__(64) clique_kernel(CliqueArgs A) {
 
 }  // namespace
 
-size_t clique_lds_bytes(int dmax, int W, int k, bool rows_in_lds) {
+size_t clique_lds_bytes(int dmax, int W, int k) {
   auto a16 = [](size_t x) { return (x + 15) & ~static_cast<size_t>(15); };
-  size_t off = rows_in_lds ? static_cast<size_t>(W) * dmax * 8 : 0;
+  size_t off = static_cast<size_t>(2) * kLocalMax * 8;
   off = a16(off) + static_cast<size_t>(k + 1) * W * 8;
   off = a16(off) + static_cast<size_t>(dmax) * 4;
   off = a16(off) + static_cast<size_t>(dmax + 1) * 4;
@@ -619,17 +777,12 @@ size_t clique_lds_bytes(int dmax, int W, int k, bool rows_in_lds) {
   return a16(off);
 }
 
-hipError_t clique_occupancy(bool rows_in_lds, size_t lds_bytes, int* blocks_per_cu) {
-  if (rows_in_lds)
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, clique_kernel<true>, 64, lds_bytes);
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, clique_kernel<false>, 64, lds_bytes);
+hipError_t clique_occupancy(size_t lds_bytes, int* blocks_per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, clique_kernel, 64, lds_bytes);
 }
 
-hipError_t launch_clique(const CliqueArgs& a, int grid, bool rows_in_lds, size_t lds_bytes, hipStream_t s) {
-  if (rows_in_lds)
-    hipLaunchKernelGGL(clique_kernel<true>, dim3(grid), dim3(64), lds_bytes, s, a);
-  else
-    hipLaunchKernelGGL(clique_kernel<false>, dim3(grid), dim3(64), lds_bytes, s, a);
+hipError_t launch_clique(const CliqueArgs& a, int grid, size_t lds_bytes, hipStream_t s) {
+  hipLaunchKernelGGL(clique_kernel, dim3(grid), dim3(64), lds_bytes, s, a);
   return hipGetLastError();
 }
 

@@ -58,9 +58,9 @@ struct MotifArgs {
 };
 
 // kernel launchers (return hipSuccess or the launch error)
-hipError_t launch_clique(const CliqueArgs& a, int grid, bool rows_in_lds, size_t lds_bytes, hipStream_t s);
-size_t clique_lds_bytes(int dmax, int W, int k, bool rows_in_lds);
-hipError_t clique_occupancy(bool rows_in_lds, size_t lds_bytes, int* blocks_per_cu);
+hipError_t launch_clique(const CliqueArgs& a, int grid, size_t lds_bytes, hipStream_t s);
+size_t clique_lds_bytes(int dmax, int W, int k);
+hipError_t clique_occupancy(size_t lds_bytes, int* blocks_per_cu);
 
 hipError_t launch_motif(const MotifArgs& a, int grid, size_t lds_bytes, hipStream_t s);
 size_t motif_lds_bytes(int k, int ncls);
