@@ -487,6 +487,7 @@ Sched make_sched(dm_graph* g, const Opt& o, int grid, int64_t nq, const int32_t*
   int trig = static_cast<int>(r * grid);
   S.idle_trigger = trig < 1 ? 1 : trig;
   S.period = 64;
+  S.waves = grid;
   return S;
 }
 

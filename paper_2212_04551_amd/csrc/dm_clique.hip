@@ -43,6 +43,7 @@ struct CliqueLds {
   uint64_t* lr;     // [2][128] re-indexed rows (word-major) of a set of <= 128 members
   uint64_t* cset;   // [4] the set handed to the dense solver
   int* pos;         // [128] positions (in N+(root)) of re-indexed members
+  int* pst;         // [128] solver: first pair task of each member
 };
 
 __device__ __forceinline__ size_t align16(size_t x) { return (x + 15) & ~static_cast<size_t>(15); }
@@ -75,6 +76,8 @@ __device__ CliqueLds carve(unsigned char* smem, int dmax, int W, int k) {
   L.cset = reinterpret_cast<uint64_t*>(smem + off);
   off += 4 * 8;
   L.pos = reinterpret_cast<int*>(smem + off);
+  off += kReindexMax * 4;
+  L.pst = reinterpret_cast<int*>(smem + off);
   return L;
 }
 
@@ -93,6 +96,10 @@ __device__ CliqueLds carve(unsigned char* smem, int dmax, int W, int k) {
 // selects a word of a register array without dynamic register indexing.
 
 constexpr int kSolverMaxQ = 8;
+// A solver job donates part of itself only in the launch's tail (a quarter of
+// the waves idle) and while at least this many pair tasks are untaken: the
+// taker rebuilds the root's rows and the prefix first.
+constexpr int kJobDonateMin = 1024;
 
 // rows the solver reads always live in LDS: an address-space-3 pointer makes
 // every load a ds_read (no flat-address dispatch)
@@ -190,6 +197,21 @@ __device__ __forceinline__ int select_nth(const uint64_t (&x)[NW], int r) {
   return base + pos;
 }
 
+// Where a solver job sits in the search, so that part of it can be donated:
+// the root, its stats row, the depth of the job's set (the prefix is in
+// L.cur[1 .. depth-1]), the end of its first-member range in positions of
+// N+(root), and the map from the job's member ids to positions (null: equal).
+struct JobCtx {
+  const Sched* S;
+  int root;
+  int64_t stat;
+  int depth;
+  int hi_pos;
+  const int* map;
+  int* prefix;
+  int wave_gid;
+};
+
 // q-cliques, q >= 3, inside C (rows upper-triangular: row i holds members
 // above i) whose first member is in `first`.  The work is split into pair
 // tasks (i, j), j a member of C adjacent to i and above it, numbered by a
@@ -199,7 +221,7 @@ __device__ __forceinline__ int select_nth(const uint64_t (&x)[NW], int r) {
 // tasks run out.  Returns this lane's share.
 template <int NW>
 __device__ __forceinline__ uint64_t lane_solve(const uint64_t (&C)[NW], const uint64_t (&first)[NW], int q,
-                                               LdsU64* lr, int stride, LdsI32* pst) {
+                                               LdsU64* lr, int stride, LdsI32* pst, const JobCtx& J) {
   const int lane = lane_id();
   int total = 0;
 #pragma unroll
@@ -227,12 +249,34 @@ __device__ __forceinline__ uint64_t lane_solve(const uint64_t (&C)[NW], const ui
   int d = -1;  // depth below the pair; -1: needs a task
   bool done = false;
   int tbase = 0;
+  int hi_pos = J.hi_pos;  // end (in positions) of the first members still owned
   for (;;) {
     const bool want = !done && d < 0;
     const uint64_t wb = ballot(want);
     // refill in batches: decoding a task costs a binary search and a select,
     // so lanes wait until a quarter of the wave is free (or none is busy)
     if (wb && (__popcll(wb) >= kWave / 4 || ballot(d >= 0) == 0)) {
+      // idle waves elsewhere: hand over the first members whose pair tasks
+      // make up about the upper half of the untaken ones
+      if (J.S->donate && total - tbase >= kJobDonateMin && sched_want_donation_tail(*J.S)) {
+        const int tmid = tbase + (total - tbase) / 2;
+        int ic = 0;  // last member whose range starts before tmid
+#pragma unroll
+        for (int st = 32 * NW; st >= 1; st >>= 1)
+          if (pst[ic + st] < tmid) ic += st;
+        ++ic;
+        if (ic < 64 * NW) {
+          const int cut = pst[ic];
+          const int pos = J.map ? J.map[ic] : ic;
+          if (cut < total && hi_pos - pos >= 1) {
+            const int pay = task_payload(J.root, J.stat, J.depth, pos, hi_pos, J.prefix);
+            if (sched_publish(*J.S, pay, J.wave_gid)) {
+              total = cut;
+              hi_pos = pos;
+            }
+          }
+        }
+      }
       if (want) {
         const int t = tbase + mbcnt(wb);
         if (t < total) {
@@ -306,7 +350,8 @@ __device__ __forceinline__ uint64_t lane_solve(const uint64_t (&C)[NW], const ui
 // q-cliques (1 <= q <= kSolverMaxQ) inside the set Cl (NW words) whose first
 // member lies in [lo, hi); returns this lane's share.
 template <int NW>
-__device__ uint64_t small_solve(LdsU64* Cl, int q, LdsU64* lr, int stride, int lo, int hi, LdsI32* pst) {
+__device__ uint64_t small_solve(LdsU64* Cl, int q, LdsU64* lr, int stride, int lo, int hi, LdsI32* pst,
+                               const JobCtx& J) {
   const int lane = lane_id();
   uint64_t C[NW], first[NW];
 #pragma unroll
@@ -350,17 +395,17 @@ __device__ uint64_t small_solve(LdsU64* Cl, int q, LdsU64* lr, int stride, int l
       }
     }
   } else {
-    add = lane_solve<NW>(C, first, q, lr, stride, pst);
+    add = lane_solve<NW>(C, first, q, lr, stride, pst, J);
   }
   return add;
 }
 
 __device__ __forceinline__ uint64_t small_solve_any(int nw, const uint64_t* Cg, int q, const uint64_t* lrg, int stride,
-                                                    int lo, int hi, int* pstg) {
+                                                    int lo, int hi, int* pstg, const JobCtx& J) {
   LdsU64* C = as_lds(Cg);
   LdsU64* lr = as_lds(lrg);
   LdsI32* pst = (LdsI32*)(pstg);
-  return nw == 1 ? small_solve<1>(C, q, lr, stride, lo, hi, pst) : small_solve<2>(C, q, lr, stride, lo, hi, pst);
+  return nw == 1 ? small_solve<1>(C, q, lr, stride, lo, hi, pst, J) : small_solve<2>(C, q, lr, stride, lo, hi, pst, J);
 }
 
 // Local ids for the members of the multi-word set C (at most kReindexMax, by
@@ -582,6 +627,8 @@ __device__ void run_task(const CliqueArgs& A, const CliqueLds& L, uint64_t* rows
     // a job cannot be donated.
     bool job = false, job_last = false;
     int job_nw = 1, job_q = 0, job_stride = 0, job_lo = 0, job_hi = 0;
+    int job_depth = 0, job_hipos = 0;
+    const int* job_map = nullptr;
     const uint64_t* job_C = nullptr;
     const uint64_t* job_R = nullptr;
     // Fast path (at most 64 words): lane w keeps word w of the current level's
@@ -601,6 +648,9 @@ __device__ void run_task(const CliqueArgs& A, const CliqueLds& L, uint64_t* rows
       job_stride = kLocalMax;
       job_lo = t.lo;
       job_hi = hi_t;
+      job_depth = s0;
+      job_hipos = hi_t;
+      job_map = nullptr;
     } else if (s0 == k - 2) {
       leaf_parent(s0, t.lo, hi_t);
       depth = -1;
@@ -613,7 +663,8 @@ __device__ void run_task(const CliqueArgs& A, const CliqueLds& L, uint64_t* rows
     int steps = 0;
     while (depth >= 0) {
       if (job) {
-        add_acc(small_solve_any(job_nw, job_C, job_q, job_R, job_stride, job_lo, job_hi, L.pos));
+        const JobCtx J{&A.S, v, t.stat, job_depth, job_hipos, job_map, L.cur, wave_gid};
+        add_acc(small_solve_any(job_nw, job_C, job_q, job_R, job_stride, job_lo, job_hi, L.pst, J));
         job = false;
         if (job_last) break;
       }
@@ -674,6 +725,9 @@ __device__ void run_task(const CliqueArgs& A, const CliqueLds& L, uint64_t* rows
           job_stride = kLocalMax;
           job_lo = 0;
           job_hi = d;
+          job_depth = depth + 1;
+          job_hipos = d;
+          job_map = nullptr;
         } else if (solver && bounded && cnt <= kReindexMax) {
           job_nw = reindex(L.stk + (depth + 1) * W, Wd, rows, rs, L);
           job = true;
@@ -683,6 +737,9 @@ __device__ void run_task(const CliqueArgs& A, const CliqueLds& L, uint64_t* rows
           job_stride = kReindexMax;
           job_lo = 0;
           job_hi = kReindexMax;
+          job_depth = depth + 1;
+          job_hipos = d;
+          job_map = L.pos;
         } else if (depth + 1 == k - 2) {
           leaf_parent(depth + 1, 0, d);
         } else {
@@ -730,7 +787,9 @@ __device__ void run_task(const CliqueArgs& A, const CliqueLds& L, uint64_t* rows
   }
 }
 
-__global__ void __launch_bounds__(64) clique_kernel(CliqueArgs A) {
+// 4 waves per SIMD: the register budget (128 VGPRs) this needs holds the
+// kernel without spills and is what keeps row-read latency covered
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) clique_kernel(CliqueArgs A) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int lane = lane_id();
   const int wave_gid = blockIdx.x;
@@ -773,7 +832,7 @@ size_t clique_lds_bytes(int dmax, int W, int k) {
   off = a16(off) + static_cast<size_t>(dmax) * 4;
   off = a16(off) + static_cast<size_t>(dmax + 1) * 4;
   off = a16(off) + 2 * (kMaxK + 2) * 4;
-  off = a16(off) + kReindexMax / 64 * kReindexMax * 8 + 4 * 8 + kReindexMax * 4;
+  off = a16(off) + kReindexMax / 64 * kReindexMax * 8 + 4 * 8 + 2 * kReindexMax * 4;
   return a16(off);
 }
 

@@ -138,6 +138,7 @@ struct Sched {
   int donate;                 // donation enabled
   int idle_trigger;           // donate only when at least this many waves are idle
   int period;                 // DFS steps between donation checks
+  int waves;                  // waves in the launch
 };
 
 // A unit of work: root vertex, its stats row, the traversal depth the task
@@ -187,6 +188,18 @@ __device__ __forceinline__ bool sched_want_donation(const Sched& S) {
     unsigned long long st = ld_relaxed_u64(S.state);
     int pending = static_cast<int>(st & 0xffffffffu);
     want = (idle >= S.idle_trigger && idle > pending && pending < S.nslots) ? 1 : 0;
+  }
+  return uni(want) != 0;
+}
+
+// Tail-only variant: at least a quarter of the launch's waves is idle.
+__device__ __forceinline__ bool sched_want_donation_tail(const Sched& S) {
+  int want = 0;
+  if (lane_id() == 0) {
+    int idle = ld_relaxed(S.idle);
+    unsigned long long st = ld_relaxed_u64(S.state);
+    int pending = static_cast<int>(st & 0xffffffffu);
+    want = (4 * idle >= S.waves && idle > pending && pending < S.nslots) ? 1 : 0;
   }
   return uni(want) != 0;
 }

@@ -49,6 +49,16 @@ def test_clique_complete(n):
         assert dm.count_cliques(h, k) == math.comb(n, k), (n, k)
 
 
+def test_clique_dense_wide_roots():
+    """Cocktail party on 80 pairs (160 vertices, degree 158): roots wider than
+    128 keep their rows in global memory and hand dense re-indexed sets with
+    5 or more levels to the solver, which splits them among idle waves.
+    Closed form C(80, k) 2^k."""
+    h = dm.load_graph(gg.cocktail_party(80))
+    for k in (5, 6, 7):
+        assert dm.count_cliques(h, k) == math.comb(80, k) * 2 ** k, k
+
+
 @pytest.mark.parametrize("parts", [[3] * 12, [1, 2, 3, 4, 5, 6, 7], [2] * 9, [40, 1, 1, 25]])
 def test_clique_multipartite(parts):
     h = dm.load_graph(gg.complete_multipartite(parts))
