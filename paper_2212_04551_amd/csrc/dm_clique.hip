@@ -558,26 +558,41 @@ __device__ void run_task(const CliqueArgs& A, const CliqueLds& L, uint64_t* rows
     running = uni(running);
     if (lane == 0) L.offs[d] = running;
     const int Wd = (d + 63) >> 6;
-    for (int idx = lane; idx < Wd * d; idx += kWave) {
-      const int w = idx / d, p = idx - w * d;
-      rows[static_cast<size_t>(w) * rs + p] = 0ull;
-    }
-    wave_sync();
-    // ---- adjacency of N+(v) restricted to itself, as bitmap rows
-    for (int tt = lane; tt < running; tt += kWave) {
-      int lo = 0, hi = d;  // i = last index with offs[i] <= tt
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (L.offs[mid] <= tt) lo = mid; else hi = mid;
+    // ---- adjacency of N+(v) restricted to itself, as bitmap rows: a block
+    // of rows at a time in the LDS tile L.rows (LDS atomics), then stored to
+    // the global region for roots wider than kLocalMax (one write per word)
+    const int tile_rows = lds_rows ? d : (2 * kLocalMax) / Wd;
+    for (int p0 = 0; p0 < d; p0 += tile_rows) {
+      const int p1 = p0 + tile_rows < d ? p0 + tile_rows : d;
+      const int ts = lds_rows ? kLocalMax : tile_rows;  // tile stride
+      for (int idx = lane; idx < Wd * (p1 - p0); idx += kWave) {
+        const int w = idx / (p1 - p0), p = idx - w * (p1 - p0);
+        L.rows[w * ts + p] = 0ull;
       }
-      const int i = lo;
-      const int e = A.col[A.rp[L.nbr[i]] + (tt - L.offs[i])];
-      int a = i + 1, b = d;  // e > nbr[i], so search above i
-      while (a < b) {
-        const int mid = (a + b) >> 1;
-        if (L.nbr[mid] < e) a = mid + 1; else b = mid;
+      wave_sync();
+      for (int tt = L.offs[p0] + lane; tt < L.offs[p1]; tt += kWave) {
+        int lo = p0, hi = p1;  // i = last index with offs[i] <= tt
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (L.offs[mid] <= tt) lo = mid; else hi = mid;
+        }
+        const int i = lo;
+        const int e = A.col[A.rp[L.nbr[i]] + (tt - L.offs[i])];
+        int a = i + 1, b = d;  // e > nbr[i], so search above i
+        while (a < b) {
+          const int mid = (a + b) >> 1;
+          if (L.nbr[mid] < e) a = mid + 1; else b = mid;
+        }
+        if (a < d && L.nbr[a] == e) atomicOr(reinterpret_cast<unsigned long long*>(&L.rows[(a >> 6) * ts + (i - p0)]), 1ull << (a & 63));
       }
-      if (a < d && L.nbr[a] == e) atomicOr(reinterpret_cast<unsigned long long*>(&rows[static_cast<size_t>(a >> 6) * rs + i]), 1ull << (a & 63));
+      wave_sync();
+      if (!lds_rows) {
+        for (int idx = lane; idx < Wd * (p1 - p0); idx += kWave) {
+          const int w = idx / (p1 - p0), p = idx - w * (p1 - p0);
+          rows[static_cast<size_t>(w) * rs + p0 + p] = L.rows[w * ts + p];
+        }
+        wave_sync();
+      }
     }
     // ---- level-1 candidate set and the task prefix
     for (int w = lane; w < Wd; w += kWave) {
