@@ -65,6 +65,9 @@ constexpr int kBins = 16;  // masks of a (k-2)-traversal entry, k <= 6
 // A leaf-level range is donated only when this many entries are untried: the
 // taker re-extends the whole prefix first.
 constexpr int kLeafDonateMin = 128;
+// Leaf-level lists of at most this many entries are copied to LDS, so the
+// neighbour lookups binary-search LDS instead of global memory.
+constexpr int kLeafLds = 1024;
 
 struct MotifLds {
   unsigned long long* cnt;  // [ncls] class counters of the current graph
@@ -80,6 +83,8 @@ struct MotifLds {
   int* cursor;              // [kSuf]
   int* endv;                // [kSuf]
   int* esize;               // [kSuf]
+  int* ev;                  // [kLeafLds] leaf level: copy of the (k-2)-traversal's list
+  uint8_t* em;              // [kLeafLds] and of its masks
 };
 
 __device__ __forceinline__ int off_of(int i) { return i * (i - 1) / 2 - 1; }  // bitmap field of v_i, i >= 2
@@ -105,6 +110,8 @@ __device__ MotifLds carve(unsigned char* smem, int ncls) {
   L.cursor = reinterpret_cast<int*>(take(kSuf * 4));
   L.endv = reinterpret_cast<int*>(take(kSuf * 4));
   L.esize = reinterpret_cast<int*>(take(kSuf * 4));
+  L.ev = reinterpret_cast<int*>(take(kLeafLds * 4));
+  L.em = reinterpret_cast<uint8_t*>(take(kLeafLds));
   return L;
 }
 
@@ -233,9 +240,19 @@ __device__ void extend_level(const MotifArgs& A, const MotifLds& L, MotifWave& M
 __device__ __forceinline__ int leaf_level(const MotifArgs& A, const MotifLds& L, MotifWave& MW, int s, int lo, int hi,
                           const Task& t, int wave_gid, uint64_t& nodes_l, uint64_t& leaves_l, uint64_t& reads_l) {
   const int lane = lane_id();
-  const int32_t* Ev = MW.vert + A.level_off[s];
-  const uint8_t* Em = MW.mask + A.level_off[s];
   const int ns = L.esize[s];
+  // the list (and masks) in LDS when it fits, else in this wave's global region
+  const bool in_lds = ns <= kLeafLds;
+  if (in_lds) {
+    const int32_t* Gv = MW.vert + A.level_off[s];
+    const uint8_t* Gm = MW.mask + A.level_off[s];
+    for (int i = lane; i < ns; i += kWave) {
+      L.ev[i] = Gv[i];
+      L.em[i] = Gm[i];
+    }
+  }
+  const int32_t* Ev = in_lds ? L.ev : MW.vert + A.level_off[s];
+  const uint8_t* Em = in_lds ? L.em : MW.mask + A.level_off[s];
   const int nm = 1 << s;
   const unsigned low = static_cast<unsigned>(nm - 1);
   const int v0 = L.tr[0];
@@ -477,7 +494,8 @@ __device__ __forceinline__ void run_task(const MotifArgs& A, const MotifLds& L, 
   }
 }
 
-__global__ void __launch_bounds__(64) motif_kernel(MotifArgs A) {
+// 4 waves per SIMD (128 VGPRs): enough waves to cover the lookups' latency
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) motif_kernel(MotifArgs A) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int lane = lane_id();
   const int wave_gid = blockIdx.x;
@@ -522,6 +540,7 @@ size_t motif_lds_bytes(int k, int ncls) {
   size_t off = a16(static_cast<size_t>(ncls) * 8) + a16(kBins * kBins * 8) + a16(kBins * 8) + a16(2 * kBins * 4);
   off += a16((kWave + 1) * 8) + a16(kWave * 8) + a16(kWave * 4);
   off += 2 * a16(kSuf * 4) + a16(kSuf * kSuf * 4) + 3 * a16(kSuf * 4);
+  off += a16(kLeafLds * 4) + a16(kLeafLds);
   return off;
 }
 
