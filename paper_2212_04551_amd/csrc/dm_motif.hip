@@ -67,7 +67,10 @@ constexpr int kBins = 16;  // masks of a (k-2)-traversal entry, k <= 6
 constexpr int kLeafDonateMin = 128;
 // Leaf-level lists of at most this many entries are copied to LDS, so the
 // neighbour lookups binary-search LDS instead of global memory.
-constexpr int kLeafLds = 1024;
+constexpr int kLeafLds = 800;
+// Membership filter over the LDS copy: one bit per (vertex mod 8192); most
+// neighbours of an x are not in the list and are rejected without a search.
+constexpr int kFilterWords = 256;
 
 struct MotifLds {
   unsigned long long* cnt;  // [ncls] class counters of the current graph
@@ -85,6 +88,7 @@ struct MotifLds {
   int* esize;               // [kSuf]
   int* ev;                  // [kLeafLds] leaf level: copy of the (k-2)-traversal's list
   uint8_t* em;              // [kLeafLds] and of its masks
+  unsigned* filt;           // [kFilterWords] membership filter of the LDS copy (zero between calls)
 };
 
 __device__ __forceinline__ int off_of(int i) { return i * (i - 1) / 2 - 1; }  // bitmap field of v_i, i >= 2
@@ -112,6 +116,7 @@ __device__ MotifLds carve(unsigned char* smem, int ncls) {
   L.esize = reinterpret_cast<int*>(take(kSuf * 4));
   L.ev = reinterpret_cast<int*>(take(kLeafLds * 4));
   L.em = reinterpret_cast<uint8_t*>(take(kLeafLds));
+  L.filt = reinterpret_cast<unsigned*>(take(kFilterWords * 4));
   return L;
 }
 
@@ -247,8 +252,10 @@ __device__ __forceinline__ int leaf_level(const MotifArgs& A, const MotifLds& L,
     const int32_t* Gv = MW.vert + A.level_off[s];
     const uint8_t* Gm = MW.mask + A.level_off[s];
     for (int i = lane; i < ns; i += kWave) {
-      L.ev[i] = Gv[i];
+      const int y = Gv[i];
+      L.ev[i] = y;
       L.em[i] = Gm[i];
+      atomicOr(&L.filt[(y >> 5) & (kFilterWords - 1)], 1u << (y & 31));
     }
   }
   const int32_t* Ev = in_lds ? L.ev : MW.vert + A.level_off[s];
@@ -290,8 +297,9 @@ __device__ __forceinline__ int leaf_level(const MotifArgs& A, const MotifLds& L,
         for (int step = kWave / 2; step >= 1; step >>= 1)
           if (L.sl_start[o + step] <= f) o += step;
         const int w = A.col[L.sl_base[o] + (f - L.sl_start[o])];
+        const bool maybe = !in_lds || ((L.filt[(w >> 5) & (kFilterWords - 1)] >> (w & 31)) & 1u);
         if (w > v0) {
-          const int jj = lower_bound_g(Ev, ns, w);
+          const int jj = maybe ? lower_bound_g(Ev, ns, w) : ns;
           if (jj < ns && Ev[jj] == w) {
             if (jj > c + o && canonical(L, s, w, Em[jj])) key = L.sl_mask[o] * kBins + static_cast<int>(Em[jj] & low);
           } else if (!in_tr(L, s, w)) {
@@ -336,6 +344,9 @@ __device__ __forceinline__ int leaf_level(const MotifArgs& A, const MotifLds& L,
     }
   }
   wave_sync();
+  // ---- clear the filter words this list set
+  if (in_lds)
+    for (int i = lane; i < ns; i += kWave) L.filt[(Ev[i] >> 5) & (kFilterWords - 1)] = 0u;
   // ---- one dictionary lookup per non-empty bin
   const int code_tr = L.code[s];
   const int fx = s >= 2 ? off_of(s) : 0;  // v_1's field is implied
@@ -509,6 +520,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4)))
   MW.mask = A.ext_mask + static_cast<size_t>(wave_gid) * A.wave_ext_cap;
   MW.nbuf = A.new_buf + static_cast<size_t>(wave_gid) * A.dmax;
   for (int c = lane; c < A.ncls; c += kWave) L.cnt[c] = 0;
+  for (int c = lane; c < kFilterWords; c += kWave) L.filt[c] = 0u;
   wave_sync();
   const uint64_t t_begin = wall_clock64();
   SchedIter it;
@@ -540,7 +552,7 @@ size_t motif_lds_bytes(int k, int ncls) {
   size_t off = a16(static_cast<size_t>(ncls) * 8) + a16(kBins * kBins * 8) + a16(kBins * 8) + a16(2 * kBins * 4);
   off += a16((kWave + 1) * 8) + a16(kWave * 8) + a16(kWave * 4);
   off += 2 * a16(kSuf * 4) + a16(kSuf * kSuf * 4) + 3 * a16(kSuf * 4);
-  off += a16(kLeafLds * 4) + a16(kLeafLds);
+  off += a16(kLeafLds * 4) + a16(kLeafLds) + a16(kFilterWords * 4);
   return off;
 }
 
