@@ -27,15 +27,20 @@ KS = (3, 4, 5, 6, 7, 8)
 # HBM bytes of the k=8 clique_kernel launch from rocprofv3 (2.0 x FETCH_SIZE +
 # 1.0 x WRITE_SIZE, factors from a copy kernel of known size), valid only for
 # the kernel source they were taken on.
-TRAFFIC = {"source_sha": "85891e85cfc5a20f", "bytes_per_launch": 2.0 * 4536160.1875 * 1024 + 61021.75 * 1024}
+TRAFFIC = {"source_sha": "baadedc0170249d9", "bytes_per_launch": 2.0 * 5827718.125 * 1024 + 1288861.21875 * 1024}
 
 
-def kernel_source_sha() -> str:
+def kernel_source_sha(kernel: str = "dm_clique.hip") -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in ("dm_clique.hip", "dm_device.hpp"):
+    for f in (kernel, "dm_device.hpp"):
         h.update(open(os.path.join(ROOT, "paper_2212_04551_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
+
+
+# HBM bytes per launch of the motif kernel on the sampled 5-motif workload
+# (same scaling), valid only for the kernel source they were taken on.
+TRAFFIC_MOTIF = {"source_sha": "f28548eaee7b007c", "bytes_per_launch": 2.0 * 263395344.5 * 1024 + 69029313.21875 * 1024}
 # MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz issue 39.3e12 32-bit integer
 # VALU operations per second (bitwise AND and popcount are single-issue ops).
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
@@ -104,6 +109,17 @@ def timed_steps(fn, steps, warmup, label):
         log(f"{label} step {s} done")
     torch.cuda.synchronize()
     return r, (time.perf_counter() - t0) * 1e3 / steps
+
+
+def copy_probe():
+    """One 1 GiB device-to-device copy: the calibration kernel of known size
+    for the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    src = torch.empty(1 << 28, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
 
 
 def idle_fraction(ws):
@@ -185,11 +201,7 @@ def wl_cl1m_clique(args):
         return counts
 
     if args.copy_probe:
-        src = torch.empty(1 << 28, dtype=torch.int32, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+        copy_probe()
 
     for w in range(args.warmup):
         t = time.perf_counter()
@@ -312,6 +324,64 @@ def wl_cl100k_learned(args):
     return out
 
 
+def wl_cl100k_motif_sample(args):
+    """5-motifs on the cl100k graph (weight cap 1414), a seeded 5% root sample:
+    the motif kernel alone, with its HBM roofline."""
+    import torch
+    from paper_2212_04551_amd import dm
+    from paper_2212_04551_amd import graphgen as gg
+
+    g = gg.chung_lu(100_000, 1_000_000, 2.3, 1414.0, args.seed)[0]
+    roots = np.sort(np.random.default_rng(7).choice(g.n, g.n // 20, replace=False)).astype(np.int32)
+    h = dm.load_graph(g)
+    stream = torch.cuda.current_stream()
+    if args.copy_probe:
+        copy_probe()
+    # algorithmic bytes: every expanded node reads its newest vertex's row_ptr
+    # pair (16 B) and adjacency (4 B per entry), from an untimed record run
+    stats = torch.zeros((len(roots), 3), dtype=torch.int64, device="cuda")
+    ref = dm.count_motifs(h, 5, roots=roots, root_stats=stats)
+    st = stats.cpu().numpy().astype(np.float64)
+    nodes, reads = st[:, 0].sum(), st[:, 2].sum()
+    alg_bytes = 16.0 * nodes + 4.0 * reads
+    for _ in range(args.warmup):
+        dm.count_motifs(h, 5, roots=roots, stream=stream)
+    evs = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s_ in range(args.steps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        c = dm.count_motifs(h, 5, roots=roots, stream=stream)
+        e1.record(stream)
+        evs.append((e0, e1))
+        log(f"step {s_} done")
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    assert np.array_equal(c, ref)
+    kms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    n_sub = int(c.sum())
+    out = base_record(n_sub / (ms / 1e3), ms, args.steps, args.warmup,
+                      "induced 5-motif counting, Chung-Lu n=1e5 m=1e6 gamma=2.3 weight cap 1414 seed 0, "
+                      "seeded 5% root sample (5000 roots), plain",
+                      {"subgraphs": n_sub, "roots": int(len(roots)), "tree_nodes": int(nodes),
+                       "adjacency_reads": int(reads), "kernel_ms": kms})
+    achieved = alg_bytes / (kms / 1e3) / 1e9
+    sha = kernel_source_sha("dm_motif.hip")
+    out["roofline"] = {
+        "bound": "hbm",
+        "kernel": "motif_kernel",
+        "achieved": achieved,
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": achieved / HBM_PEAK_GBS,
+        "traffic": TRAFFIC_MOTIF["bytes_per_launch"] if sha == TRAFFIC_MOTIF["source_sha"] else None,
+        "work": f"16 B x {int(nodes)} tree nodes + 4 B x {int(reads)} adjacency entries",
+    }
+    return out
+
+
 def wl_batch4096(args):
     import torch
     from paper_2212_04551_amd import dm
@@ -388,6 +458,7 @@ WORKLOADS = {
     "cl1m-clique": wl_cl1m_clique,
     "er516-motif4": wl_er516_motif,
     "cl100k-motif-learned": wl_cl100k_learned,
+    "cl100k-motif5-sample": wl_cl100k_motif_sample,
     "batch4096-motif5": wl_batch4096,
     "sbm-clique-largek": wl_sbm_largek,
 }
