@@ -313,16 +313,42 @@ __device__ __forceinline__ uint64_t lane_solve(const uint64_t (&C)[NW], const ui
         const int i = wsel * 64 + __builtin_ctzll(cw);
 #pragma unroll
         for (int w = 0; w < NW; ++w) cur[w] = (w == wsel) ? (cw & (cw - 1)) : cur[w];
+        const int r = r0 - d;  // members still to choose at this depth, i included
+        // at the last level's parent a second member is taken in the same pass
+        // (both row reads in flight before either is used)
+        int w2 = -1;
+        if (r == 2) {
+#pragma unroll
+          for (int w = NW - 1; w >= 0; --w)
+            if (cur[w]) w2 = w;
+        }
+        uint64_t after2[NW];
+        int i2 = i;
+        if (w2 >= 0) {
+          const uint64_t c2 = pick<NW>(cur, w2);
+          i2 = w2 * 64 + __builtin_ctzll(c2);
+#pragma unroll
+          for (int w = 0; w < NW; ++w) after2[w] = (w == w2) ? (c2 & (c2 - 1)) : cur[w];
+        } else {
+#pragma unroll
+          for (int w = 0; w < NW; ++w) after2[w] = 0;
+        }
         uint64_t ch[NW];
-        int cnt = 0;
+        int cnt = 0, cnt2 = 0;
 #pragma unroll
         for (int q2 = 0; q2 < NW; ++q2) {
-          ch[q2] = cur[q2] & lr[q2 * stride + i];
+          const uint64_t ra = lr[q2 * stride + i];
+          const uint64_t rb = lr[q2 * stride + i2];
+          ch[q2] = cur[q2] & ra;
           cnt += __popcll(ch[q2]);
+          cnt2 += __popcll(after2[q2] & rb);
         }
-        const int r = r0 - d;  // members still to choose at this depth, i included
         if (r == 2) {
-          acc += static_cast<uint64_t>(cnt);
+          acc += static_cast<uint64_t>(cnt + cnt2);
+          if (w2 >= 0) {
+#pragma unroll
+            for (int w = 0; w < NW; ++w) cur[w] = after2[w];
+          }
         } else if (cnt >= r - 1) {
           const uint64_t c0 = cur[0], c1 = NW == 2 ? pick<NW>(cur, 1) : 0;
           if (d == 0) { sa0 = c0; sa1 = c1; }
