@@ -399,7 +399,7 @@ __device__ uint64_t small_solve(LdsU64* Cl, int q, LdsU64* lr, int stride, int l
         for (int q2 = 0; q2 < NW; ++q2) add += static_cast<uint64_t>(__popcll(C[q2] & lr[q2 * stride + i]));
       }
     }
-  } else if (q <= 4) {
+  } else if (q <= 3) {
     // the wave walks the first member i, lane j takes the second member
     for (int w = 0; w < NW; ++w) {
       uint64_t x = pick<NW>(first, w);
