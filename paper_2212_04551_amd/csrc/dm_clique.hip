@@ -314,41 +314,51 @@ __device__ __forceinline__ uint64_t lane_solve(const uint64_t (&C)[NW], const ui
 #pragma unroll
         for (int w = 0; w < NW; ++w) cur[w] = (w == wsel) ? (cw & (cw - 1)) : cur[w];
         const int r = r0 - d;  // members still to choose at this depth, i included
-        // at the last level's parent a second member is taken in the same pass
-        // (both row reads in flight before either is used)
-        int w2 = -1;
-        if (r == 2) {
+        // at the last level's parent up to two more members are taken in the
+        // same pass (all row reads in flight before any is used)
+        constexpr int kExtra = 2;
+        uint64_t rest[kExtra][NW];
+        int ix[kExtra];
+        bool has[kExtra];
+        uint64_t scan[NW];
 #pragma unroll
-          for (int w = NW - 1; w >= 0; --w)
-            if (cur[w]) w2 = w;
-        }
-        uint64_t after2[NW];
-        int i2 = i;
-        if (w2 >= 0) {
-          const uint64_t c2 = pick<NW>(cur, w2);
-          i2 = w2 * 64 + __builtin_ctzll(c2);
+        for (int w = 0; w < NW; ++w) scan[w] = cur[w];
 #pragma unroll
-          for (int w = 0; w < NW; ++w) after2[w] = (w == w2) ? (c2 & (c2 - 1)) : cur[w];
-        } else {
+        for (int e = 0; e < kExtra; ++e) {
+          int we = -1;
+          if (r == 2) {
 #pragma unroll
-          for (int w = 0; w < NW; ++w) after2[w] = 0;
+            for (int w = NW - 1; w >= 0; --w)
+              if (scan[w]) we = w;
+          }
+          has[e] = we >= 0;
+          ix[e] = i;
+          if (has[e]) {
+            const uint64_t ce = pick<NW>(scan, we);
+            ix[e] = we * 64 + __builtin_ctzll(ce);
+#pragma unroll
+            for (int w = 0; w < NW; ++w) scan[w] = (w == we) ? (ce & (ce - 1)) : scan[w];
+          }
+#pragma unroll
+          for (int w = 0; w < NW; ++w) rest[e][w] = has[e] ? scan[w] : 0;
         }
         uint64_t ch[NW];
         int cnt = 0, cnt2 = 0;
 #pragma unroll
         for (int q2 = 0; q2 < NW; ++q2) {
           const uint64_t ra = lr[q2 * stride + i];
-          const uint64_t rb = lr[q2 * stride + i2];
+          uint64_t rx[kExtra];
+#pragma unroll
+          for (int e = 0; e < kExtra; ++e) rx[e] = lr[q2 * stride + ix[e]];
           ch[q2] = cur[q2] & ra;
           cnt += __popcll(ch[q2]);
-          cnt2 += __popcll(after2[q2] & rb);
+#pragma unroll
+          for (int e = 0; e < kExtra; ++e) cnt2 += __popcll(rest[e][q2] & rx[e]);
         }
         if (r == 2) {
           acc += static_cast<uint64_t>(cnt + cnt2);
-          if (w2 >= 0) {
 #pragma unroll
-            for (int w = 0; w < NW; ++w) cur[w] = after2[w];
-          }
+          for (int w = 0; w < NW; ++w) cur[w] = scan[w];
         } else if (cnt >= r - 1) {
           const uint64_t c0 = cur[0], c1 = NW == 2 ? pick<NW>(cur, 1) : 0;
           if (d == 0) { sa0 = c0; sa1 = c1; }
