@@ -658,6 +658,15 @@ void common_prepare(dm_graph* g, const Opt& o, Prepared* P, size_t out_count) {
   P->flags_dev = ctrl_flags(g);
 }
 
+// Persistent grid: per_cu waves on every CU, but no more than about one wave
+// per 8 queue entries (never under one wave per CU): on small graphs extra waves
+// only add contention on the scheduler's words and idle polling.
+int size_grid(int per_cu, int64_t nq) {
+  const int full = per_cu * cu_count();
+  const int64_t cap = std::max<int64_t>(cu_count(), (nq + 7) / 8);
+  return static_cast<int>(std::min<int64_t>(full, cap));
+}
+
 dm_status prepare_clique(dm_graph* g, int k, const Opt& o, hipStream_t s, const int32_t* root_graph, int ngraphs,
                          Prepared* P) {
   dm_status st = ensure_dag(g, s);
@@ -670,7 +679,7 @@ dm_status prepare_clique(dm_graph* g, int k, const Opt& o, hipStream_t s, const 
   HIP_OR_RETURN(clique_occupancy(lds, &per_cu), "occupancy");
   if (per_cu < 1) per_cu = 1;
   if (o.waves_per_cu && static_cast<int>(o.waves_per_cu) < per_cu) per_cu = static_cast<int>(o.waves_per_cu);
-  const int grid = per_cu * cu_count();
+  const int grid = size_grid(per_cu, o.roots ? o.num_roots : g->n);
   HIP_OR_RETURN(g->ctrl.ensure(ctrl_bytes()), "workspace");
   HIP_OR_RETURN(g->out.ensure(sizeof(uint64_t) * ngraphs), "workspace");
   // rows of roots with more than 128 out-neighbours: one region per wave
@@ -717,7 +726,7 @@ dm_status prepare_motif(dm_graph* g, int k, const Opt& o, hipStream_t s, const i
   if (per_cu < 1) per_cu = 1;
   if (per_cu > 16) per_cu = 16;  // the extension stacks live in global memory; bound the footprint
   if (o.waves_per_cu && static_cast<int>(o.waves_per_cu) < per_cu) per_cu = static_cast<int>(o.waves_per_cu);
-  const int grid = per_cu * cu_count();
+  const int grid = size_grid(per_cu, o.roots ? o.num_roots : g->n);
   std::memset(&P->ma, 0, sizeof(P->ma));
   MotifArgs& A = P->ma;
   int64_t cap_total = 0;
