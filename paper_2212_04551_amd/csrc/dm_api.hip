@@ -658,12 +658,14 @@ void common_prepare(dm_graph* g, const Opt& o, Prepared* P, size_t out_count) {
   P->flags_dev = ctrl_flags(g);
 }
 
-// Persistent grid: per_cu waves on every CU, but no more than about one wave
-// per 8 queue entries (never under one wave per CU): on small graphs extra waves
-// only add contention on the scheduler's words and idle polling.
-int size_grid(int per_cu, int64_t nq) {
+// Persistent grid: per_cu waves on every CU, but no more than one wave per 64
+// adjacency entries of the graph (never under one wave per CU): on tiny graphs
+// extra waves only add contention on the scheduler's words and idle polling.
+// (The number of roots is no guide: a few thousand roots of a large graph can
+// carry most of its work.)
+int size_grid(int per_cu, int64_t nnz) {
   const int full = per_cu * cu_count();
-  const int64_t cap = std::max<int64_t>(cu_count(), (nq + 7) / 8);
+  const int64_t cap = std::max<int64_t>(cu_count(), nnz / 64);
   return static_cast<int>(std::min<int64_t>(full, cap));
 }
 
@@ -679,7 +681,7 @@ dm_status prepare_clique(dm_graph* g, int k, const Opt& o, hipStream_t s, const 
   HIP_OR_RETURN(clique_occupancy(lds, &per_cu), "occupancy");
   if (per_cu < 1) per_cu = 1;
   if (o.waves_per_cu && static_cast<int>(o.waves_per_cu) < per_cu) per_cu = static_cast<int>(o.waves_per_cu);
-  const int grid = size_grid(per_cu, o.roots ? o.num_roots : g->n);
+  const int grid = size_grid(per_cu, g->nnz);
   HIP_OR_RETURN(g->ctrl.ensure(ctrl_bytes()), "workspace");
   HIP_OR_RETURN(g->out.ensure(sizeof(uint64_t) * ngraphs), "workspace");
   // rows of roots with more than 128 out-neighbours: one region per wave
@@ -726,7 +728,7 @@ dm_status prepare_motif(dm_graph* g, int k, const Opt& o, hipStream_t s, const i
   if (per_cu < 1) per_cu = 1;
   if (per_cu > 16) per_cu = 16;  // the extension stacks live in global memory; bound the footprint
   if (o.waves_per_cu && static_cast<int>(o.waves_per_cu) < per_cu) per_cu = static_cast<int>(o.waves_per_cu);
-  const int grid = size_grid(per_cu, o.roots ? o.num_roots : g->n);
+  const int grid = size_grid(per_cu, g->nnz);
   std::memset(&P->ma, 0, sizeof(P->ma));
   MotifArgs& A = P->ma;
   int64_t cap_total = 0;

@@ -89,6 +89,7 @@ struct MotifLds {
   int* ev;                  // [kLeafLds] leaf level: copy of the (k-2)-traversal's list
   uint8_t* em;              // [kLeafLds] and of its masks
   unsigned* filt;           // [kFilterWords] membership filter of the LDS copy (zero between calls)
+  int* lflag;               // [1] the (k-2)-level list was written straight into ev / em
 };
 
 __device__ __forceinline__ int off_of(int i) { return i * (i - 1) / 2 - 1; }  // bitmap field of v_i, i >= 2
@@ -117,6 +118,7 @@ __device__ MotifLds carve(unsigned char* smem, int ncls) {
   L.ev = reinterpret_cast<int*>(take(kLeafLds * 4));
   L.em = reinterpret_cast<uint8_t*>(take(kLeafLds));
   L.filt = reinterpret_cast<unsigned*>(take(kFilterWords * 4));
+  L.lflag = reinterpret_cast<int*>(take(16));
   return L;
 }
 
@@ -168,10 +170,7 @@ __device__ void extend_level(const MotifArgs& A, const MotifLds& L, MotifWave& M
   const int lane = lane_id();
   int32_t* Ev = MW.vert + A.level_off[s];
   uint8_t* Em = MW.mask + A.level_off[s];
-  int32_t* Nv = MW.vert + A.level_off[s + 1];
-  uint8_t* Nm = MW.mask + A.level_off[s + 1];
   const int ns = L.esize[s];
-  const int64_t cap = A.level_cap[s + 1];
   const int64_t xb = A.rp[x];
   const int dx = static_cast<int>(A.rp[x + 1] - xb);
   const int v0 = L.tr[0];
@@ -196,6 +195,11 @@ __device__ void extend_level(const MotifArgs& A, const MotifLds& L, MotifWave& M
     if (lane == 0) atomicOr(A.flags + 1, 1);
     nn = A.dmax;
   }
+  // the leaf level's list goes straight to LDS when it fits
+  const bool to_lds = s + 1 == A.k - 2 && static_cast<int64_t>(ns) - 1 + nn <= kLeafLds;
+  int32_t* Nv = to_lds ? L.ev : MW.vert + A.level_off[s + 1];
+  uint8_t* Nm = to_lds ? L.em : MW.mask + A.level_off[s + 1];
+  const int64_t cap = to_lds ? kLeafLds : A.level_cap[s + 1];
   wave_sync();
   // merge the surviving old entries and the new ones (both sorted by id)
   for (int j = lane; j < ns; j += kWave) {
@@ -227,6 +231,7 @@ __device__ void extend_level(const MotifArgs& A, const MotifLds& L, MotifWave& M
   }
   const unsigned mx = Em[px] & ((1u << s) - 1u);
   if (lane == 0) {
+    L.lflag[0] = to_lds ? 1 : 0;
     L.esize[s + 1] = static_cast<int>(nsz);
     L.tr[s] = x;
     L.code[s + 1] = L.code[s] | (s >= 2 ? static_cast<int>(mx << off_of(s)) : 0);
@@ -246,15 +251,22 @@ __device__ __forceinline__ int leaf_level(const MotifArgs& A, const MotifLds& L,
                           const Task& t, int wave_gid, uint64_t& nodes_l, uint64_t& leaves_l, uint64_t& reads_l) {
   const int lane = lane_id();
   const int ns = L.esize[s];
-  // the list (and masks) in LDS when it fits, else in this wave's global region
-  const bool in_lds = ns <= kLeafLds;
+  // the list (and masks) in LDS: written there by extend_level, or copied when
+  // it fits; else it stays in this wave's global region
+  const bool direct = s >= 2 && L.lflag[0] != 0;
+  const bool in_lds = direct || ns <= kLeafLds;
   if (in_lds) {
     const int32_t* Gv = MW.vert + A.level_off[s];
     const uint8_t* Gm = MW.mask + A.level_off[s];
     for (int i = lane; i < ns; i += kWave) {
-      const int y = Gv[i];
-      L.ev[i] = y;
-      L.em[i] = Gm[i];
+      int y;
+      if (direct) {
+        y = L.ev[i];
+      } else {
+        y = Gv[i];
+        L.ev[i] = y;
+        L.em[i] = Gm[i];
+      }
       atomicOr(&L.filt[(y >> 5) & (kFilterWords - 1)], 1u << (y & 31));
     }
   }
@@ -552,7 +564,7 @@ size_t motif_lds_bytes(int k, int ncls) {
   size_t off = a16(static_cast<size_t>(ncls) * 8) + a16(kBins * kBins * 8) + a16(kBins * 8) + a16(2 * kBins * 4);
   off += a16((kWave + 1) * 8) + a16(kWave * 8) + a16(kWave * 4);
   off += 2 * a16(kSuf * 4) + a16(kSuf * kSuf * 4) + 3 * a16(kSuf * 4);
-  off += a16(kLeafLds * 4) + a16(kLeafLds) + a16(kFilterWords * 4);
+  off += a16(kLeafLds * 4) + a16(kLeafLds) + a16(kFilterWords * 4) + 16;
   return off;
 }
 
