@@ -71,6 +71,21 @@ __device__ __forceinline__ int64_t wave_incl_scan_i64(int64_t x) {
   return x;
 }
 
+// Inclusive prefix maximum over the wave's lanes with DPP moves (no LDS
+// round trips): shifts by 1, 2, 4, 8 inside each row of 16 lanes, then the
+// last lane of rows 0 / 2 into rows 1 / 3 and of row 1 into rows 2 / 3.
+// All lanes must be active.
+__device__ __forceinline__ int wave_incl_max_i32(int x) {
+  constexpr int kLow = -2147483647 - 1;
+  x = max(x, __builtin_amdgcn_update_dpp(kLow, x, 0x111, 0xf, 0xf, false));  // row_shr:1
+  x = max(x, __builtin_amdgcn_update_dpp(kLow, x, 0x112, 0xf, 0xf, false));  // row_shr:2
+  x = max(x, __builtin_amdgcn_update_dpp(kLow, x, 0x114, 0xf, 0xf, false));  // row_shr:4
+  x = max(x, __builtin_amdgcn_update_dpp(kLow, x, 0x118, 0xf, 0xf, false));  // row_shr:8
+  x = max(x, __builtin_amdgcn_update_dpp(kLow, x, 0x142, 0xa, 0xf, false));  // row_bcast:15
+  x = max(x, __builtin_amdgcn_update_dpp(kLow, x, 0x143, 0xc, 0xf, false));  // row_bcast:31
+  return x;
+}
+
 __device__ __forceinline__ int wave_sum_i32(int x) {
 #pragma unroll
   for (int sh = 32; sh >= 1; sh >>= 1) x += __shfl_xor(x, sh, kWave);

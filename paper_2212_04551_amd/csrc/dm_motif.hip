@@ -90,6 +90,7 @@ struct MotifLds {
   uint8_t* em;              // [kLeafLds] and of its masks
   unsigned* filt;           // [kFilterWords] membership filter of the LDS copy (zero between calls)
   int* lflag;               // [1] the (k-2)-level list was written straight into ev / em
+  int* mark;                // [kWave] slice lane whose degree range starts at each item of a batch
 };
 
 __device__ __forceinline__ int off_of(int i) { return i * (i - 1) / 2 - 1; }  // bitmap field of v_i, i >= 2
@@ -119,6 +120,7 @@ __device__ MotifLds carve(unsigned char* smem, int ncls) {
   L.em = reinterpret_cast<uint8_t*>(take(kLeafLds));
   L.filt = reinterpret_cast<unsigned*>(take(kFilterWords * 4));
   L.lflag = reinterpret_cast<int*>(take(16));
+  L.mark = reinterpret_cast<int*>(take(kWave * 4));
   return L;
 }
 
@@ -300,14 +302,25 @@ __device__ __forceinline__ int leaf_level(const MotifArgs& A, const MotifLds& L,
       reads_l += static_cast<uint64_t>(total);
     }
     wave_sync();
-    // ---- every (x, neighbour) item of the slice, 64 at a time
+    // ---- every (x, neighbour) item of the slice, 64 at a time.  The owner of
+    // item f0 + lane is the last slice lane whose degree range starts at or
+    // before it: lanes starting inside the batch mark their first item, and a
+    // prefix maximum over the marks (seeded with the owner of f0) assigns them.
+    const int64_t my_start = incl - dx;
+    const bool my_has = dx > 0;
     for (int64_t f0 = 0; f0 < total; f0 += kWave) {
       const int64_t f = f0 + lane;
+      const uint64_t le = ballot(my_has && my_start <= f0);
+      const int o0 = le ? 63 - __builtin_clzll(le) : 0;
+      L.mark[lane] = -1;
+      wave_sync();
+      if (my_has && my_start > f0 && my_start < f0 + kWave) L.mark[my_start - f0] = lane;
+      wave_sync();
+      int o = wave_incl_max_i32(L.mark[lane]);
+      o = o > o0 ? o : o0;
+      o = o < kWave - 1 ? o : kWave - 1;
       int key = -1;
       if (f < total) {
-        int o = 0;  // last slice lane whose start is <= f
-        for (int step = kWave / 2; step >= 1; step >>= 1)
-          if (L.sl_start[o + step] <= f) o += step;
         const int w = A.col[L.sl_base[o] + (f - L.sl_start[o])];
         const bool maybe = !in_lds || ((L.filt[(w >> 5) & (kFilterWords - 1)] >> (w & 31)) & 1u);
         if (w > v0) {
@@ -564,7 +577,7 @@ size_t motif_lds_bytes(int k, int ncls) {
   size_t off = a16(static_cast<size_t>(ncls) * 8) + a16(kBins * kBins * 8) + a16(kBins * 8) + a16(2 * kBins * 4);
   off += a16((kWave + 1) * 8) + a16(kWave * 8) + a16(kWave * 4);
   off += 2 * a16(kSuf * 4) + a16(kSuf * kSuf * 4) + 3 * a16(kSuf * 4);
-  off += a16(kLeafLds * 4) + a16(kLeafLds) + a16(kFilterWords * 4) + 16;
+  off += a16(kLeafLds * 4) + a16(kLeafLds) + a16(kFilterWords * 4) + 16 + a16(kWave * 4);
   return off;
 }
 
