@@ -308,30 +308,33 @@ __device__ __forceinline__ int leaf_level(const MotifArgs& A, const MotifLds& L,
     // prefix maximum over the marks (seeded with the owner of f0) assigns them.
     const int64_t my_start = incl - dx;
     const bool my_has = dx > 0;
-    for (int64_t f0 = 0; f0 < total; f0 += kWave) {
-      const int64_t f = f0 + lane;
-      const uint64_t le = ballot(my_has && my_start <= f0);
-      const int o0 = le ? 63 - __builtin_clzll(le) : 0;
+    // owner of item fb + lane (all lanes active)
+    auto owner_of = [&](int64_t fb) -> int {
+      const uint64_t le = ballot(my_has && my_start <= fb);
+      const int ob = le ? 63 - __builtin_clzll(le) : 0;
       L.mark[lane] = -1;
       wave_sync();
-      if (my_has && my_start > f0 && my_start < f0 + kWave) L.mark[my_start - f0] = lane;
+      if (my_has && my_start > fb && my_start < fb + kWave) L.mark[my_start - fb] = lane;
       wave_sync();
       int o = wave_incl_max_i32(L.mark[lane]);
-      o = o > o0 ? o : o0;
-      o = o < kWave - 1 ? o : kWave - 1;
+      o = o > ob ? o : ob;
+      return o < kWave - 1 ? o : kWave - 1;
+    };
+    // key of neighbour w of the x at slice lane o (-1: no leaf)
+    auto classify = [&](int w, int o) -> int {
       int key = -1;
-      if (f < total) {
-        const int w = A.col[L.sl_base[o] + (f - L.sl_start[o])];
-        const bool maybe = !in_lds || ((L.filt[(w >> 5) & (kFilterWords - 1)] >> (w & 31)) & 1u);
-        if (w > v0) {
-          const int jj = maybe ? lower_bound_g(Ev, ns, w) : ns;
-          if (jj < ns && Ev[jj] == w) {
-            if (jj > c + o && canonical(L, s, w, Em[jj])) key = L.sl_mask[o] * kBins + static_cast<int>(Em[jj] & low);
-          } else if (!in_tr(L, s, w)) {
-            key = kBins * kBins + L.sl_mask[o];
-          }
+      const bool maybe = !in_lds || ((L.filt[(w >> 5) & (kFilterWords - 1)] >> (w & 31)) & 1u);
+      if (w > v0) {
+        const int jj = maybe ? lower_bound_g(Ev, ns, w) : ns;
+        if (jj < ns && Ev[jj] == w) {
+          if (jj > c + o && canonical(L, s, w, Em[jj])) key = L.sl_mask[o] * kBins + static_cast<int>(Em[jj] & low);
+        } else if (!in_tr(L, s, w)) {
+          key = kBins * kBins + L.sl_mask[o];
         }
       }
+      return key;
+    };
+    auto aggregate = [&](int key) {
       uint64_t act = ballot(key >= 0);
       while (act) {
         const int l = __ffsll(static_cast<long long>(act)) - 1;
@@ -343,6 +346,18 @@ __device__ __forceinline__ int leaf_level(const MotifArgs& A, const MotifLds& L,
         }
         act &= ~same;
       }
+    };
+    // two items per lane and pass, both adjacency reads in flight together
+    for (int64_t f0 = 0; f0 < total; f0 += 2 * kWave) {
+      const int oa = owner_of(f0);
+      const int ob = owner_of(f0 + kWave);
+      const int64_t fa = f0 + lane, fb = f0 + kWave + lane;
+      const int wa = fa < total ? A.col[L.sl_base[oa] + (fa - L.sl_start[oa])] : -1;
+      const int wb = fb < total ? A.col[L.sl_base[ob] + (fb - L.sl_start[ob])] : -1;
+      const int ka = fa < total ? classify(wa, oa) : -1;
+      const int kb = fb < total ? classify(wb, ob) : -1;
+      aggregate(ka);
+      aggregate(kb);
     }
     wave_sync();
     // ---- donation of the untried x range
