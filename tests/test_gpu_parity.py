@@ -49,6 +49,15 @@ def test_clique_complete(n):
         assert dm.count_cliques(h, k) == math.comb(n, k), (n, k)
 
 
+def test_clique_large_k_complete():
+    """K_40 at k = 10..12 (non-zero large-k counts, C(40, 12) = 5,586,853,480),
+    with the default schedule and with small chunks on one wave per CU."""
+    h = dm.load_graph(gg.complete(40))
+    for k in (10, 11, 12):
+        assert dm.count_cliques(h, k) == math.comb(40, k), k
+        assert dm.count_cliques(h, k, chunk=3, waves_per_cu=1) == math.comb(40, k), k
+
+
 def test_clique_dense_wide_roots():
     """Cocktail party on 80 pairs (160 vertices, degree 158): roots wider than
     128 keep their rows in global memory and hand dense re-indexed sets with
