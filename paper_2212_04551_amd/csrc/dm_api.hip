@@ -272,6 +272,11 @@ struct dm_graph {
   // fingerprint, grid and chunks per wave stay the same
   bool feat_ready = false;
   Buf feat, pred, lorder, lqroot, lqbounds, lqkey;
+  // cache of every root's bitmap rows (clique counting): offsets, then rows;
+  // filled by the first counting launch over all roots, read by later ones
+  bool rc_layout = false, rc_ready = false;
+  int64_t rc_words = 0;
+  Buf rcoff, rcache;
   bool lq_valid = false;
   unsigned long long lq_key = 0;
   int lq_grid = 0, lq_per_wave = 0;
@@ -503,6 +508,10 @@ namespace {
 // built.  enqueue() only issues the clears, the kernel and the copy-back, so a
 // prepared launch can be timed repeatedly (autotuner) or captured once into a
 // hipGraph and replayed (batches).
+// Largest row cache a graph handle keeps (bytes); larger graphs rebuild each
+// root's rows on every launch.
+constexpr size_t kRowCacheMax = size_t(4) << 30;
+
 struct Prepared {
   bool clique = true;
   CliqueArgs ca;
@@ -518,6 +527,7 @@ struct Prepared {
   unsigned long long* stats = nullptr;
   int64_t stats_words = 0;
   int* flags_dev = nullptr;
+  bool* rc_done = nullptr;  // set once this launch has filled the graph's row cache
 };
 
 dm_status check_flags(const int* flags) {
@@ -549,7 +559,9 @@ dm_status run_prepared(const Prepared& P, hipStream_t s, uint64_t* host_out) {
   hipError_t e = enqueue(P, s, host_out, flags);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, "kernel / copy-back");
-  return check_flags(flags);
+  const dm_status st = check_flags(flags);
+  if (st == DM_OK && P.rc_done) *P.rc_done = true;
+  return st;
 }
 
 // queue of explicit roots (original ids), optionally mapped into rank space
@@ -705,12 +717,33 @@ dm_status prepare_clique(dm_graph* g, int k, const Opt& o, hipStream_t s, const 
   A.wave_stats_len = static_cast<int>(o.wave_stats_len);
   A.rows_global = g->rows.as<unsigned long long>();
   A.prune = o.root_stats ? 0 : 1;
+  // row cache: filled by a counting launch over all roots (not a recording
+  // one, whose rows path reads member degrees), read by every later launch
+  A.rc_mode = 0;
+  A.rcache = nullptr;
+  A.rcoff = nullptr;
+  if (!o.root_stats && k >= 3) {
+    if (!g->rc_layout) {
+      HIP_OR_RETURN(g->rcoff.ensure(sizeof(int64_t) * (static_cast<size_t>(g->n) + 1)), "row cache: allocate");
+      HIP_OR_RETURN(row_cache_layout(g->drp.as<int64_t>(), g->n, g->rcoff.as<int64_t>(), &g->rc_words, s),
+                    "row cache: layout");
+      g->rc_layout = true;
+    }
+    const size_t bytes = sizeof(uint64_t) * static_cast<size_t>(g->rc_words > 0 ? g->rc_words : 1);
+    if (bytes <= kRowCacheMax && (g->rc_ready || !o.roots)) {
+      HIP_OR_RETURN(g->rcache.ensure(bytes), "row cache: allocate");
+      A.rc_mode = g->rc_ready ? 2 : 1;
+      A.rcache = g->rcache.as<unsigned long long>();
+      A.rcoff = g->rcoff.as<int64_t>();
+    }
+  }
   A.S = S;
   P->clique = true;
   P->grid = grid;
   P->lds = lds;
   P->nq = S.nq;
   common_prepare(g, o, P, static_cast<size_t>(ngraphs));
+  P->rc_done = A.rc_mode == 1 ? &g->rc_ready : nullptr;
   return DM_OK;
 }
 
@@ -822,7 +855,9 @@ dm_status time_launch(dm_graph* g, int op, int k, const Opt& o, hipStream_t s, c
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
   if (e != hipSuccess) return hip_fail(e, "tune: launch");
-  return check_flags(flags);
+  st = check_flags(flags);
+  if (st == DM_OK && P.rc_done) *P.rc_done = true;
+  return st;
 }
 
 dm_status autotune(dm_graph* g, int op, int k, const Opt& base, hipStream_t s, const int32_t* root_graph, int ngraphs,
@@ -993,6 +1028,7 @@ dm_status run_captured(BatchCache* B, const Prepared& P, uint64_t* out) {
   if (e != hipSuccess) return hip_fail(e, "batch: graph launch");
   dm_status st = check_flags(C->host_flags);
   if (st == DM_OK) std::memcpy(out, C->host_out, sizeof(uint64_t) * C->out_count);
+  if (st == DM_OK && P.rc_done) *P.rc_done = true;
   return st;
 }
 

@@ -553,11 +553,14 @@ __device__ void run_task(const CliqueArgs& A, const CliqueLds& L, uint64_t* rows
   const int64_t base = A.rp[v];
   const int d = static_cast<int>(A.rp[v + 1] - base);
   const int hi_t = t.hi < d ? t.hi : d;
-  // rows of N+(v): in LDS (stride kLocalMax) when d <= kLocalMax, else in
-  // this wave's global region (stride dmax)
+  // rows of N+(v): in LDS (stride kLocalMax) when d <= kLocalMax, else in the
+  // graph's row cache (stride d) when there is one, else in this wave's global
+  // region (stride dmax).  The cache is filled by the first launch on a graph
+  // (rc_mode 1) and read by later ones (rc_mode 2).
   const bool lds_rows = d <= kLocalMax;
-  uint64_t* rows = lds_rows ? L.rows : rows_g;
-  const int rs = lds_rows ? kLocalMax : dmax;
+  uint64_t* crow = A.rc_mode ? reinterpret_cast<uint64_t*>(A.rcache) + A.rcoff[v] : nullptr;
+  uint64_t* rows = lds_rows ? L.rows : (A.rc_mode ? crow : rows_g);
+  const int rs = lds_rows ? kLocalMax : (A.rc_mode ? d : dmax);
   uint64_t nodes_l = 0, leaves_l = 0, reads_l = 0;  // per-lane partial stats
   if (t.full_root && lane == 0) {
     nodes_l += (k >= 2) ? 1 : 0;
@@ -571,252 +574,274 @@ __device__ void run_task(const CliqueArgs& A, const CliqueLds& L, uint64_t* rows
       WA.acc += c;
       leaves_l += c;
     }
-  } else if (d > 0 && (!A.prune || d >= k - 1) && hi_t > t.lo) {
-    // ---- load N+(v), out-degree prefix of its members (Extend, coalesced)
-    int running = 0;
-    for (int c = 0; c < d; c += kWave) {
-      const int i = c + lane;
-      int od = 0;
-      if (i < d) {
-        const int u = A.col[base + i];
-        L.nbr[i] = u;
-        od = static_cast<int>(A.rp[u + 1] - A.rp[u]);
-      }
-      int incl = od;
-#pragma unroll
-      for (int sh = 1; sh < kWave; sh <<= 1) {
-        int y = __shfl_up(incl, sh, kWave);
-        if (lane >= sh) incl += y;
-      }
-      if (i < d) L.offs[i] = running + incl - od;
-      running += read_lane(incl, kWave - 1);
-    }
-    running = uni(running);
-    if (lane == 0) L.offs[d] = running;
+  } else if (d > 0 && hi_t > t.lo && (!A.prune || d >= k - 1 || A.rc_mode == 1)) {
     const int Wd = (d + 63) >> 6;
-    // ---- adjacency of N+(v) restricted to itself, as bitmap rows: a block
-    // of rows at a time in the LDS tile L.rows (LDS atomics), then stored to
-    // the global region for roots wider than kLocalMax (one write per word)
-    const int tile_rows = lds_rows ? d : (2 * kLocalMax) / Wd;
-    for (int p0 = 0; p0 < d; p0 += tile_rows) {
-      const int p1 = p0 + tile_rows < d ? p0 + tile_rows : d;
-      const int ts = lds_rows ? kLocalMax : tile_rows;  // tile stride
-      for (int idx = lane; idx < Wd * (p1 - p0); idx += kWave) {
-        const int w = idx / (p1 - p0), p = idx - w * (p1 - p0);
-        L.rows[w * ts + p] = 0ull;
-      }
-      wave_sync();
-      for (int tt = L.offs[p0] + lane; tt < L.offs[p1]; tt += kWave) {
-        int lo = p0, hi = p1;  // i = last index with offs[i] <= tt
-        while (hi - lo > 1) {
-          const int mid = (lo + hi) >> 1;
-          if (L.offs[mid] <= tt) lo = mid; else hi = mid;
+    if (A.rc_mode == 2) {
+      // ---- rows from the cache: wide roots read them in place, the rest are
+      // copied to LDS
+      if (lds_rows) {
+        for (int idx = lane; idx < Wd * d; idx += kWave) {
+          const int w = idx / d, p = idx - w * d;
+          L.rows[w * kLocalMax + p] = crow[static_cast<size_t>(w) * d + p];
         }
-        const int i = lo;
-        const int e = A.col[A.rp[L.nbr[i]] + (tt - L.offs[i])];
-        int a = i + 1, b = d;  // e > nbr[i], so search above i
-        while (a < b) {
-          const int mid = (a + b) >> 1;
-          if (L.nbr[mid] < e) a = mid + 1; else b = mid;
-        }
-        if (a < d && L.nbr[a] == e) atomicOr(reinterpret_cast<unsigned long long*>(&L.rows[(a >> 6) * ts + (i - p0)]), 1ull << (a & 63));
+        wave_sync();
       }
-      wave_sync();
-      if (!lds_rows) {
+    } else {
+      // ---- load N+(v), out-degree prefix of its members (Extend, coalesced)
+      int running = 0;
+      for (int c = 0; c < d; c += kWave) {
+        const int i = c + lane;
+        int od = 0;
+        if (i < d) {
+          const int u = A.col[base + i];
+          L.nbr[i] = u;
+          od = static_cast<int>(A.rp[u + 1] - A.rp[u]);
+        }
+        int incl = od;
+#pragma unroll
+        for (int sh = 1; sh < kWave; sh <<= 1) {
+          int y = __shfl_up(incl, sh, kWave);
+          if (lane >= sh) incl += y;
+        }
+        if (i < d) L.offs[i] = running + incl - od;
+        running += read_lane(incl, kWave - 1);
+      }
+      running = uni(running);
+      if (lane == 0) L.offs[d] = running;
+      // ---- adjacency of N+(v) restricted to itself, as bitmap rows: a block
+      // of rows at a time in the LDS tile L.rows (LDS atomics), then stored to
+      // the global region for roots wider than kLocalMax (one write per word)
+      const int tile_rows = lds_rows ? d : (2 * kLocalMax) / Wd;
+      for (int p0 = 0; p0 < d; p0 += tile_rows) {
+        const int p1 = p0 + tile_rows < d ? p0 + tile_rows : d;
+        const int ts = lds_rows ? kLocalMax : tile_rows;  // tile stride
         for (int idx = lane; idx < Wd * (p1 - p0); idx += kWave) {
           const int w = idx / (p1 - p0), p = idx - w * (p1 - p0);
-          rows[static_cast<size_t>(w) * rs + p0 + p] = L.rows[w * ts + p];
+          L.rows[w * ts + p] = 0ull;
         }
         wave_sync();
-      }
-    }
-    // ---- level-1 candidate set and the task prefix
-    for (int w = lane; w < Wd; w += kWave) {
-      const int rem = d - w * 64;
-      L.stk[1 * W + w] = rem >= 64 ? ~0ull : ((1ull << rem) - 1);
-    }
-    wave_sync();
-    for (int s = 1; s < t.depth; ++s) {
-      const int p = L.cur[s];
-      for (int w = lane; w < Wd; w += kWave) L.stk[(s + 1) * W + w] = L.stk[s * W + w] & rows[static_cast<size_t>(w) * rs + p];
-      wave_sync();
-    }
-    // roots with at most 128 out-neighbours: their rows already are local rows
-    // (positions = local ids, Wd <= 2 words, in LDS with stride kLocalMax)
-    const bool solver = A.prune != 0;
-    const bool root_local = solver && lds_rows;
-    auto add_acc = [&](uint64_t x) {
-      const uint64_t before = WA.acc;
-      WA.acc += x;
-      if (WA.acc < before) WA.ovf = 1;
-    };
-
-    // leaf-parent step: traversal of size s = k-2 with candidate set C_s;
-    // each lane takes extensions p (one per word) inside [lo, hi).
-    auto leaf_parent = [&](int s, int lo, int hi) {
-      const uint64_t* C = L.stk + s * W;
-      for (int w0 = 0; w0 < Wd; ++w0) {
-        const int p = w0 * 64 + lane;
-        const bool on = p >= lo && p < hi && p < d && ((C[w0] >> lane) & 1ull);
-        if (on) {
-          uint64_t pc = 0;
-          for (int w = w0; w < Wd; ++w) pc += static_cast<uint64_t>(__popcll(C[w] & rows[static_cast<size_t>(w) * rs + p]));
-          const uint64_t before = WA.acc;
-          WA.acc += pc;
-          if (WA.acc < before) WA.ovf = 1;
-          nodes_l += 1;
-          reads_l += static_cast<uint64_t>(L.offs[p + 1] - L.offs[p]);
-          leaves_l += pc;
+        for (int tt = L.offs[p0] + lane; tt < L.offs[p1]; tt += kWave) {
+          int lo = p0, hi = p1;  // i = last index with offs[i] <= tt
+          while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (L.offs[mid] <= tt) lo = mid; else hi = mid;
+          }
+          const int i = lo;
+          const int e = A.col[A.rp[L.nbr[i]] + (tt - L.offs[i])];
+          int a = i + 1, b = d;  // e > nbr[i], so search above i
+          while (a < b) {
+            const int mid = (a + b) >> 1;
+            if (L.nbr[mid] < e) a = mid + 1; else b = mid;
+          }
+          if (a < d && L.nbr[a] == e) atomicOr(reinterpret_cast<unsigned long long*>(&L.rows[(a >> 6) * ts + (i - p0)]), 1ull << (a & 63));
         }
-      }
-    };
-
-    const int s0 = t.depth;
-    // The dense solver has a single call site (so it is inlined once): the
-    // DFS records a pending job and the loop head runs it.  Jobs are bounded
-    // (one-word sets, or at most 4 remaining levels on two-word sets) because
-    // a job cannot be donated.
-    bool job = false, job_last = false;
-    int job_nw = 1, job_q = 0, job_stride = 0, job_lo = 0, job_hi = 0;
-    int job_depth = 0, job_hipos = 0;
-    const int* job_map = nullptr;
-    const uint64_t* job_C = nullptr;
-    const uint64_t* job_R = nullptr;
-    // Fast path (at most 64 words): lane w keeps word w of the current level's
-    // candidate set in a register, so choosing the next extension is a ballot
-    // and extending it is one row read per lane.  cur / hiv entries are
-    // written by every lane with the same value, so no barrier is needed to
-    // read them back.
-    const bool fast = Wd <= kWave;
-    uint64_t cw = 0;
-    int depth = s0;
-    if (root_local && k - s0 <= kSolverMaxQ && (k - s0 <= 3 || d <= 64)) {
-      job = job_last = true;
-      job_nw = Wd;
-      job_C = L.stk + s0 * W;
-      job_q = k - s0;
-      job_R = L.rows;
-      job_stride = kLocalMax;
-      job_lo = t.lo;
-      job_hi = hi_t;
-      job_depth = s0;
-      job_hipos = hi_t;
-      job_map = nullptr;
-    } else if (s0 == k - 2) {
-      leaf_parent(s0, t.lo, hi_t);
-      depth = -1;
-    } else {
-      L.cur[depth] = t.lo - 1;
-      L.hiv[depth] = hi_t;
-      if (fast && lane < Wd) cw = L.stk[depth * W + lane];
-      wave_sync();
-    }
-    int steps = 0;
-    while (depth >= 0) {
-      if (job) {
-        const JobCtx J{&A.S, v, t.stat, job_depth, job_hipos, job_map, L.cur, wave_gid};
-        add_acc(small_solve_any(job_nw, job_C, job_q, job_R, job_stride, job_lo, job_hi, L.pst, J));
-        job = false;
-        if (job_last) break;
-      }
-      int u;
-      if (fast) {
-        const int from = L.cur[depth] + 1, to = L.hiv[depth];
-        const uint64_t m = lane < Wd ? (cw & range_mask64(from - 64 * lane, to - 64 * lane)) : 0ull;
-        const uint64_t bl = ballot(m != 0ull);
-        if (!bl) {
-          u = -1;
-        } else {
-          const int l = __ffsll(static_cast<long long>(bl)) - 1;
-          const uint64_t wm = __shfl(m, l, kWave);
-          u = uni(64 * l + __builtin_ctzll(wm));
-        }
-      } else {
-        u = next_bit(L.stk + depth * W, L.cur[depth] + 1, L.hiv[depth]);
-      }
-      if (u < 0) {
-        if (depth == s0) break;
-        --depth;
-        if (fast && lane < Wd) cw = L.stk[depth * W + lane];
-        continue;
-      }
-      L.cur[depth] = u;
-      if (lane == 0) {
-        nodes_l += 1;
-        reads_l += static_cast<uint64_t>(L.offs[u + 1] - L.offs[u]);
-      }
-      int cnt = 0;
-      uint64_t x = 0;
-      if (fast) {
-        if (lane < Wd) x = cw & rows[static_cast<size_t>(lane) * rs + u];
-        cnt = uni(wave_sum_i32(__popcll(x)));
-      } else {
-        for (int w = lane; w < Wd; w += kWave) {
-          const uint64_t y = L.stk[depth * W + w] & rows[static_cast<size_t>(w) * rs + u];
-          L.stk[(depth + 1) * W + w] = y;
-          cnt += __popcll(y);
-        }
-        cnt = uni(wave_sum_i32(cnt));
         wave_sync();
-      }
-      const int q = k - depth - 1;  // vertices still to add below the child
-      if (!A.prune || cnt >= q) {
-        const bool bounded = q <= kSolverMaxQ && (cnt <= 64 || q <= 4);
-        const bool need_lds = (solver && bounded && (root_local || cnt <= kReindexMax)) || depth + 1 == k - 2;
-        if (fast && need_lds) {
-          if (lane < Wd) L.stk[(depth + 1) * W + lane] = x;
+        if (!lds_rows) {
+          for (int idx = lane; idx < Wd * (p1 - p0); idx += kWave) {
+            const int w = idx / (p1 - p0), p = idx - w * (p1 - p0);
+            rows[static_cast<size_t>(w) * rs + p0 + p] = L.rows[w * ts + p];
+          }
           wave_sync();
         }
-        if (root_local && bounded) {
-          job = true;
-          job_nw = Wd;
-          job_C = L.stk + (depth + 1) * W;
-          job_q = q;
-          job_R = L.rows;
-          job_stride = kLocalMax;
-          job_lo = 0;
-          job_hi = d;
-          job_depth = depth + 1;
-          job_hipos = d;
-          job_map = nullptr;
-        } else if (solver && bounded && cnt <= kReindexMax) {
-          job_nw = reindex(L.stk + (depth + 1) * W, Wd, rows, rs, L);
-          job = true;
-          job_C = L.cset;
-          job_q = q;
-          job_R = L.lr;
-          job_stride = kReindexMax;
-          job_lo = 0;
-          job_hi = kReindexMax;
-          job_depth = depth + 1;
-          job_hipos = d;
-          job_map = L.pos;
-        } else if (depth + 1 == k - 2) {
-          leaf_parent(depth + 1, 0, d);
-        } else {
-          if (fast) {
-            if (lane < Wd) L.stk[(depth + 1) * W + lane] = x;
-            cw = x;
-          }
-          ++depth;
-          L.cur[depth] = -1;
-          L.hiv[depth] = d;
-          if (!fast) wave_sync();
+      }
+      if (A.rc_mode == 1 && lds_rows) {
+        for (int idx = lane; idx < Wd * d; idx += kWave) {
+          const int w = idx / d, p = idx - w * d;
+          crow[static_cast<size_t>(w) * d + p] = L.rows[w * kLocalMax + p];
         }
       }
-      // ---- donation (Section IV-D redistribute, done by the busy wave)
-      if (A.S.donate && (++steps % A.S.period) == 0 && sched_want_donation(A.S)) {
+    }
+    // a root with fewer than k-1 out-neighbours has no k-clique: when it is
+    // here only to fill the row cache, the counting below is skipped
+    if (!A.prune || d >= k - 1) {
+      // ---- level-1 candidate set and the task prefix
+      for (int w = lane; w < Wd; w += kWave) {
+        const int rem = d - w * 64;
+        L.stk[1 * W + w] = rem >= 64 ? ~0ull : ((1ull << rem) - 1);
+      }
+      wave_sync();
+      for (int s = 1; s < t.depth; ++s) {
+        const int p = L.cur[s];
+        for (int w = lane; w < Wd; w += kWave) L.stk[(s + 1) * W + w] = L.stk[s * W + w] & rows[static_cast<size_t>(w) * rs + p];
         wave_sync();
-        for (int s = s0; s <= depth; ++s) {
-          const int from = L.cur[s] + 1, to = L.hiv[s];
-          const int c = count_bits(L.stk + s * W, from, to);
-          if (c >= 2) {
-            const int keep = c - c / 2;
-            const int mid = select_bit(L.stk + s * W, from, to, keep + 1);
-            const int pay = task_payload(v, t.stat, s, mid, to, L.cur);
-            if (sched_publish(A.S, pay, wave_gid)) L.hiv[s] = mid;
+      }
+      // roots with at most 128 out-neighbours: their rows already are local rows
+      // (positions = local ids, Wd <= 2 words, in LDS with stride kLocalMax)
+      const bool solver = A.prune != 0;
+      const bool root_local = solver && lds_rows;
+      auto add_acc = [&](uint64_t x) {
+        const uint64_t before = WA.acc;
+        WA.acc += x;
+        if (WA.acc < before) WA.ovf = 1;
+      };
+
+      // leaf-parent step: traversal of size s = k-2 with candidate set C_s;
+      // each lane takes extensions p (one per word) inside [lo, hi).
+      auto leaf_parent = [&](int s, int lo, int hi) {
+        const uint64_t* C = L.stk + s * W;
+        for (int w0 = 0; w0 < Wd; ++w0) {
+          const int p = w0 * 64 + lane;
+          const bool on = p >= lo && p < hi && p < d && ((C[w0] >> lane) & 1ull);
+          if (on) {
+            uint64_t pc = 0;
+            for (int w = w0; w < Wd; ++w) pc += static_cast<uint64_t>(__popcll(C[w] & rows[static_cast<size_t>(w) * rs + p]));
+            const uint64_t before = WA.acc;
+            WA.acc += pc;
+            if (WA.acc < before) WA.ovf = 1;
+            nodes_l += 1;
+            reads_l += static_cast<uint64_t>(L.offs[p + 1] - L.offs[p]);
+            leaves_l += pc;
+          }
+        }
+      };
+
+      const int s0 = t.depth;
+      // The dense solver has a single call site (so it is inlined once): the
+      // DFS records a pending job and the loop head runs it.  Jobs are bounded
+      // (one-word sets, or at most 4 remaining levels on two-word sets) because
+      // a job cannot be donated.
+      bool job = false, job_last = false;
+      int job_nw = 1, job_q = 0, job_stride = 0, job_lo = 0, job_hi = 0;
+      int job_depth = 0, job_hipos = 0;
+      const int* job_map = nullptr;
+      const uint64_t* job_C = nullptr;
+      const uint64_t* job_R = nullptr;
+      // Fast path (at most 64 words): lane w keeps word w of the current level's
+      // candidate set in a register, so choosing the next extension is a ballot
+      // and extending it is one row read per lane.  cur / hiv entries are
+      // written by every lane with the same value, so no barrier is needed to
+      // read them back.
+      const bool fast = Wd <= kWave;
+      uint64_t cw = 0;
+      int depth = s0;
+      if (root_local && k - s0 <= kSolverMaxQ && (k - s0 <= 3 || d <= 64)) {
+        job = job_last = true;
+        job_nw = Wd;
+        job_C = L.stk + s0 * W;
+        job_q = k - s0;
+        job_R = L.rows;
+        job_stride = kLocalMax;
+        job_lo = t.lo;
+        job_hi = hi_t;
+        job_depth = s0;
+        job_hipos = hi_t;
+        job_map = nullptr;
+      } else if (s0 == k - 2) {
+        leaf_parent(s0, t.lo, hi_t);
+        depth = -1;
+      } else {
+        L.cur[depth] = t.lo - 1;
+        L.hiv[depth] = hi_t;
+        if (fast && lane < Wd) cw = L.stk[depth * W + lane];
+        wave_sync();
+      }
+      int steps = 0;
+      while (depth >= 0) {
+        if (job) {
+          const JobCtx J{&A.S, v, t.stat, job_depth, job_hipos, job_map, L.cur, wave_gid};
+          add_acc(small_solve_any(job_nw, job_C, job_q, job_R, job_stride, job_lo, job_hi, L.pst, J));
+          job = false;
+          if (job_last) break;
+        }
+        int u;
+        if (fast) {
+          const int from = L.cur[depth] + 1, to = L.hiv[depth];
+          const uint64_t m = lane < Wd ? (cw & range_mask64(from - 64 * lane, to - 64 * lane)) : 0ull;
+          const uint64_t bl = ballot(m != 0ull);
+          if (!bl) {
+            u = -1;
+          } else {
+            const int l = __ffsll(static_cast<long long>(bl)) - 1;
+            const uint64_t wm = __shfl(m, l, kWave);
+            u = uni(64 * l + __builtin_ctzll(wm));
+          }
+        } else {
+          u = next_bit(L.stk + depth * W, L.cur[depth] + 1, L.hiv[depth]);
+        }
+        if (u < 0) {
+          if (depth == s0) break;
+          --depth;
+          if (fast && lane < Wd) cw = L.stk[depth * W + lane];
+          continue;
+        }
+        L.cur[depth] = u;
+        if (lane == 0) {
+          nodes_l += 1;
+          reads_l += static_cast<uint64_t>(L.offs[u + 1] - L.offs[u]);
+        }
+        int cnt = 0;
+        uint64_t x = 0;
+        if (fast) {
+          if (lane < Wd) x = cw & rows[static_cast<size_t>(lane) * rs + u];
+          cnt = uni(wave_sum_i32(__popcll(x)));
+        } else {
+          for (int w = lane; w < Wd; w += kWave) {
+            const uint64_t y = L.stk[depth * W + w] & rows[static_cast<size_t>(w) * rs + u];
+            L.stk[(depth + 1) * W + w] = y;
+            cnt += __popcll(y);
+          }
+          cnt = uni(wave_sum_i32(cnt));
+          wave_sync();
+        }
+        const int q = k - depth - 1;  // vertices still to add below the child
+        if (!A.prune || cnt >= q) {
+          const bool bounded = q <= kSolverMaxQ && (cnt <= 64 || q <= 4);
+          const bool need_lds = (solver && bounded && (root_local || cnt <= kReindexMax)) || depth + 1 == k - 2;
+          if (fast && need_lds) {
+            if (lane < Wd) L.stk[(depth + 1) * W + lane] = x;
             wave_sync();
-            break;
+          }
+          if (root_local && bounded) {
+            job = true;
+            job_nw = Wd;
+            job_C = L.stk + (depth + 1) * W;
+            job_q = q;
+            job_R = L.rows;
+            job_stride = kLocalMax;
+            job_lo = 0;
+            job_hi = d;
+            job_depth = depth + 1;
+            job_hipos = d;
+            job_map = nullptr;
+          } else if (solver && bounded && cnt <= kReindexMax) {
+            job_nw = reindex(L.stk + (depth + 1) * W, Wd, rows, rs, L);
+            job = true;
+            job_C = L.cset;
+            job_q = q;
+            job_R = L.lr;
+            job_stride = kReindexMax;
+            job_lo = 0;
+            job_hi = kReindexMax;
+            job_depth = depth + 1;
+            job_hipos = d;
+            job_map = L.pos;
+          } else if (depth + 1 == k - 2) {
+            leaf_parent(depth + 1, 0, d);
+          } else {
+            if (fast) {
+              if (lane < Wd) L.stk[(depth + 1) * W + lane] = x;
+              cw = x;
+            }
+            ++depth;
+            L.cur[depth] = -1;
+            L.hiv[depth] = d;
+            if (!fast) wave_sync();
+          }
+        }
+        // ---- donation (Section IV-D redistribute, done by the busy wave)
+        if (A.S.donate && (++steps % A.S.period) == 0 && sched_want_donation(A.S)) {
+          wave_sync();
+          for (int s = s0; s <= depth; ++s) {
+            const int from = L.cur[s] + 1, to = L.hiv[s];
+            const int c = count_bits(L.stk + s * W, from, to);
+            if (c >= 2) {
+              const int keep = c - c / 2;
+              const int mid = select_bit(L.stk + s * W, from, to, keep + 1);
+              const int pay = task_payload(v, t.stat, s, mid, to, L.cur);
+              if (sched_publish(A.S, pay, wave_gid)) L.hiv[s] = mid;
+              wave_sync();
+              break;
+            }
           }
         }
       }

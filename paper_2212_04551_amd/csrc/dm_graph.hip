@@ -241,6 +241,40 @@ hipError_t launch_fill_u64(unsigned long long* out, int64_t count, unsigned long
     }                                      \
   } while (0)
 
+// words of root v's bitmap rows: ceil(d / 64) words for each of its d members
+__global__ void row_words_kernel(const int64_t* drp, int32_t n, int64_t* words) {
+  const int64_t v = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (v < n) {
+    const int64_t d = drp[v + 1] - drp[v];
+    words[v] = ((d + 63) / 64) * d;
+  }
+}
+
+// Layout of a graph's cached bitmap rows: off[v] = words before root v (n + 1
+// entries; off[n] = total).  `off` needs n + 1 int64 of device memory.
+hipError_t row_cache_layout(const int64_t* drp, int32_t n, int64_t* off, int64_t* total, hipStream_t s) {
+  hipError_t e = hipSuccess;
+  int64_t* words = nullptr;
+  void* temp = nullptr;
+  size_t tb = 0;
+  *total = 0;
+  if (n <= 0) return hipMemsetAsync(off, 0, sizeof(int64_t), s);
+  e = hipMalloc(&words, sizeof(int64_t) * (static_cast<size_t>(n) + 1));
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(row_words_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, drp, n, words);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemsetAsync(words + n, 0, sizeof(int64_t), s);
+  if (e == hipSuccess) e = hipcub::DeviceScan::ExclusiveSum(nullptr, tb, words, off, n + 1, s);
+  if (e == hipSuccess) e = hipMalloc(&temp, tb > 0 ? tb : 16);
+  if (e == hipSuccess) e = hipcub::DeviceScan::ExclusiveSum(temp, tb, words, off, n + 1, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(total, off + n, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (temp) (void)hipFree(temp);
+  if (words) (void)hipFree(words);
+  return e;
+}
+
 hipError_t orient_by_degree(const int64_t* rp, const int32_t* col, int32_t n, int64_t nnz, int32_t* rank,
                             int32_t* order, int64_t* drp, int32_t* dcol, int* dmax_out, hipStream_t s) {
   hipError_t err = hipSuccess;

@@ -29,6 +29,9 @@ struct CliqueArgs {
   unsigned long long* wave_stats;  // 4 per wave, or null
   int wave_stats_len;
   unsigned long long* rows_global; // per-wave bitmap rows when they do not fit in LDS
+  unsigned long long* rcache;      // the graph's cached bitmap rows (root v at rcoff[v], stride d)
+  const int64_t* rcoff;
+  int rc_mode;             // 0: no cache, 1: build it while counting, 2: read it
   int prune;               // skip subtrees that cannot reach k vertices
   Sched S;
 };
@@ -79,6 +82,7 @@ hipError_t relabel_by_rank(const int64_t* rp, const int32_t* col, int32_t n, int
 hipError_t launch_max_degree(const int64_t* rp, int32_t n, int* out, hipStream_t s);
 // map vertex ids through a table: out[i] = map[in[i]]
 hipError_t launch_gather_i32(const int32_t* map, const int32_t* in, int32_t* out, int64_t count, hipStream_t s);
+hipError_t row_cache_layout(const int64_t* drp, int32_t n, int64_t* off, int64_t* total, hipStream_t s);
 // offset copy: out[i] = in[i] + off (int64 row offsets) / (int32 column ids)
 hipError_t launch_offset_i64(const int64_t* in, int64_t* out, int64_t count, int64_t off, hipStream_t s);
 hipError_t launch_offset_i32(const int32_t* in, int32_t* out, int64_t count, int32_t off, hipStream_t s);
