@@ -279,6 +279,29 @@ def test_range_donation_runs_every_root_once():
         assert np.array_equal(st[:, 0], mn) and np.array_equal(st[:, 1], ml)
 
 
+def test_row_cache_any_call_order():
+    """The per-graph row cache is filled by the first counting launch over all
+    roots and read by later ones: a first call at large k (whose pruned roots
+    still fill their rows), root subsets before and after the cache exists, and
+    recording calls all give the oracle's counts."""
+    import torch
+    g = gg.chung_lu(4000, 24000, 2.2, 250.0, 17)[0]
+    ref = {k: O.clique_count(g, k, threads=8) for k in (3, 4, 5, 6, 7)}
+    sub = np.random.default_rng(3).permutation(g.n)[:1000].astype(np.int32)
+    h = dm.load_graph(g)
+    part = dm.count_cliques(h, 4, roots=sub)          # no cache yet: subsets do not fill it
+    assert part == O.clique_count(g, 4, roots=sub, threads=8)
+    assert dm.count_cliques(h, 7) == ref[7]           # fills the cache
+    for k in (3, 4, 5, 6):
+        assert dm.count_cliques(h, k) == ref[k], k    # reads it
+    assert dm.count_cliques(h, 4, roots=sub) == part
+    stats = torch.zeros((g.n, 3), dtype=torch.int64, device="cuda")
+    tot, leaves, nodes, reads = O.clique_count(g, 5, per_root=True, threads=8)
+    assert dm.count_cliques(h, 5, root_stats=stats) == tot
+    st = stats.cpu().numpy().astype(np.uint64)
+    assert np.array_equal(st[:, 0], nodes) and np.array_equal(st[:, 2], reads)
+
+
 def test_root_lists_partition_the_count():
     g = gg.chung_lu(4000, 16000, 2.2, 80.0, 11)[0]
     h = dm.load_graph(g)
