@@ -27,7 +27,7 @@ KS = (3, 4, 5, 6, 7, 8)
 # HBM bytes of the k=8 clique_kernel launch from rocprofv3 (2.0 x FETCH_SIZE +
 # 1.0 x WRITE_SIZE, factors from a copy kernel of known size), valid only for
 # the kernel source they were taken on.
-TRAFFIC = {"source_sha": "baadedc0170249d9", "bytes_per_launch": 2.0 * 5827718.125 * 1024 + 1288861.21875 * 1024}
+TRAFFIC = {"source_sha": "4a8e3702e6c44f06", "bytes_per_launch": 2.0 * 832625.7 * 1024 + 1463881.1 * 1024}
 
 
 def kernel_source_sha(kernel: str = "dm_clique.hip") -> str:
@@ -40,7 +40,7 @@ def kernel_source_sha(kernel: str = "dm_clique.hip") -> str:
 
 # HBM bytes per launch of the motif kernel on the sampled 5-motif workload
 # (same scaling), valid only for the kernel source they were taken on.
-TRAFFIC_MOTIF = {"source_sha": "f28548eaee7b007c", "bytes_per_launch": 2.0 * 263395344.5 * 1024 + 69029313.21875 * 1024}
+TRAFFIC_MOTIF = {"source_sha": "f0fc5084a0a9987d", "bytes_per_launch": 2.0 * 265415101.7 * 1024 + 53041239.1 * 1024}
 # MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz issue 39.3e12 32-bit integer
 # VALU operations per second (bitwise AND and popcount are single-issue ops).
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
