@@ -369,14 +369,19 @@ __device__ __forceinline__ uint64_t lane_solve(const uint64_t (&C)[NW], const ui
           for (int w = 0; w < NW; ++w) cur[w] = ch[w];
           ++d;
         }
-      } else if (d == 0) {
-        d = -1;
-      } else {
-        --d;
-        const uint64_t g0 = d == 0 ? sa0 : (d == 1 ? sb0 : (d == 2 ? sc0 : sd0));
-        const uint64_t g1 = d == 0 ? sa1 : (d == 1 ? sb1 : (d == 2 ? sc1 : sd1));
-        cur[0] = g0;
-        if constexpr (NW == 2) cur[NW - 1] = g1;
+      }
+      // a set used up in this pass is popped in the same pass
+      bool empty = true;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) empty = empty && cur[w] == 0;
+      if (empty) {
+        if (d == 0) {
+          d = -1;
+        } else {
+          --d;
+          cur[0] = d == 0 ? sa0 : (d == 1 ? sb0 : (d == 2 ? sc0 : sd0));
+          if constexpr (NW == 2) cur[NW - 1] = d == 0 ? sa1 : (d == 1 ? sb1 : (d == 2 ? sc1 : sd1));
+        }
       }
     }
   }
