@@ -100,6 +100,8 @@ constexpr int kSolverMaxQ = 8;
 // the waves idle) and while at least this many pair tasks are untaken: the
 // taker rebuilds the root's rows and the prefix first.
 constexpr int kJobDonateMin = 1024;
+// free lanes that trigger a refill of pair tasks in the lane solver
+constexpr int kRefillMin = 8;
 
 // rows the solver reads always live in LDS: an address-space-3 pointer makes
 // every load a ds_read (no flat-address dispatch)
@@ -250,12 +252,15 @@ __device__ __forceinline__ uint64_t lane_solve(const uint64_t (&C)[NW], const ui
   bool done = false;
   int tbase = 0;
   int hi_pos = J.hi_pos;  // end (in positions) of the first members still owned
+  // the next (up to) 64 untaken pair tasks are decoded together, one per lane
+  // (packed i << 8 | j in pend), and handed to free lanes by a lane shuffle
+  int gen_base = 0, gen_n = 0;  // decoded tasks: gen_base .. gen_base + gen_n - 1
+  int pend = 0;
   for (;;) {
     const bool want = !done && d < 0;
     const uint64_t wb = ballot(want);
-    // refill in batches: decoding a task costs a binary search and a select,
-    // so lanes wait until a quarter of the wave is free (or none is busy)
-    if (wb && (__popcll(wb) >= kWave / 4 || ballot(d >= 0) == 0)) {
+    const int nw = __popcll(wb);
+    if (wb && (nw >= kRefillMin || ballot(d >= 0) == 0)) {
       // idle waves elsewhere: hand over the first members whose pair tasks
       // make up about the upper half of the untaken ones
       if (J.S->donate && total - tbase >= kJobDonateMin && sched_want_donation_tail(*J.S)) {
@@ -277,8 +282,12 @@ __device__ __forceinline__ uint64_t lane_solve(const uint64_t (&C)[NW], const ui
           }
         }
       }
-      if (want) {
-        const int t = tbase + mbcnt(wb);
+      if (tbase + nw > gen_base + gen_n && gen_base + gen_n < total) {
+        // decode tasks tbase + lane: binary search over the task prefix for the
+        // first member i, then the (t - pst[i])-th candidate above it
+        gen_base = tbase;
+        gen_n = total - tbase < kWave ? total - tbase : kWave;
+        const int t = tbase + lane;
         if (t < total) {
           int i = 0;  // last member whose task range starts at or before t
 #pragma unroll
@@ -287,11 +296,20 @@ __device__ __forceinline__ uint64_t lane_solve(const uint64_t (&C)[NW], const ui
           uint64_t ci[NW];
 #pragma unroll
           for (int q2 = 0; q2 < NW; ++q2) ci[q2] = C[q2] & lr[q2 * stride + i];
-          const int j = select_nth<NW>(ci, t - pst[i]);
+          pend = (i << 8) | select_nth<NW>(ci, t - pst[i]);
+        }
+      }
+      // task tbase + rank goes to the rank-th free lane; every decoded task
+      // below total lies in [gen_base, gen_base + gen_n)
+      const int t = tbase + mbcnt(wb);
+      const int ij = __shfl(pend, want ? (t - gen_base) & (kWave - 1) : 0, kWave);
+      if (want) {
+        if (t < total) {
+          const int i = ij >> 8, j = ij & 255;
           int cnt = 0;
 #pragma unroll
           for (int q2 = 0; q2 < NW; ++q2) {
-            cur[q2] = ci[q2] & lr[q2 * stride + j];
+            cur[q2] = C[q2] & lr[q2 * stride + i] & lr[q2 * stride + j];
             cnt += __popcll(cur[q2]);
           }
           if (r0 == 1) acc += static_cast<uint64_t>(cnt);
@@ -300,7 +318,7 @@ __device__ __forceinline__ uint64_t lane_solve(const uint64_t (&C)[NW], const ui
           done = true;
         }
       }
-      tbase += __popcll(wb);
+      tbase += nw;
     }
     if (ballot(!done) == 0) break;
     if (d >= 0) {
