@@ -461,19 +461,20 @@ int cu_count() {
 }
 
 constexpr int kSlots = 1024;
-constexpr size_t kCtrlHead = 0;    // u64 qhead
 constexpr size_t kCtrlState = 8;   // u64 state
 constexpr size_t kCtrlIdle = 16;   // int idle
 constexpr size_t kCtrlFlags = 20;  // int flags[2]
 constexpr size_t kCtrlSlots = 32;  // int slot_state[kSlots], then slot_data
+// queue heads (kQueueHeads u64 counters, 128 B apart) after the slot data
+constexpr size_t kCtrlHeads = (kCtrlSlots + sizeof(int) * kSlots + sizeof(int) * kSlots * kTaskInts + 127) & ~size_t(127);
 
-size_t ctrl_bytes() { return kCtrlSlots + sizeof(int) * kSlots + sizeof(int) * kSlots * kTaskInts; }
+size_t ctrl_bytes() { return kCtrlHeads + sizeof(unsigned long long) * kHeadStride * kQueueHeads; }
 
 // scheduler fields common to both kernels
 Sched make_sched(dm_graph* g, const Opt& o, int grid, int64_t nq, const int32_t* qroot, const int32_t* qstat) {
   Sched S{};
   char* c = g->ctrl.as<char>();
-  S.qhead = reinterpret_cast<unsigned long long*>(c + kCtrlHead);
+  S.qhead = reinterpret_cast<unsigned long long*>(c + kCtrlHeads);
   S.state = reinterpret_cast<unsigned long long*>(c + kCtrlState);
   S.idle = reinterpret_cast<int*>(c + kCtrlIdle);
   S.slot_state = reinterpret_cast<int*>(c + kCtrlSlots);

@@ -123,10 +123,17 @@ __device__ __forceinline__ int add_i32(int* p, int v) {
   return __hip_atomic_fetch_add(p, v, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// add v to a global uint64 counter; a wrap sets *flag
+// Relaxed: no data is published through the word.  An acquire / release
+// atomic at agent scope writes back and invalidates this XCD's L2 around the
+// operation, which a per-task atomic must not do.
+__device__ __forceinline__ unsigned long long add_u64_relaxed(unsigned long long* p, unsigned long long v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// add v to a global uint64 counter (read only after the launch); a wrap sets *flag
 __device__ __forceinline__ void add_counter(unsigned long long* p, unsigned long long v, int* flag) {
   if (v == 0) return;
-  unsigned long long old = add_u64(p, v);
+  unsigned long long old = add_u64_relaxed(p, v);
   if (old + v < old) atomicOr(flag, 1);
 }
 
@@ -136,7 +143,7 @@ __device__ __forceinline__ void add_counter(unsigned long long* p, unsigned long
 constexpr unsigned long long kActiveOne = 1ull << 32;
 
 struct Sched {
-  unsigned long long* qhead;  // next queue entry (or chunk index when qbounds != null)
+  unsigned long long* qhead;  // kQueueHeads block counters kHeadStride words apart (one counter when qbounds != null)
   unsigned long long* state;  // (active << 32) | pending
   int* idle;                  // waves waiting for a donated task
   int* slot_state;            // per slot: 0 empty, 1 being written, 2 full, 3 being read
@@ -166,22 +173,47 @@ struct Task {
   int full_root;  // the task starts the root (counts the root node itself)
 };
 
+// The fixed-size root queue is split into blocks of `chunk` entries dealt
+// round-robin to kQueueHeads counters (block B belongs to head B mod
+// kQueueHeads), each on its own 128-byte line: a wave starts at head
+// wave_gid mod kQueueHeads (its XCD when blocks are placed round-robin) and
+// moves on when that head is drained, so no single address takes every grab
+// and the blocks still come out in about queue order.
+constexpr int kQueueHeads = 8;
+constexpr int kHeadStride = 16;  // u64 words between two heads
+
 // Grab the next range of queue entries; returns false when the queue is drained.
 // All lanes get the same result.
-__device__ __forceinline__ bool sched_grab(const Sched& S, int64_t* b, int64_t* e) {
-  long long base = 0;
-  if (lane_id() == 0) base = static_cast<long long>(add_u64(S.qhead, 1ull * (S.qbounds ? 1 : S.chunk)));
-  base = uni64(base);
+__device__ __forceinline__ bool sched_grab(const Sched& S, int* head, unsigned* dead, int wave_gid, int64_t* b,
+                                           int64_t* e) {
   if (S.qbounds) {
-    if (base >= S.nchunks) return false;
-    *b = S.qbounds[base];
-    *e = S.qbounds[base + 1];
-  } else {
-    if (base >= S.nq) return false;
-    *b = base;
-    *e = base + S.chunk < S.nq ? base + S.chunk : S.nq;
+    long long c = 0;
+    if (lane_id() == 0) c = static_cast<long long>(add_u64_relaxed(S.qhead, 1ull));
+    c = uni64(c);
+    if (c >= S.nchunks) return false;
+    *b = S.qbounds[c];
+    *e = S.qbounds[c + 1];
+    return true;
   }
-  return true;
+  const int64_t nblocks = (S.nq + S.chunk - 1) / S.chunk;
+  if (*head < 0) *head = wave_gid % kQueueHeads;
+  for (int tries = 0; tries < kQueueHeads; ++tries) {
+    const int h = (*head + tries) % kQueueHeads;
+    if ((*dead >> h) & 1u) continue;
+    // the queue arrays are read-only inputs: the counter needs no ordering
+    long long j = 0;
+    if (lane_id() == 0) j = static_cast<long long>(add_u64_relaxed(S.qhead + h * kHeadStride, 1ull));
+    j = uni64(j);
+    const int64_t blk = h + static_cast<int64_t>(kQueueHeads) * j;
+    if (blk < nblocks) {
+      *head = h;
+      *b = blk * S.chunk;
+      *e = *b + S.chunk < S.nq ? *b + S.chunk : S.nq;
+      return true;
+    }
+    *dead |= 1u << h;
+  }
+  return false;
 }
 
 __device__ __forceinline__ Task sched_entry(const Sched& S, int64_t e, int hi_default) {
@@ -335,12 +367,16 @@ struct SchedIter {
   int mode;  // 0: taking queue chunks, 1: waiting, 2: running donated work
   int64_t q, e;
   uint64_t t0, t_idle;
+  int head;       // queue head this wave grabs from (-1: not chosen yet)
+  unsigned dead;  // heads found drained
 };
 
 __device__ __forceinline__ void sched_begin(const Sched& S, SchedIter& it) {
   it.mode = 0;
   it.q = it.e = 0;
   it.t0 = it.t_idle = 0;
+  it.head = -1;
+  it.dead = 0;
   if (lane_id() == 0) add_u64(S.state, kActiveOne);
 }
 
@@ -367,7 +403,7 @@ __device__ __forceinline__ bool sched_next(const Sched& S, SchedIter& it, int wa
     }
     if (it.mode == 0) {
       int64_t b, e;
-      if (sched_grab(S, &b, &e)) {
+      if (sched_grab(S, &it.head, &it.dead, wave_gid, &b, &e)) {
         it.q = b;
         it.e = e;
         continue;
