@@ -27,7 +27,7 @@ KS = (3, 4, 5, 6, 7, 8)
 # HBM bytes of the k=8 clique_kernel launch from rocprofv3 (2.0 x FETCH_SIZE +
 # 1.0 x WRITE_SIZE, factors from a copy kernel of known size), valid only for
 # the kernel source they were taken on.
-TRAFFIC = {"source_sha": "4a8e3702e6c44f06", "bytes_per_launch": 2.0 * 832625.7 * 1024 + 1463881.1 * 1024}
+TRAFFIC = {"source_sha": "eab535496a8037fd", "bytes_per_launch": 2.0 * 852669.0 * 1024 + 456354.5 * 1024}
 
 
 def kernel_source_sha(kernel: str = "dm_clique.hip") -> str:
@@ -40,7 +40,7 @@ def kernel_source_sha(kernel: str = "dm_clique.hip") -> str:
 
 # HBM bytes per launch of the motif kernel on the sampled 5-motif workload
 # (same scaling), valid only for the kernel source they were taken on.
-TRAFFIC_MOTIF = {"source_sha": "f0fc5084a0a9987d", "bytes_per_launch": 2.0 * 265415101.7 * 1024 + 53041239.1 * 1024}
+TRAFFIC_MOTIF = {"source_sha": "648a55e4ceb3b389", "bytes_per_launch": 2.0 * 265523566.4 * 1024 + 53815628.9 * 1024}
 # MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz issue 39.3e12 32-bit integer
 # VALU operations per second (bitwise AND and popcount are single-issue ops).
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
