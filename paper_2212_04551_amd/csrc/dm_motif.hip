@@ -71,6 +71,16 @@ constexpr int kLeafLds = 800;
 // Membership filter over the LDS copy: one bit per (vertex mod 8192); most
 // neighbours of an x are not in the list and are rejected without a search.
 constexpr int kFilterWords = 256;
+// A list longer than kLeafLds stays in global memory; the LDS space of the
+// copy then holds a second, larger filter (one bit per vertex mod 16384), and
+// a lookup searches global memory only when both filters hold the vertex.
+constexpr int kBigFilterWords = 512;
+static_assert(kBigFilterWords * 4 <= kLeafLds * 4, "big filter lives in the list copy's LDS space");
+__device__ __forceinline__ int filt_index(int y, bool big) {
+  // the small filter takes the low bits for an LDS list, a multiplicative hash
+  // (top 13 bits) alongside the big filter
+  return big ? static_cast<int>((static_cast<uint32_t>(y) * 0x9E3779B1u) >> 19) : (y & (kFilterWords * 32 - 1));
+}
 
 struct MotifLds {
   unsigned long long* cnt;  // [ncls] class counters of the current graph
@@ -257,6 +267,7 @@ __device__ __forceinline__ int leaf_level(const MotifArgs& A, const MotifLds& L,
   // it fits; else it stays in this wave's global region
   const bool direct = s >= 2 && L.lflag[0] != 0;
   const bool in_lds = direct || ns <= kLeafLds;
+  unsigned* bigf = reinterpret_cast<unsigned*>(L.ev);
   if (in_lds) {
     const int32_t* Gv = MW.vert + A.level_off[s];
     const uint8_t* Gm = MW.mask + A.level_off[s];
@@ -269,7 +280,18 @@ __device__ __forceinline__ int leaf_level(const MotifArgs& A, const MotifLds& L,
         L.ev[i] = y;
         L.em[i] = Gm[i];
       }
-      atomicOr(&L.filt[(y >> 5) & (kFilterWords - 1)], 1u << (y & 31));
+      const int f = filt_index(y, false);
+      atomicOr(&L.filt[f >> 5], 1u << (f & 31));
+    }
+  } else {
+    for (int i = lane; i < kBigFilterWords; i += kWave) bigf[i] = 0u;
+    wave_sync();
+    const int32_t* Gv = MW.vert + A.level_off[s];
+    for (int i = lane; i < ns; i += kWave) {
+      const int y = Gv[i];
+      atomicOr(&bigf[(y >> 5) & (kBigFilterWords - 1)], 1u << (y & 31));
+      const int f = filt_index(y, true);
+      atomicOr(&L.filt[f >> 5], 1u << (f & 31));
     }
   }
   const int32_t* Ev = in_lds ? L.ev : MW.vert + A.level_off[s];
@@ -323,7 +345,9 @@ __device__ __forceinline__ int leaf_level(const MotifArgs& A, const MotifLds& L,
     // key of neighbour w of the x at slice lane o (-1: no leaf)
     auto classify = [&](int w, int o) -> int {
       int key = -1;
-      const bool maybe = !in_lds || ((L.filt[(w >> 5) & (kFilterWords - 1)] >> (w & 31)) & 1u);
+      const int f = filt_index(w, !in_lds);
+      bool maybe = (L.filt[f >> 5] >> (f & 31)) & 1u;
+      if (!in_lds) maybe = maybe && ((bigf[(w >> 5) & (kBigFilterWords - 1)] >> (w & 31)) & 1u);
       if (w > v0) {
         const int jj = maybe ? lower_bound_g(Ev, ns, w) : ns;
         if (jj < ns && Ev[jj] == w) {
@@ -384,9 +408,11 @@ __device__ __forceinline__ int leaf_level(const MotifArgs& A, const MotifLds& L,
     }
   }
   wave_sync();
-  // ---- clear the filter words this list set
+  // ---- clear the filter words this list set (all of them for a global list)
   if (in_lds)
-    for (int i = lane; i < ns; i += kWave) L.filt[(Ev[i] >> 5) & (kFilterWords - 1)] = 0u;
+    for (int i = lane; i < ns; i += kWave) L.filt[filt_index(Ev[i], false) >> 5] = 0u;
+  else
+    for (int i = lane; i < kFilterWords; i += kWave) L.filt[i] = 0u;
   // ---- one dictionary lookup per non-empty bin
   const int code_tr = L.code[s];
   const int fx = s >= 2 ? off_of(s) : 0;  // v_1's field is implied

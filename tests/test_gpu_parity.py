@@ -120,6 +120,44 @@ def test_motif_complete_bipartite():
     assert np.array_equal(motifs(g, 4), exp)
 
 
+def test_motif_long_leaf_lists():
+    """Leaf-level lists longer than the LDS copy (800 entries) stay in global
+    memory behind two LDS membership filters.  K_{820,860}: at k=3 every list
+    is one side (820 entries, all neighbours of an entry are non-members); at
+    k=4 a list holds both sides (about 1680 entries, the neighbours of an
+    entry are members).  Closed forms: paths of 3 = a C(b,2) + b C(a,2);
+    4-cycles C(a,2) C(b,2), 3-stars a C(b,3) + b C(a,3)."""
+    a, b = 820, 860
+    g = gg.complete_bipartite(a, b)
+    p3 = int(np.nonzero(O.motif_brute(gg.path(3), 3))[0][0])
+    exp3 = np.zeros(2, np.uint64)
+    exp3[p3] = a * math.comb(b, 2) + b * math.comb(a, 2)
+    assert np.array_equal(motifs(g, 3), exp3)
+    c4 = int(np.nonzero(O.motif_brute(gg.cycle(4), 4))[0][0])
+    s3 = int(np.nonzero(O.motif_brute(gg.star(3), 4))[0][0])
+    exp4 = np.zeros(6, np.uint64)
+    exp4[c4] = math.comb(a, 2) * math.comb(b, 2)
+    exp4[s3] = a * math.comb(b, 3) + b * math.comb(a, 3)
+    assert np.array_equal(motifs(g, 4), exp4)
+
+
+def test_motif_hub_lists_match_oracle():
+    """A sparse graph with two adjacent hubs of degree 850: the lists of
+    traversals through a hub exceed the LDS copy, and most neighbours looked
+    up in them are absent (filter rejections and false positives)."""
+    rng = np.random.default_rng(11)
+    base = gg.erdos_renyi(3000, 9000, 3)
+    src = np.repeat(np.arange(base.n), np.diff(base.row_ptr))
+    edges = set((int(x), int(y)) for x, y in zip(src, base.col) if x < y)
+    for hub in (3000, 3001):
+        for v in rng.choice(3000, 850, replace=False):
+            edges.add((int(v), hub))
+    edges.add((3000, 3001))
+    g = gg.from_edges(3002, sorted(edges))
+    for k in (3, 4):
+        assert np.array_equal(motifs(g, k), O.motif_count(g, k, threads=8)), k
+
+
 # ------------------------------------------------------------------ exhaustive tiny graphs
 
 def _all_graphs(n):
