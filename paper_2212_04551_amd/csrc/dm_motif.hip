@@ -72,10 +72,14 @@ constexpr int kLeafLds = 800;
 // neighbours of an x are not in the list and are rejected without a search.
 constexpr int kFilterWords = 256;
 // A list longer than kLeafLds stays in global memory; the LDS space of the
-// copy then holds a second, larger filter (one bit per vertex mod 16384), and
-// a lookup searches global memory only when both filters hold the vertex.
-constexpr int kBigFilterWords = 512;
-static_assert(kBigFilterWords * 4 <= kLeafLds * 4, "big filter lives in the list copy's LDS space");
+// copy then holds a second filter (one bit per vertex mod 8192, next to the
+// hashed small one) and fences: every fstride-th entry of the list.  A lookup
+// that passes both filters binary-searches the fences in LDS and then reads
+// the one window of at most kWindow entries it selects, all loads at once.
+constexpr int kBigFilterWords = 256;
+constexpr int kFenceMax = kLeafLds - kBigFilterWords;
+constexpr int kWindow = 8;
+static_assert(kFenceMax > 0, "big filter and fences share the list copy's LDS space");
 __device__ __forceinline__ int filt_index(int y, bool big) {
   // the small filter takes the low bits for an LDS list, a multiplicative hash
   // (top 13 bits) alongside the big filter
@@ -268,6 +272,9 @@ __device__ __forceinline__ int leaf_level(const MotifArgs& A, const MotifLds& L,
   const bool direct = s >= 2 && L.lflag[0] != 0;
   const bool in_lds = direct || ns <= kLeafLds;
   unsigned* bigf = reinterpret_cast<unsigned*>(L.ev);
+  int* fence = L.ev + kBigFilterWords;
+  const int fstride = (ns + kFenceMax - 1) / kFenceMax;  // entries per fence (global list)
+  const int nfence = fstride > 0 ? (ns + fstride - 1) / fstride : 0;
   if (in_lds) {
     const int32_t* Gv = MW.vert + A.level_off[s];
     const uint8_t* Gm = MW.mask + A.level_off[s];
@@ -292,10 +299,39 @@ __device__ __forceinline__ int leaf_level(const MotifArgs& A, const MotifLds& L,
       atomicOr(&bigf[(y >> 5) & (kBigFilterWords - 1)], 1u << (y & 31));
       const int f = filt_index(y, true);
       atomicOr(&L.filt[f >> 5], 1u << (f & 31));
+      if (i % fstride == 0) fence[i / fstride] = y;
     }
   }
-  const int32_t* Ev = in_lds ? L.ev : MW.vert + A.level_off[s];
-  const uint8_t* Em = in_lds ? L.em : MW.mask + A.level_off[s];
+  // list reads branch on where the list lives (uniform), so LDS reads stay
+  // LDS instructions instead of generic ones
+  const int32_t* Gv = MW.vert + A.level_off[s];
+  const uint8_t* Gm = MW.mask + A.level_off[s];
+  auto ev_at = [&](int j) -> int { return in_lds ? L.ev[j] : Gv[j]; };
+  auto em_at = [&](int j) -> unsigned { return in_lds ? L.em[j] : Gm[j]; };
+  // position of w in the list, or -1
+  auto ev_find = [&](int w) -> int {
+    if (in_lds) {
+      const int j = lower_bound_g(L.ev, ns, w);
+      return j < ns && L.ev[j] == w ? j : -1;
+    }
+    int lo = 0, hi = nfence;  // first fence above w
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (fence[mid] <= w) lo = mid + 1; else hi = mid;
+    }
+    if (lo == 0) return -1;
+    const int b = (lo - 1) * fstride;
+    const int n = ns - b < fstride ? ns - b : fstride;
+    if (fstride <= kWindow) {
+      int pos = -1;
+#pragma unroll
+      for (int q = 0; q < kWindow; ++q)
+        if (q < n && Gv[b + q] == w) pos = b + q;
+      return pos;
+    }
+    const int j = b + lower_bound_g(Gv + b, n, w);
+    return j < b + n && Gv[j] == w ? j : -1;
+  };
   const int nm = 1 << s;
   const unsigned low = static_cast<unsigned>(nm - 1);
   const int v0 = L.tr[0];
@@ -307,8 +343,8 @@ __device__ __forceinline__ int leaf_level(const MotifArgs& A, const MotifLds& L,
     // ---- slice: canonical entries and a prefix sum of their degrees
     const int j = c + lane;
     const bool in = j < hi;
-    const int x = in ? Ev[j] : 0;
-    const unsigned m = in ? Em[j] : 0u;
+    const int x = in ? ev_at(j) : 0;
+    const unsigned m = in ? em_at(j) : 0u;
     const bool ok = in && canonical(L, s, x, m);
     const int64_t xb = ok ? A.rp[x] : 0;
     const int64_t dx = ok ? A.rp[x + 1] - xb : 0;
@@ -349,9 +385,10 @@ __device__ __forceinline__ int leaf_level(const MotifArgs& A, const MotifLds& L,
       bool maybe = (L.filt[f >> 5] >> (f & 31)) & 1u;
       if (!in_lds) maybe = maybe && ((bigf[(w >> 5) & (kBigFilterWords - 1)] >> (w & 31)) & 1u);
       if (w > v0) {
-        const int jj = maybe ? lower_bound_g(Ev, ns, w) : ns;
-        if (jj < ns && Ev[jj] == w) {
-          if (jj > c + o && canonical(L, s, w, Em[jj])) key = L.sl_mask[o] * kBins + static_cast<int>(Em[jj] & low);
+        const int jj = maybe ? ev_find(w) : -1;
+        if (jj >= 0) {
+          const unsigned mj = em_at(jj);
+          if (jj > c + o && canonical(L, s, w, mj)) key = L.sl_mask[o] * kBins + static_cast<int>(mj & low);
         } else if (!in_tr(L, s, w)) {
           key = kBins * kBins + L.sl_mask[o];
         }
@@ -396,8 +433,8 @@ __device__ __forceinline__ int leaf_level(const MotifArgs& A, const MotifLds& L,
   // ---- canonical entries per mask over [lo, hi) and [hi, |E|)
   for (int c = lo; c < ns; c += kWave) {
     const int j = c + lane;
-    const bool ok = j < ns && canonical(L, s, Ev[j], Em[j]);
-    const int key = ok ? static_cast<int>(Em[j] & low) + (j >= hi ? kBins : 0) : -1;
+    const bool ok = j < ns && canonical(L, s, ev_at(j), em_at(j));
+    const int key = ok ? static_cast<int>(em_at(j) & low) + (j >= hi ? kBins : 0) : -1;
     uint64_t act = ballot(ok);
     while (act) {
       const int l = __ffsll(static_cast<long long>(act)) - 1;
@@ -410,7 +447,7 @@ __device__ __forceinline__ int leaf_level(const MotifArgs& A, const MotifLds& L,
   wave_sync();
   // ---- clear the filter words this list set (all of them for a global list)
   if (in_lds)
-    for (int i = lane; i < ns; i += kWave) L.filt[filt_index(Ev[i], false) >> 5] = 0u;
+    for (int i = lane; i < ns; i += kWave) L.filt[filt_index(L.ev[i], false) >> 5] = 0u;
   else
     for (int i = lane; i < kFilterWords; i += kWave) L.filt[i] = 0u;
   // ---- one dictionary lookup per non-empty bin
