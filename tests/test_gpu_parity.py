@@ -273,6 +273,26 @@ SCHED = [
 ]
 
 
+def test_queue_heads_small_and_ragged_queues():
+    """The root queue is dealt in blocks of `chunk` entries to 8 heads: queues
+    shorter than the head count, block counts that do not divide evenly, a
+    last block shorter than `chunk`, and one block larger than the queue all
+    run every root exactly once (root subsets against the oracle's per-root
+    sums, and full launches)."""
+    g = gg.chung_lu(3000, 30000, 2.1, 400.0, 9)[0]  # 80% of roots have a triangle
+    h = dm.load_graph(g)
+    k = 3
+    tot, leaves, _, _ = O.clique_count(g, k, per_root=True, threads=8)
+    rng = np.random.default_rng(5)
+    for nroots in (1, 3, 8, 9, 17, 1001):
+        roots = np.sort(rng.choice(g.n, nroots, replace=False)).astype(np.int32)
+        want = int(leaves[roots].astype(np.uint64).sum())
+        for chunk in (1, 2, 3, 7, 64, 4096):
+            assert dm.count_cliques(h, k, roots=roots, chunk=chunk) == want, (nroots, chunk)
+    for chunk in (1, 5, 375, 376, 377, 4096):
+        assert dm.count_cliques(h, k, chunk=chunk) == tot, chunk
+
+
 def test_schedule_invariance_cliques():
     g = gg.chung_lu(20000, 200000, 2.1, 1500.0, 3)[0]
     h = dm.load_graph(g)
