@@ -79,6 +79,10 @@ constexpr int kFilterWords = 256;
 constexpr int kBigFilterWords = 256;
 constexpr int kFenceMax = kLeafLds - kBigFilterWords;
 constexpr int kWindow = 8;
+// An LDS list is indexed by value: entry values above v0 are cut into
+// kBuckets ranges of 2^shift ids, and bk[b] is the first index of range b, so
+// a lookup searches only the entries of its own range.
+constexpr int kBuckets = 256;
 static_assert(kFenceMax > 0, "big filter and fences share the list copy's LDS space");
 __device__ __forceinline__ int filt_index(int y, bool big) {
   // the small filter takes the low bits for an LDS list, a multiplicative hash
@@ -105,6 +109,7 @@ struct MotifLds {
   unsigned* filt;           // [kFilterWords] membership filter of the LDS copy (zero between calls)
   int* lflag;               // [1] the (k-2)-level list was written straight into ev / em
   int* mark;                // [kWave] slice lane whose degree range starts at each item of a batch
+  uint16_t* bk;             // [kBuckets + 1] leaf level: first LDS-list index of each value range
 };
 
 __device__ __forceinline__ int off_of(int i) { return i * (i - 1) / 2 - 1; }  // bitmap field of v_i, i >= 2
@@ -135,6 +140,7 @@ __device__ MotifLds carve(unsigned char* smem, int ncls) {
   L.filt = reinterpret_cast<unsigned*>(take(kFilterWords * 4));
   L.lflag = reinterpret_cast<int*>(take(16));
   L.mark = reinterpret_cast<int*>(take(kWave * 4));
+  L.bk = reinterpret_cast<uint16_t*>(take((kBuckets + 1) * 2));
   return L;
 }
 
@@ -271,6 +277,7 @@ __device__ __forceinline__ int leaf_level(const MotifArgs& A, const MotifLds& L,
   // it fits; else it stays in this wave's global region
   const bool direct = s >= 2 && L.lflag[0] != 0;
   const bool in_lds = direct || ns <= kLeafLds;
+  int bbase = 0, bmax = -1, bshift = 0;  // value index of an LDS list
   unsigned* bigf = reinterpret_cast<unsigned*>(L.ev);
   int* fence = L.ev + kBigFilterWords;
   const int fstride = (ns + kFenceMax - 1) / kFenceMax;  // entries per fence (global list)
@@ -290,6 +297,18 @@ __device__ __forceinline__ int leaf_level(const MotifArgs& A, const MotifLds& L,
       const int f = filt_index(y, false);
       atomicOr(&L.filt[f >> 5], 1u << (f & 31));
     }
+    wave_sync();
+    // value index of the LDS copy (every entry is above v0)
+    bbase = L.tr[0] + 1;
+    bmax = ns > 0 ? L.ev[ns - 1] : bbase - 1;
+    while (((bmax - bbase) >> bshift) >= kBuckets) ++bshift;
+    for (int i = lane; i < ns; i += kWave) {
+      const int b = (L.ev[i] - bbase) >> bshift;
+      const int bp = i ? ((L.ev[i - 1] - bbase) >> bshift) : -1;
+      for (int q = bp + 1; q <= b; ++q) L.bk[q] = static_cast<uint16_t>(i);
+    }
+    const int blast = ns > 0 ? ((bmax - bbase) >> bshift) : -1;
+    for (int q = blast + 1 + lane; q <= kBuckets; q += kWave) L.bk[q] = static_cast<uint16_t>(ns);
   } else {
     for (int i = lane; i < kBigFilterWords; i += kWave) bigf[i] = 0u;
     wave_sync();
@@ -311,8 +330,11 @@ __device__ __forceinline__ int leaf_level(const MotifArgs& A, const MotifLds& L,
   // position of w in the list, or -1
   auto ev_find = [&](int w) -> int {
     if (in_lds) {
-      const int j = lower_bound_g(L.ev, ns, w);
-      return j < ns && L.ev[j] == w ? j : -1;
+      if (w > bmax || w < bbase) return -1;
+      const int b = (w - bbase) >> bshift;
+      const int lo = L.bk[b], hi = L.bk[b + 1];
+      const int j = lo + lower_bound_g(L.ev + lo, hi - lo, w);
+      return j < hi && L.ev[j] == w ? j : -1;
     }
     int lo = 0, hi = nfence;  // first fence above w
     while (lo < hi) {
@@ -656,6 +678,7 @@ size_t motif_lds_bytes(int k, int ncls) {
   off += a16((kWave + 1) * 8) + a16(kWave * 8) + a16(kWave * 4);
   off += 2 * a16(kSuf * 4) + a16(kSuf * kSuf * 4) + 3 * a16(kSuf * 4);
   off += a16(kLeafLds * 4) + a16(kLeafLds) + a16(kFilterWords * 4) + 16 + a16(kWave * 4);
+  off += a16((kBuckets + 1) * 2);
   return off;
 }
 
