@@ -277,7 +277,22 @@ __device__ __forceinline__ int leaf_level(const MotifArgs& A, const MotifLds& L,
   // it fits; else it stays in this wave's global region
   const bool direct = s >= 2 && L.lflag[0] != 0;
   const bool in_lds = direct || ns <= kLeafLds;
-  int bbase = 0, bmax = -1, bshift = 0;  // value index of an LDS list
+  // value index (bk) of a sorted LDS array a[0..n) whose entries lie in
+  // (v0, vmax]: the LDS copy of the list, or the fences of a global one
+  int bbase = 0, bmax = -1, bshift = 0;
+  auto build_index = [&](const int* a, int n, int vmax) {
+    bbase = L.tr[0] + 1;
+    bmax = vmax;
+    bshift = 0;
+    while (((bmax - bbase) >> bshift) >= kBuckets) ++bshift;
+    for (int i = lane; i < n; i += kWave) {
+      const int b = (a[i] - bbase) >> bshift;
+      const int bp = i ? ((a[i - 1] - bbase) >> bshift) : -1;
+      for (int q = bp + 1; q <= b; ++q) L.bk[q] = static_cast<uint16_t>(i);
+    }
+    const int blast = n > 0 ? ((a[n - 1] - bbase) >> bshift) : -1;
+    for (int q = blast + 1 + lane; q <= kBuckets; q += kWave) L.bk[q] = static_cast<uint16_t>(n);
+  };
   unsigned* bigf = reinterpret_cast<unsigned*>(L.ev);
   int* fence = L.ev + kBigFilterWords;
   const int fstride = (ns + kFenceMax - 1) / kFenceMax;  // entries per fence (global list)
@@ -298,17 +313,7 @@ __device__ __forceinline__ int leaf_level(const MotifArgs& A, const MotifLds& L,
       atomicOr(&L.filt[f >> 5], 1u << (f & 31));
     }
     wave_sync();
-    // value index of the LDS copy (every entry is above v0)
-    bbase = L.tr[0] + 1;
-    bmax = ns > 0 ? L.ev[ns - 1] : bbase - 1;
-    while (((bmax - bbase) >> bshift) >= kBuckets) ++bshift;
-    for (int i = lane; i < ns; i += kWave) {
-      const int b = (L.ev[i] - bbase) >> bshift;
-      const int bp = i ? ((L.ev[i - 1] - bbase) >> bshift) : -1;
-      for (int q = bp + 1; q <= b; ++q) L.bk[q] = static_cast<uint16_t>(i);
-    }
-    const int blast = ns > 0 ? ((bmax - bbase) >> bshift) : -1;
-    for (int q = blast + 1 + lane; q <= kBuckets; q += kWave) L.bk[q] = static_cast<uint16_t>(ns);
+    build_index(L.ev, ns, ns > 0 ? L.ev[ns - 1] : L.tr[0]);
   } else {
     for (int i = lane; i < kBigFilterWords; i += kWave) bigf[i] = 0u;
     wave_sync();
@@ -320,6 +325,8 @@ __device__ __forceinline__ int leaf_level(const MotifArgs& A, const MotifLds& L,
       atomicOr(&L.filt[f >> 5], 1u << (f & 31));
       if (i % fstride == 0) fence[i / fstride] = y;
     }
+    wave_sync();
+    build_index(fence, nfence, Gv[ns - 1]);
   }
   // list reads branch on where the list lives (uniform), so LDS reads stay
   // LDS instructions instead of generic ones
@@ -336,13 +343,13 @@ __device__ __forceinline__ int leaf_level(const MotifArgs& A, const MotifLds& L,
       const int j = lo + lower_bound_g(L.ev + lo, hi - lo, w);
       return j < hi && L.ev[j] == w ? j : -1;
     }
-    int lo = 0, hi = nfence;  // first fence above w
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (fence[mid] <= w) lo = mid + 1; else hi = mid;
-    }
-    if (lo == 0) return -1;
-    const int b = (lo - 1) * fstride;
+    if (w > bmax || w < bbase) return -1;
+    // fences <= w: those of earlier ranges and a search inside w's own range
+    const int r = (w - bbase) >> bshift;
+    const int flo = L.bk[r], fhi = L.bk[r + 1];
+    const int nf = flo + lower_bound_g(fence + flo, fhi - flo, w + 1);
+    if (nf == 0) return -1;
+    const int b = (nf - 1) * fstride;
     const int n = ns - b < fstride ? ns - b : fstride;
     if (fstride <= kWindow) {
       int pos = -1;
