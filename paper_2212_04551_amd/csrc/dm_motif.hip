@@ -437,17 +437,21 @@ __device__ __forceinline__ int leaf_level(const MotifArgs& A, const MotifLds& L,
         act &= ~same;
       }
     };
-    // two items per lane and pass, both adjacency reads in flight together
-    for (int64_t f0 = 0; f0 < total; f0 += 2 * kWave) {
+    // three items per lane and pass, their adjacency reads in flight together
+    for (int64_t f0 = 0; f0 < total; f0 += 3 * kWave) {
       const int oa = owner_of(f0);
       const int ob = owner_of(f0 + kWave);
-      const int64_t fa = f0 + lane, fb = f0 + kWave + lane;
+      const int oc = owner_of(f0 + 2 * kWave);
+      const int64_t fa = f0 + lane, fb = f0 + kWave + lane, fc = f0 + 2 * kWave + lane;
       const int wa = fa < total ? A.col[L.sl_base[oa] + (fa - L.sl_start[oa])] : -1;
       const int wb = fb < total ? A.col[L.sl_base[ob] + (fb - L.sl_start[ob])] : -1;
+      const int wc = fc < total ? A.col[L.sl_base[oc] + (fc - L.sl_start[oc])] : -1;
       const int ka = fa < total ? classify(wa, oa) : -1;
       const int kb = fb < total ? classify(wb, ob) : -1;
+      const int kc = fc < total ? classify(wc, oc) : -1;
       aggregate(ka);
       aggregate(kb);
+      aggregate(kc);
     }
     wave_sync();
     // ---- donation of the untried x range
