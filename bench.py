@@ -40,7 +40,7 @@ def kernel_source_sha(kernel: str = "dm_clique.hip") -> str:
 
 # HBM bytes per launch of the motif kernel on the sampled 5-motif workload
 # (same scaling), valid only for the kernel source they were taken on.
-TRAFFIC_MOTIF = {"source_sha": "1a8d3452e1a82ec7", "bytes_per_launch": 2.0 * 234161369.6 * 1024 + 54530510.6 * 1024}
+TRAFFIC_MOTIF = {"source_sha": "98e6d219ceea12ac", "bytes_per_launch": 2.0 * 233289032.6 * 1024 + 54953631.5 * 1024}
 # MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz issue 39.3e12 32-bit integer
 # VALU operations per second (bitwise AND and popcount are single-issue ops).
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
