@@ -80,8 +80,10 @@ typedef struct {
     uint32_t size;
     uint32_t sched;          /* DM_SCHED_* | DM_RECORD_ROOTS | DM_NO_DONATION */
     void* stream;            /* hipStream_t or NULL */
-    uint32_t chunk;          /* plain queue: roots per grab (0 = 1); learned queue:
-                                chunks of equal predicted cost per wave (0 = 8) */
+    uint32_t chunk;          /* plain queue: roots per grab (0 = 1; the queue's blocks of
+                                `chunk` roots are dealt round-robin to 8 counters, so the roots
+                                of one launch leave in about, not exactly, rank order);
+                                learned queue: chunks of equal predicted cost per wave (0 = 8) */
     float rebalance;         /* donate once at least this fraction of waves is idle; 0 = default */
     uint32_t waves_per_cu;   /* resident waves per CU for the persistent grid; 0 = occupancy maximum */
     const float* mlp;        /* DM_SCHED_LEARNED: device pointer to DM_MLP_NPARAMS floats */
