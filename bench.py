@@ -27,7 +27,7 @@ KS = (3, 4, 5, 6, 7, 8)
 # HBM bytes of the k=8 clique_kernel launch from rocprofv3 (2.0 x FETCH_SIZE +
 # 1.0 x WRITE_SIZE, factors from a copy kernel of known size), valid only for
 # the kernel source they were taken on.
-TRAFFIC = {"source_sha": "eab535496a8037fd", "bytes_per_launch": 2.0 * 852669.0 * 1024 + 456354.5 * 1024}
+TRAFFIC = {"source_sha": "d75f273089e93618", "bytes_per_launch": 2.0 * 771431.9 * 1024 + 410721.7 * 1024}
 
 
 def kernel_source_sha(kernel: str = "dm_clique.hip") -> str:

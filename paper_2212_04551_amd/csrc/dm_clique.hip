@@ -255,6 +255,7 @@ __device__ __forceinline__ uint64_t lane_solve(const uint64_t (&C)[NW], const ui
   // the next (up to) 64 untaken pair tasks are decoded together, one per lane
   // (packed i << 8 | j in pend), and handed to free lanes by a lane shuffle
   int gen_base = 0, gen_n = 0;  // decoded tasks: gen_base .. gen_base + gen_n - 1
+  int nrefill = 0;
   int pend = 0;
   for (;;) {
     const bool want = !done && d < 0;
@@ -263,7 +264,8 @@ __device__ __forceinline__ uint64_t lane_solve(const uint64_t (&C)[NW], const ui
     if (wb && (nw >= kRefillMin || ballot(d >= 0) == 0)) {
       // idle waves elsewhere: hand over the first members whose pair tasks
       // make up about the upper half of the untaken ones
-      if (J.S->donate && total - tbase >= kJobDonateMin && sched_want_donation_tail(*J.S)) {
+      // (two relaxed loads past the L2 and a wait: checked on every 8th refill)
+      if (J.S->donate && (++nrefill & 7) == 0 && total - tbase >= kJobDonateMin && sched_want_donation_tail(*J.S)) {
         const int tmid = tbase + (total - tbase) / 2;
         int ic = 0;  // last member whose range starts before tmid
 #pragma unroll
