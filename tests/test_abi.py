@@ -105,3 +105,15 @@ def test_argument_errors_without_gpu():
     assert L.dm_load_csr(-1, None, None, 0, None, ctypes.byref(h)) == dm.DM_E_ARG
     assert L.dm_load_csr(3, None, None, 0, None, None) == dm.DM_E_ARG
     assert L.dm_strerror(dm.DM_E_OVERFLOW) == b"uint64 count overflow"
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU; asked for more it exits with status 2 and a
+    message, before touching a device."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr
+    assert r.stdout == ""
