@@ -52,9 +52,12 @@ def _load():
     L.or_clique_brute.argtypes = [i32, vp, vp, ctypes.c_int, vp, vp]
     L.or_motif_brute.restype = ctypes.c_int
     L.or_motif_brute.argtypes = [i32, vp, vp, ctypes.c_int, vp, vp]
-    for f in (L.or_clique_roots, L.or_motif_roots):
-        f.restype = ctypes.c_int
-        f.argtypes = [i32, vp, vp, ctypes.c_int, vp, i64, ctypes.c_int, vp, vp, vp, vp]
+    L.or_clique_roots.restype = ctypes.c_int
+    L.or_clique_roots.argtypes = [i32, vp, vp, ctypes.c_int, vp, i64, ctypes.c_int, vp, vp, vp, vp,
+                                  ctypes.c_double, vp]
+    L.or_motif_roots.restype = ctypes.c_int
+    L.or_motif_roots.argtypes = [i32, vp, vp, ctypes.c_int, vp, i64, ctypes.c_int, vp, vp, vp, vp,
+                                 ctypes.c_double, vp, vp]
     for f in (L.or_clique_timed, L.or_motif_timed):
         f.restype = ctypes.c_uint64
         f.argtypes = [i32, vp, vp, ctypes.c_int, vp, i64, ctypes.c_int, ctypes.c_double,
@@ -168,7 +171,7 @@ def clique_count(g, k: int, roots=None, threads: int = 1, per_root: bool = False
     tot = np.zeros(1, dtype=np.uint64)
     arrs = [np.zeros(max(cnt, 1), dtype=np.uint64) for _ in range(3)] if per_root else [None] * 3
     rc = _load().or_clique_roots(g.n, rp.ctypes.data, col.ctypes.data, k, _ptr(r), nr, threads,
-                                 tot.ctypes.data, *[_ptr(a) for a in arrs])
+                                 tot.ctypes.data, *[_ptr(a) for a in arrs], 0.0, None)
     if rc < 0:
         raise ValueError("bad arguments")
     if rc == 1:
@@ -178,11 +181,29 @@ def clique_count(g, k: int, roots=None, threads: int = 1, per_root: bool = False
     return int(tot[0])
 
 
+def clique_budgeted(g, k: int, roots, threads: int, root_budget: float):
+    """Per-root clique records with a time budget per root.
+
+    Returns (done, leaves, nodes, reads) aligned with ``roots``: done[i] is
+    True when root i finished within ``root_budget`` seconds; the records of
+    the other roots are partial and must not be used."""
+    rp, col = _csr(g)
+    r, nr = _roots(roots)
+    tot = np.zeros(1, dtype=np.uint64)
+    arrs = [np.zeros(max(nr, 1), dtype=np.uint64) for _ in range(3)]
+    done = np.zeros(max(nr, 1), dtype=np.uint8)
+    rc = _load().or_clique_roots(g.n, rp.ctypes.data, col.ctypes.data, k, _ptr(r), nr, threads,
+                                 tot.ctypes.data, *[_ptr(a) for a in arrs], float(root_budget), done.ctypes.data)
+    if rc != 0:
+        raise ValueError("bad arguments or overflow")
+    return (done[:nr].astype(bool),) + tuple(a[:nr] for a in arrs)
+
+
 def motif_count(g, k: int, roots=None, threads: int = 1, per_root: bool = False):
     """Per-class connected induced k-set counts by ESU (Wernicke 2006).
 
-    With ``roots`` only sets whose minimum id is listed are counted.  With
-    ``per_root`` returns (counts, leaves, nodes, reads).
+    With ``roots`` only sets whose lowest (degree, id) vertex is listed are
+    counted.  With ``per_root`` returns (counts, leaves, nodes, reads).
     """
     rp, col = _csr(g)
     r, nr = _roots(roots)
@@ -190,7 +211,7 @@ def motif_count(g, k: int, roots=None, threads: int = 1, per_root: bool = False)
     out = np.zeros(num_classes(k), dtype=np.uint64)
     arrs = [np.zeros(max(cnt, 1), dtype=np.uint64) for _ in range(3)] if per_root else [None] * 3
     rc = _load().or_motif_roots(g.n, rp.ctypes.data, col.ctypes.data, k, _ptr(r), nr, threads,
-                                out.ctypes.data, *[_ptr(a) for a in arrs])
+                                out.ctypes.data, *[_ptr(a) for a in arrs], 0.0, None, None)
     if rc < 0:
         raise ValueError("bad arguments")
     if rc == 1:
@@ -198,6 +219,26 @@ def motif_count(g, k: int, roots=None, threads: int = 1, per_root: bool = False)
     if per_root:
         return (out,) + tuple(a[:cnt] for a in arrs)
     return out
+
+
+def motif_budgeted(g, k: int, roots, threads: int, root_budget: float):
+    """Per-root motif records with a time budget per root.
+
+    Returns (done, counts, leaves, nodes, reads): done as in clique_budgeted,
+    counts[i] the class counts of root i (nroots x ncls)."""
+    rp, col = _csr(g)
+    r, nr = _roots(roots)
+    ncls = num_classes(k)
+    out = np.zeros(ncls, dtype=np.uint64)
+    arrs = [np.zeros(max(nr, 1), dtype=np.uint64) for _ in range(3)]
+    done = np.zeros(max(nr, 1), dtype=np.uint8)
+    per = np.zeros((max(nr, 1), ncls), dtype=np.uint64)
+    rc = _load().or_motif_roots(g.n, rp.ctypes.data, col.ctypes.data, k, _ptr(r), nr, threads,
+                                out.ctypes.data, *[_ptr(a) for a in arrs], float(root_budget), done.ctypes.data,
+                                per.ctypes.data)
+    if rc != 0:
+        raise ValueError("bad arguments or overflow")
+    return (done[:nr].astype(bool), per[:nr]) + tuple(a[:nr] for a in arrs)
 
 
 # ------------------------------------------------------------------ time-bounded runs

@@ -36,7 +36,17 @@
  *   nodes(r)  = number of j-vertex traversals (1 <= j <= k-1) credited to r
  *               (j-cliques, or connected j-sets, whose root is r),
  *   reads(r)  = sum over those traversals of the degree (out-degree in rank
- *               order for cliques) of the vertex added last.
+ *               order for cliques) of the vertex added last.  For cliques the
+ *               last vertex is the highest-ranked one.  For motifs it is the
+ *               last vertex of the set's canonical order (the reading of the
+ *               canonicality filter of Section IV-E used throughout: start at
+ *               the lowest-ranked vertex, then repeatedly add the lowest-ranked
+ *               vertex adjacent to those already taken), so the figure depends
+ *               on the set only, not on the order an enumerator visits it in.
+ *
+ * Per-root time budget (for choosing heavy roots the oracle can finish):
+ * with root_budget > 0 each root may run for that many seconds; done[i] = 1
+ * marks the roots that finished, and only those enter the totals.
  */
 #define _POSIX_C_SOURCE 200809L
 #include <pthread.h>
@@ -321,6 +331,11 @@ typedef struct {
     const int64_t* outdeg;   /* neighbours of higher rank */
     /* motif */
     const class_info* ci;
+    /* optional per-root budget (seconds; 0 = none), completion flags, and
+       per-root class counts (motifs; nroots x ncls) */
+    double root_budget;
+    uint8_t* done;
+    uint64_t* root_counts;
     /* optional wall-clock deadline (CLOCK_MONOTONIC seconds; 0 = none) */
     double deadline;
     atomic_int expired;
@@ -342,12 +357,30 @@ static double now_s(void) {
     return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
 }
 
-/* true once the job's deadline has passed (checked every 4096 calls per thread) */
-static int past_deadline(job_t* J, unsigned* tick) {
-    if (J->deadline <= 0.0) return 0;
-    if (atomic_load(&J->expired)) return 1;
-    if ((++*tick & 4095u) == 0 && now_s() > J->deadline) atomic_store(&J->expired, 1);
-    return atomic_load(&J->expired);
+/* Per-thread stop state for the current root: its own budget's deadline
+   (0 = none) and whether it ran out. */
+typedef struct {
+    double deadline;
+    int out;
+} root_clock;
+
+/* true once the job's deadline or the current root's budget has passed
+   (the clock is read every 4096 calls per thread) */
+static int past_deadline(job_t* J, unsigned* tick, root_clock* rc) {
+    if (rc->out) return 1;
+    if (J->deadline <= 0.0 && rc->deadline <= 0.0) return 0;
+    if (J->deadline > 0.0 && atomic_load(&J->expired)) return 1;
+    if ((++*tick & 4095u) == 0) {
+        double t = now_s();
+        if (J->deadline > 0.0 && t > J->deadline) atomic_store(&J->expired, 1);
+        if (rc->deadline > 0.0 && t > rc->deadline) rc->out = 1;
+    }
+    return rc->out || (J->deadline > 0.0 && atomic_load(&J->expired));
+}
+
+static void root_clock_start(const job_t* J, root_clock* rc) {
+    rc->out = 0;
+    rc->deadline = J->root_budget > 0.0 ? now_s() + J->root_budget : 0.0;
 }
 
 /* ---------------------------------------------------------------- cliques */
@@ -358,6 +391,7 @@ typedef struct {
     int32_t* buf[33];   /* candidate list per depth */
     int64_t cap;
     unsigned tick;
+    root_clock rc;
 } clq_ctx;
 
 
@@ -367,7 +401,7 @@ typedef struct {
  * whose last vertex is `last`.
  */
 static void clq_expand(job_t* J, clq_ctx* C, int s, int32_t last, const int32_t* cand, int64_t nc) {
-    if (past_deadline(J, &C->tick)) return;
+    if (past_deadline(J, &C->tick, &C->rc)) return;
     add_u64(&C->nodes, 1, &C->ovf);
     add_u64(&C->reads, (uint64_t)J->outdeg[last], &C->ovf);
     if (s == J->k - 1) { add_u64(&C->leaves, (uint64_t)nc, &C->ovf); return; }
@@ -402,6 +436,7 @@ static void* clq_worker(void* arg) {
         atomic_fetch_add(&J->started, 1);
         int32_t r = J->roots[i];
         C.leaves = C.nodes = C.reads = 0;
+        root_clock_start(J, &C.rc);
         if (J->k == 1) {
             C.leaves = 1;
         } else {
@@ -413,7 +448,9 @@ static void* clq_worker(void* arg) {
         if (J->leaves) J->leaves[i] = C.leaves;
         if (J->nodes) J->nodes[i] = C.nodes;
         if (J->reads) J->reads[i] = C.reads;
-        add_u64(&total, C.leaves, &ovf);
+        if (J->done) J->done[i] = C.rc.out ? 0 : 1;
+        /* a root stopped by its own budget does not enter the total */
+        if (!C.rc.out || J->deadline > 0.0) add_u64(&total, C.leaves, &ovf);
     }
     for (int s = 0; s <= J->k && s <= 32; ++s) free(C.buf[s]);
     pthread_mutex_lock(&J->lock);
@@ -451,11 +488,15 @@ static void run_pool(job_t* J, int nthreads, void* (*fn)(void*)) {
 
 /*
  * k-cliques credited to the listed roots (all vertices when roots == NULL).
+ * leaves / nodes / reads (nullable, nroots entries) get the per-root records.
+ * With root_budget > 0 each root runs for at most that many seconds; done
+ * (nullable) marks the roots that finished, and only those are in *out_total.
  * Returns 0, or 1 when a uint64 sum overflowed, or -1 on bad arguments.
  */
 int or_clique_roots(int32_t n, const int64_t* rp, const int32_t* col, int k,
                     const int32_t* roots, int64_t nroots, int nthreads, uint64_t* out_total,
-                    uint64_t* leaves, uint64_t* nodes, uint64_t* reads) {
+                    uint64_t* leaves, uint64_t* nodes, uint64_t* reads, double root_budget,
+                    uint8_t* done) {
     if (k < 1 || k > 32 || n < 0) return -1;
     job_t* J = (job_t*)calloc(1, sizeof(job_t));
     J->g = (graph_t){ n, rp, col };
@@ -471,6 +512,8 @@ int or_clique_roots(int32_t n, const int64_t* rp, const int32_t* col, int k,
     J->nroots = nroots;
     atomic_init(&J->next, 0);
     J->leaves = leaves; J->nodes = nodes; J->reads = reads;
+    J->root_budget = root_budget;
+    J->done = done;
     J->rank = make_rank(&J->g);
     int64_t* od = (int64_t*)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
     for (int32_t v = 0; v < n; ++v)
@@ -501,20 +544,58 @@ typedef struct {
     int32_t* ext[OR_MAXK + 1];  /* extension list per depth */
     int32_t* blocked;           /* # of sub vertices adjacent to x, or in sub (n entries) */
     uint64_t leaves, nodes, reads;
-    uint64_t counts[128];
+    uint64_t counts[128];       /* per class, the current root only */
     int ovf;
+    root_clock rc;
 } esu_ctx;
 
-static void esu_leaf(esu_ctx* E) {
+/* edge bitmap (column order) of sub[0..s-1] */
+static uint32_t sub_code(const esu_ctx* E, int s) {
+    const graph_t* g = &E->J->g;
+    uint32_t c = 0;
+    for (int i = 1; i < s; ++i)
+        for (int t = 0; t < i; ++t)
+            if (has_edge(g, E->sub[t], E->sub[i])) c |= 1u << pair_bit(t, i);
+    return c;
+}
+
+/* the k-set sub[0..k-2] + w: its class from the edge bitmap; `prefix` is the
+   bitmap of sub[0..k-2] */
+static void esu_leaf(esu_ctx* E, uint32_t prefix, int32_t w) {
     const job_t* J = E->J;
     int k = J->k;
-    uint32_t c = 0;
-    for (int i = 1; i < k; ++i)
-        for (int t = 0; t < i; ++t)
-            if (has_edge(&J->g, E->sub[t], E->sub[i])) c |= 1u << pair_bit(t, i);
+    uint32_t c = prefix;
+    for (int t = 0; t < k - 1; ++t)
+        if (has_edge(&J->g, E->sub[t], w)) c |= 1u << pair_bit(t, k - 1);
     int q = J->ci->class_of_code[c];
     if (q >= 0) add_u64(&E->counts[q], 1, &E->ovf);
     add_u64(&E->leaves, 1, &E->ovf);
+}
+
+/* Last vertex of the canonical order of the connected set sub[0..s-1]: start
+   at the lowest-ranked vertex, then repeatedly take the lowest-ranked vertex
+   adjacent to one already taken. */
+static int32_t canonical_last(const esu_ctx* E, int s) {
+    const job_t* J = E->J;
+    int taken[OR_MAXK] = {0};
+    int first = 0;
+    for (int i = 1; i < s; ++i)
+        if (J->rank[E->sub[i]] < J->rank[E->sub[first]]) first = i;
+    taken[first] = 1;
+    int last = first;
+    for (int step = 1; step < s; ++step) {
+        int best = -1;
+        for (int i = 0; i < s; ++i) {
+            if (taken[i]) continue;
+            int adj = 0;
+            for (int t = 0; t < s && !adj; ++t)
+                if (taken[t] && has_edge(&J->g, E->sub[t], E->sub[i])) adj = 1;
+            if (adj && (best < 0 || J->rank[E->sub[i]] < J->rank[E->sub[best]])) best = i;
+        }
+        taken[best] = 1;
+        last = best;
+    }
+    return E->sub[last];
 }
 
 /* mark / unmark the closed neighbourhood of a vertex that joins / leaves sub */
@@ -531,10 +612,16 @@ static void esu_block(esu_ctx* E, int32_t w, int d) {
 static void esu_extend(esu_ctx* E, int s, const int32_t* ext, int64_t ne) {
     job_t* J = E->J;
     const graph_t* g = &J->g;
-    if (s == J->k) { esu_leaf(E); return; }
-    if (past_deadline(J, &E->tick)) return;
+    if (past_deadline(J, &E->tick, &E->rc)) return;
     add_u64(&E->nodes, 1, &E->ovf);
-    add_u64(&E->reads, (uint64_t)deg_of(g, E->sub[s - 1]), &E->ovf);
+    add_u64(&E->reads, (uint64_t)deg_of(g, canonical_last(E, s)), &E->ovf);
+    if (s == J->k - 1) {
+        /* every candidate completes a k-set: classify it; the extension list
+           and neighbourhood marks of a deeper level are not needed */
+        uint32_t prefix = sub_code(E, s);
+        for (int64_t i = ne - 1; i >= 0; --i) esu_leaf(E, prefix, ext[i]);
+        return;
+    }
     int32_t* nxt = E->ext[s + 1];
     /* remove candidates one at a time from the back of the list */
     for (int64_t i = ne - 1; i >= 0; --i) {
@@ -571,6 +658,8 @@ static void* esu_worker(void* arg) {
         int32_t r = J->roots[i];
         E.root = r;
         E.leaves = E.nodes = E.reads = 0;
+        memset(E.counts, 0, sizeof E.counts);
+        root_clock_start(J, &E.rc);
         E.sub[0] = r;
         if (J->k == 1) {
             add_u64(&E.counts[0], 1, &E.ovf);
@@ -586,9 +675,17 @@ static void* esu_worker(void* arg) {
         if (J->leaves) J->leaves[i] = E.leaves;
         if (J->nodes) J->nodes[i] = E.nodes;
         if (J->reads) J->reads[i] = E.reads;
+        if (J->done) J->done[i] = E.rc.out ? 0 : 1;
+        if (J->root_counts)
+            for (int q = 0; q < J->ci->ncls; ++q) J->root_counts[i * J->ci->ncls + q] = E.counts[q];
+        /* a root stopped by its own budget does not enter the totals */
+        if (!E.rc.out || J->deadline > 0.0) {
+            pthread_mutex_lock(&J->lock);
+            for (int q = 0; q < J->ci->ncls; ++q) add_u64(&J->counts[q], E.counts[q], &J->overflow);
+            pthread_mutex_unlock(&J->lock);
+        }
     }
     pthread_mutex_lock(&J->lock);
-    for (int q = 0; q < J->ci->ncls; ++q) add_u64(&J->counts[q], E.counts[q], &J->overflow);
     if (E.ovf) J->overflow = 1;
     pthread_mutex_unlock(&J->lock);
     for (int s = 0; s <= J->k; ++s) free(E.ext[s]);
@@ -598,12 +695,15 @@ static void* esu_worker(void* arg) {
 
 /*
  * Connected induced k-sets credited to the listed roots (all when roots == NULL),
- * counted per class into out_counts (ncls entries).  Returns 0, 1 on overflow,
- * -1 on bad arguments.
+ * counted per class into out_counts (ncls entries).  Per-root records as for
+ * cliques, plus root_counts (nullable, nroots x ncls) with each root's own
+ * class counts; root_budget / done as for cliques (out_counts then holds the
+ * finished roots only).  Returns 0, 1 on overflow, -1 on bad arguments.
  */
 int or_motif_roots(int32_t n, const int64_t* rp, const int32_t* col, int k,
                    const int32_t* roots, int64_t nroots, int nthreads, uint64_t* out_counts,
-                   uint64_t* leaves, uint64_t* nodes, uint64_t* reads) {
+                   uint64_t* leaves, uint64_t* nodes, uint64_t* reads, double root_budget,
+                   uint8_t* done, uint64_t* root_counts) {
     const class_info* ci = classes(k);
     if (!ci || n < 0 || k > OR_MAX_MOTIF_K) return -1;
     job_t* J = (job_t*)calloc(1, sizeof(job_t));
@@ -621,6 +721,9 @@ int or_motif_roots(int32_t n, const int64_t* rp, const int32_t* col, int k,
     J->nroots = nroots;
     atomic_init(&J->next, 0);
     J->leaves = leaves; J->nodes = nodes; J->reads = reads;
+    J->root_budget = root_budget;
+    J->done = done;
+    J->root_counts = root_counts;
     J->rank = make_rank(&J->g);
     pthread_mutex_init(&J->lock, NULL);
     run_pool(J, nthreads, esu_worker);

@@ -353,28 +353,100 @@ def test_l1_vs_l2_random(seed):
         assert tb == tc and np.array_equal(ptb, cl)
 
 
-def test_motif_tree_nodes_are_connected_sets():
+def _greedy_last(G, S, key):
+    """Last vertex of the canonical order of the connected set S: the lowest
+    vertex by `key` first, then repeatedly the lowest vertex adjacent to the
+    ones already taken (written out with networkx adjacency)."""
+    taken = [min(S, key=key)]
+    rest = set(S) - set(taken)
+    while rest:
+        nxt = min((v for v in rest if any(G.has_edge(v, t) for t in taken)), key=key)
+        taken.append(nxt)
+        rest.remove(nxt)
+    return taken[-1]
+
+
+@pytest.mark.parametrize("seed,n,m", [(5, 12, 24), (6, 13, 40), (7, 11, 18)])
+def test_motif_tree_nodes_are_connected_sets(seed, n, m):
     """nodes(r) = number of connected j-sets (j<k) whose lowest (degree, id)
-    vertex is r; leaves(r) the same for k-sets (brute force)."""
-    g = gg.erdos_renyi(12, 24, 5)
+    vertex is r; leaves(r) the same for k-sets; reads(r) = sum over those
+    j-sets of the degree of the last vertex of their canonical order (brute
+    force over every subset)."""
+    g = gg.erdos_renyi(n, m, seed)
     G = to_nx(g)
     deg = g.degrees()
     key = lambda v: (deg[v], v)
-    k = 5
-    exp_nodes = np.zeros(g.n, np.int64)
-    exp_leaves = np.zeros(g.n, np.int64)
-    for j in range(1, k + 1):
-        for S in itertools.combinations(range(g.n), j):
-            if nx.is_connected(G.subgraph(S)):
-                if j < k:
-                    exp_nodes[min(S, key=key)] += 1
-                else:
-                    exp_leaves[min(S, key=key)] += 1
-    _, leaves, nodes, reads = O.motif_count(g, k, per_root=True)
-    assert np.array_equal(nodes.astype(np.int64), exp_nodes)
-    assert np.array_equal(leaves.astype(np.int64), exp_leaves)
-    # reads: each node adds the degree of its newest vertex, so at least the root's
-    assert (reads >= 0).all()
+    for k in (3, 4, 5):
+        exp_nodes = np.zeros(g.n, np.int64)
+        exp_leaves = np.zeros(g.n, np.int64)
+        exp_reads = np.zeros(g.n, np.int64)
+        for j in range(1, k + 1):
+            for S in itertools.combinations(range(g.n), j):
+                if nx.is_connected(G.subgraph(S)):
+                    r = min(S, key=key)
+                    if j < k:
+                        exp_nodes[r] += 1
+                        exp_reads[r] += deg[_greedy_last(G, S, key)]
+                    else:
+                        exp_leaves[r] += 1
+        _, leaves, nodes, reads = O.motif_count(g, k, per_root=True)
+        assert np.array_equal(nodes.astype(np.int64), exp_nodes), k
+        assert np.array_equal(leaves.astype(np.int64), exp_leaves), k
+        assert np.array_equal(reads.astype(np.int64), exp_reads), k
+
+
+def test_motif_reads_not_the_enumeration_order():
+    """A graph where the canonical order's last vertex differs from the order
+    ESU visits the set in: the path 0-3-1-2 ... checked on every labelled
+    4-vertex graph against the brute-force definition."""
+    pairs = [(i, j) for i in range(5) for j in range(i + 1, 5)]
+    for mask in range(0, 1 << len(pairs), 7):
+        g = gg.from_edges(5, [p for b, p in enumerate(pairs) if mask >> b & 1])
+        G = to_nx(g)
+        deg = g.degrees()
+        key = lambda v: (deg[v], v)
+        k = 4
+        exp = np.zeros(g.n, np.int64)
+        for j in range(1, k):
+            for S in itertools.combinations(range(g.n), j):
+                if nx.is_connected(G.subgraph(S)):
+                    exp[min(S, key=key)] += deg[_greedy_last(G, S, key)]
+        _, _, _, reads = O.motif_count(g, k, per_root=True)
+        assert np.array_equal(reads.astype(np.int64), exp), mask
+
+
+def test_budgeted_records_equal_unbudgeted():
+    """A per-root budget that every root meets changes nothing: same per-root
+    records, every root marked done."""
+    g = gg.erdos_renyi(200, 1500, 4)
+    roots = np.arange(0, 200, 3, dtype=np.int32)
+    _, l, nd, rd = O.clique_count(g, 4, roots=roots, per_root=True, threads=2)
+    done, l2, nd2, rd2 = O.clique_budgeted(g, 4, roots, 2, 30.0)
+    assert done.all() and np.array_equal(l, l2) and np.array_equal(nd, nd2) and np.array_equal(rd, rd2)
+    c, ml, mn, mr = O.motif_count(g, 4, roots=roots, per_root=True, threads=2)
+    done, per, ml2, mn2, mr2 = O.motif_budgeted(g, 4, roots, 2, 30.0)
+    assert done.all() and np.array_equal(ml, ml2) and np.array_equal(mn, mn2) and np.array_equal(mr, mr2)
+    assert np.array_equal(per.sum(axis=0), c) and np.array_equal(per.sum(axis=1), ml)
+
+
+def test_budget_stops_a_heavy_root():
+    """Roots that cannot finish in 0.2 s (K_60 at k=12: C(59, 11) ~ 1.3e12
+    cliques from vertex 0; K_200 at k=6: C(199, 5) ~ 2.5e9 sets from vertex 0)
+    are reported not done and left out of the totals; a light root beside them
+    (an end of a path on 8 vertices, root of one 6-vertex path) finishes."""
+    import time
+    g = gg.disjoint_union([gg.complete(60), gg.path(5)])[0]
+    roots = np.array([0, 60], dtype=np.int32)
+    t = time.perf_counter()
+    done, leaves, _, _ = O.clique_budgeted(g, 12, roots, 2, 0.2)
+    assert time.perf_counter() - t < 10
+    assert list(done) == [False, True] and leaves[1] == 0
+    g = gg.disjoint_union([gg.complete(200), gg.path(8)])[0]
+    roots = np.array([0, 200], dtype=np.int32)
+    t = time.perf_counter()
+    done, per, ml, _, _ = O.motif_budgeted(g, 6, roots, 2, 0.2)
+    assert time.perf_counter() - t < 10
+    assert list(done) == [False, True] and per[1].sum() == ml[1] == 1
 
 
 @pytest.mark.parametrize("k", [3, 4, 5])
