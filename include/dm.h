@@ -58,7 +58,9 @@ typedef enum {
 enum {
     DM_CSR_HOST = 0,    /* row_ptr / col are host pointers */
     DM_CSR_DEVICE = 1,  /* row_ptr / col are device pointers (copied device-to-device) */
-    DM_CSR_TRUSTED = 2  /* skip validation (caller guarantees the conventions above) */
+    DM_CSR_TRUSTED = 2, /* skip validation (caller guarantees the conventions above) */
+    DM_CSR_ORIENT = 4   /* also build the (degree, id) orientation used by clique counting
+                           now, instead of at the first clique call */
 };
 
 /* dm_options.sched bits */
@@ -67,7 +69,14 @@ enum {
     DM_SCHED_LEARNED = 1,  /* order and chunk roots by the MLP's predicted subtree size */
     DM_SCHED_AUTOTUNE = 2, /* pick chunk / rebalance / waves-per-CU from the tuner cache */
     DM_RECORD_ROOTS = 4,   /* write per-root {tree nodes, leaves, adjacency reads} */
-    DM_NO_DONATION = 8     /* disable in-kernel work donation (ablation: static schedule) */
+    DM_NO_DONATION = 8,    /* disable in-kernel work donation (ablation: static schedule) */
+    DM_SCHED_COST = 16,    /* order and chunk roots like DM_SCHED_LEARNED, by the caller's
+                              per-vertex costs `root_cost` instead of the MLP's predictions
+                              (e.g. recorded tree sizes: the ordering a perfect predictor gives) */
+    DM_IMPL_DFS = 32       /* ablation (Section V-A, the DFS implementation of Table III): one
+                              lane per traversal instead of one wave, each lane taking roots from
+                              a global counter; same counts.  Plain root order over every root
+                              only (with DM_NO_DONATION or nothing else), clique k <= 16. */
 };
 
 enum { DM_OP_CLIQUE = 0, DM_OP_MOTIF = 1 };
@@ -97,6 +106,12 @@ typedef struct {
                                 {busy ticks, idle ticks, tree nodes, tasks taken} */
     uint32_t wave_stats_len; /* number of waves wave_stats can hold */
     uint64_t counter_bias;   /* test hook: global accumulators start at this value (0 normally) */
+    uint32_t wait_limit_us;  /* longest time (microseconds) an idle wave of the persistent grid
+                                waits for donated work before it gives up (0 = 600 s).  A wave that gives up
+                                makes the call fail with DM_E_HIP (every wave still exits
+                                normally), so a scheduler fault cannot keep the GPU busy. */
+    const float* root_cost;  /* DM_SCHED_COST: device pointer, n floats indexed by vertex id,
+                                log(1 + expected tree nodes) of each root (the MLP's scale) */
 } dm_options;
 
 /*

@@ -267,6 +267,7 @@ struct dm_graph {
   Buf urp, ucol;
   // workspace reused across calls
   Buf ctrl, out, rows, ext_vert, ext_mask, newbuf, qroot, qstat, qlo, qhi, rgraph;
+  Buf dfs_stack, dfs_mask;  // per-lane stacks of the one-lane-per-traversal ablation
   // learned ordering: features (cached), predictions, LPT order, chunk starts
   // and the order in rank space; the queue is reused while the parameter
   // fingerprint, grid and chunks per wave stay the same
@@ -310,12 +311,14 @@ static bool host_validate(int32_t n, const int64_t* rp, const int32_t* col, std:
   return true;
 }
 
+static dm_status ensure_dag(dm_graph* g, hipStream_t s);
+
 extern "C" dm_status dm_load_csr(int32_t n, const int64_t* row_ptr, const int32_t* col, uint32_t flags, void* stream,
                                  dm_graph** out) {
   if (!out) return fail(DM_E_ARG, "null output handle");
   *out = nullptr;
   if (n < 0 || !row_ptr || (!col && n > 0)) return fail(DM_E_ARG, "n < 0 or null CSR array");
-  if (flags & ~3u) return fail(DM_E_ARG, "unknown flag");
+  if (flags & ~7u) return fail(DM_E_ARG, "unknown flag");
   const bool on_device = flags & DM_CSR_DEVICE;
   const bool trusted = flags & DM_CSR_TRUSTED;
   int64_t nnz = 0;
@@ -366,6 +369,12 @@ extern "C" dm_status dm_load_csr(int32_t n, const int64_t* row_ptr, const int32_
     return bail(fail(DM_E_CSR, buf));
   }
   g->dmax = hostw[1];
+  if (flags & DM_CSR_ORIENT) {
+    const dm_status st = ensure_dag(g, s);
+    if (st != DM_OK) return bail(st);
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return bail(hip_fail(e, "dm_load_csr: orient"));
+  }
   *out = g;
   return DM_OK;
 }
@@ -427,13 +436,21 @@ struct Opt {
   uint64_t* wave_stats = nullptr;
   uint32_t wave_stats_len = 0;
   uint64_t bias = 0;
+  uint32_t wait_limit_us = 0;
+  const float* root_cost = nullptr;
 };
 
 dm_status read_opt(const dm_options* o, Opt* r) {
   *r = Opt();
   if (!o) return DM_OK;
   if (o->size != sizeof(dm_options)) return fail(DM_E_ARG, "dm_options.size != sizeof(dm_options)");
-  if (o->sched & ~15u) return fail(DM_E_ARG, "unknown sched bits");
+  if (o->sched & ~63u) return fail(DM_E_ARG, "unknown sched bits");
+  if ((o->sched & DM_IMPL_DFS) && ((o->sched & ~static_cast<uint32_t>(DM_IMPL_DFS | DM_NO_DONATION)) || o->roots))
+    return fail(DM_E_ARG, "DM_IMPL_DFS runs the plain root order over every root, with no other option");
+  if ((o->sched & DM_SCHED_COST) && (o->sched & DM_SCHED_LEARNED))
+    return fail(DM_E_ARG, "DM_SCHED_COST and DM_SCHED_LEARNED are exclusive");
+  if ((o->sched & DM_SCHED_COST) && !o->root_cost) return fail(DM_E_ARG, "DM_SCHED_COST needs root_cost");
+  if ((o->sched & DM_SCHED_COST) && o->roots) return fail(DM_E_ARG, "cost ordering orders every root; no root list");
   if (o->rebalance < 0.f || o->rebalance > 1.f) return fail(DM_E_ARG, "rebalance must be in [0, 1]");
   if (o->num_roots < 0 || (o->num_roots > 0 && !o->roots)) return fail(DM_E_ARG, "bad root list");
   if ((o->sched & DM_RECORD_ROOTS) && !o->root_stats) return fail(DM_E_ARG, "DM_RECORD_ROOTS needs root_stats");
@@ -450,7 +467,22 @@ dm_status read_opt(const dm_options* o, Opt* r) {
   r->wave_stats = o->wave_stats;
   r->wave_stats_len = o->wave_stats ? o->wave_stats_len : 0;
   r->bias = o->counter_bias;
+  r->wait_limit_us = o->wait_limit_us;
+  r->root_cost = (o->sched & DM_SCHED_COST) ? o->root_cost : nullptr;
   return DM_OK;
+}
+
+// Default bound on how long an idle wave waits for donated work.  A launch's
+// idle waves are normally fed within microseconds; only a scheduler fault can
+// starve them this long.
+constexpr uint32_t kDefaultWaitLimitUs = 600000000u;
+
+// wall-clock ticks (the counter read by wall_clock64) in `us` microseconds
+uint64_t wait_ticks(uint32_t us) {
+  int dev = 0, khz = 0;
+  (void)hipGetDevice(&dev);
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0) khz = 100000;
+  return static_cast<uint64_t>(us ? us : kDefaultWaitLimitUs) * static_cast<uint64_t>(khz) / 1000u;
 }
 
 int cu_count() {
@@ -471,9 +503,8 @@ constexpr size_t kCtrlHeads = (kCtrlSlots + sizeof(int) * kSlots + sizeof(int) *
 size_t ctrl_bytes() { return kCtrlHeads + sizeof(unsigned long long) * kHeadStride * kQueueHeads; }
 
 // scheduler fields common to both kernels
-Sched make_sched(dm_graph* g, const Opt& o, int grid, int64_t nq, const int32_t* qroot, const int32_t* qstat) {
+Sched make_sched_at(char* c, const Opt& o, int grid, int64_t nq, const int32_t* qroot, const int32_t* qstat) {
   Sched S{};
-  char* c = g->ctrl.as<char>();
   S.qhead = reinterpret_cast<unsigned long long*>(c + kCtrlHeads);
   S.state = reinterpret_cast<unsigned long long*>(c + kCtrlState);
   S.idle = reinterpret_cast<int*>(c + kCtrlIdle);
@@ -494,7 +525,13 @@ Sched make_sched(dm_graph* g, const Opt& o, int grid, int64_t nq, const int32_t*
   S.idle_trigger = trig < 1 ? 1 : trig;
   S.period = 64;
   S.waves = grid;
+  S.wait_limit = wait_ticks(o.wait_limit_us);
+  S.flags = reinterpret_cast<int*>(c + kCtrlFlags);
   return S;
+}
+
+Sched make_sched(dm_graph* g, const Opt& o, int grid, int64_t nq, const int32_t* qroot, const int32_t* qstat) {
+  return make_sched_at(g->ctrl.as<char>(), o, grid, nq, qroot, qstat);
 }
 
 int* ctrl_flags(dm_graph* g) { return reinterpret_cast<int*>(g->ctrl.as<char>() + kCtrlFlags); }
@@ -532,6 +569,8 @@ struct Prepared {
 };
 
 dm_status check_flags(const int* flags) {
+  if (flags[1] & kFlagWaitLimit)
+    return fail(DM_E_HIP, "an idle wave waited longer than the scheduler's wait limit; the launch was abandoned");
   if (flags[1]) {
     char buf[96];
     std::snprintf(buf, sizeof buf, "internal capacity check failed (0x%x)", flags[1]);
@@ -603,14 +642,21 @@ dm_status ensure_features(dm_graph* g, hipStream_t s) {
 // cached on the handle and rebuilt when the parameters' fingerprint, the grid
 // or the chunk count change.
 dm_status learned_queue(dm_graph* g, const Opt& o, int grid, hipStream_t s, int64_t* nchunks) {
-  dm_status st = ensure_features(g, s);
-  if (st != DM_OK) return st;
+  // predictions: the MLP's on the graph's features, or the caller's costs
+  const bool given = o.root_cost != nullptr;
+  if (!given) {
+    dm_status st = ensure_features(g, s);
+    if (st != DM_OK) return st;
+  }
   const size_t n = static_cast<size_t>(g->n > 0 ? g->n : 1);
   HIP_OR_RETURN(g->lqkey.ensure(sizeof(unsigned long long)), "learned: allocate");
-  HIP_OR_RETURN(param_fingerprint(o.mlp, kMlpBlob, g->lqkey.as<unsigned long long>(), s), "learned: fingerprint");
+  HIP_OR_RETURN(param_fingerprint(given ? o.root_cost : o.mlp, given ? g->n : kMlpBlob,
+                                  g->lqkey.as<unsigned long long>(), s),
+                "learned: fingerprint");
   unsigned long long key = 0;
   HIP_OR_RETURN(hipMemcpyAsync(&key, g->lqkey.p, sizeof(key), hipMemcpyDeviceToHost, s), "learned: fingerprint");
   HIP_OR_RETURN(hipStreamSynchronize(s), "learned: fingerprint");
+  if (given) key = ~key;  // keep cost-ordered and MLP-ordered queues apart
   const int per_wave = o.chunk ? static_cast<int>(o.chunk) : 8;
   if (g->lq_valid && key == g->lq_key && grid == g->lq_grid && per_wave == g->lq_per_wave) {
     *nchunks = g->lq_nchunks;
@@ -621,8 +667,9 @@ dm_status learned_queue(dm_graph* g, const Opt& o, int grid, hipStream_t s, int6
   HIP_OR_RETURN(g->lorder.ensure(sizeof(int32_t) * n), "learned: allocate");
   HIP_OR_RETURN(g->lqroot.ensure(sizeof(int32_t) * n), "learned: allocate");
   HIP_OR_RETURN(g->lqbounds.ensure(sizeof(int64_t) * (n + 1)), "learned: allocate");
-  HIP_OR_RETURN(mlp_forward(o.mlp, g->feat.as<int64_t>(), g->n, g->pred.as<float>(), s), "learned: forward");
-  HIP_OR_RETURN(lpt_order(g->pred.as<float>(), g->n, grid * per_wave, g->lorder.as<int32_t>(),
+  if (!given)
+    HIP_OR_RETURN(mlp_forward(o.mlp, g->feat.as<int64_t>(), g->n, g->pred.as<float>(), s), "learned: forward");
+  HIP_OR_RETURN(lpt_order(given ? o.root_cost : g->pred.as<float>(), g->n, grid * per_wave, g->lorder.as<int32_t>(),
                           g->lqbounds.as<int64_t>(), nchunks, s),
                 "learned: order");
   HIP_OR_RETURN(launch_gather_i32(g->rank.as<int32_t>(), g->lorder.as<int32_t>(), g->lqroot.as<int32_t>(), g->n, s),
@@ -648,7 +695,7 @@ dm_status build_queue(dm_graph* g, const Opt& o, int grid, hipStream_t s, Sched*
     S->nq = o.num_roots;
     S->qroot = g->qroot.as<int32_t>();
     S->qstat = nullptr;
-  } else if (o.sched & DM_SCHED_LEARNED) {
+  } else if (o.sched & (DM_SCHED_LEARNED | DM_SCHED_COST)) {
     int64_t nchunks = 0;
     dm_status st = learned_queue(g, o, grid, s, &nchunks);
     if (st != DM_OK) return st;
@@ -697,8 +744,6 @@ dm_status prepare_clique(dm_graph* g, int k, const Opt& o, hipStream_t s, const 
   const int grid = size_grid(per_cu, g->nnz);
   HIP_OR_RETURN(g->ctrl.ensure(ctrl_bytes()), "workspace");
   HIP_OR_RETURN(g->out.ensure(sizeof(uint64_t) * ngraphs), "workspace");
-  // rows of roots with more than 128 out-neighbours: one region per wave
-  HIP_OR_RETURN(g->rows.ensure(sizeof(uint64_t) * static_cast<size_t>(grid) * W * dmax), "workspace");
   Sched S = make_sched(g, o, grid, g->n, nullptr, nullptr);
   st = build_queue(g, o, grid, s, &S);
   if (st != DM_OK) return st;
@@ -716,7 +761,6 @@ dm_status prepare_clique(dm_graph* g, int k, const Opt& o, hipStream_t s, const 
   A.root_stats = reinterpret_cast<unsigned long long*>(o.root_stats);
   A.wave_stats = reinterpret_cast<unsigned long long*>(o.wave_stats);
   A.wave_stats_len = static_cast<int>(o.wave_stats_len);
-  A.rows_global = g->rows.as<unsigned long long>();
   A.prune = o.root_stats ? 0 : 1;
   // row cache: filled by a counting launch over all roots (not a recording
   // one, whose rows path reads member degrees), read by every later launch
@@ -737,6 +781,13 @@ dm_status prepare_clique(dm_graph* g, int k, const Opt& o, hipStream_t s, const 
       A.rcache = g->rcache.as<unsigned long long>();
       A.rcoff = g->rcoff.as<int64_t>();
     }
+  }
+  // rows of roots with more than kLocalMax out-neighbours when no row cache
+  // serves the launch: one region per wave
+  A.rows_global = nullptr;
+  if (A.rc_mode == 0 && dmax > kCliqueLocalRows) {
+    HIP_OR_RETURN(g->rows.ensure(sizeof(uint64_t) * static_cast<size_t>(grid) * W * dmax), "workspace");
+    A.rows_global = g->rows.as<unsigned long long>();
   }
   A.S = S;
   P->clique = true;
@@ -918,6 +969,77 @@ dm_status autotune(dm_graph* g, int op, int k, const Opt& base, hipStream_t s, c
 
 }  // namespace
 
+// ---------------------------------------------------------------- one lane per traversal (ablation)
+
+namespace {
+
+// Per-lane stacks are capped at this many bytes in total; the grid shrinks
+// to the lanes that fit.
+constexpr size_t kDfsStackMax = size_t(4) << 30;
+
+dm_status run_dfs(dm_graph* g, int op, int k, const Opt& o, hipStream_t s, uint64_t* host_out, int ncls) {
+  DfsArgs A;
+  std::memset(&A, 0, sizeof A);
+  int dmax = 1;
+  if (op == DM_OP_CLIQUE) {
+    if (k > kDfsMaxK) return fail(DM_E_K, "DM_IMPL_DFS counts cliques up to k = 16");
+    dm_status st = ensure_dag(g, s);
+    if (st != DM_OK) return st;
+    A.rp = g->drp.as<int64_t>();
+    A.col = g->dcol.as<int32_t>();
+    dmax = g->ddmax > 0 ? g->ddmax : 1;
+    A.lane_stride = static_cast<int64_t>(k > 3 ? k - 3 : 1) * dmax;
+  } else {
+    uint8_t* dtab = nullptr;
+    HIP_OR_RETURN(device_table(k, &dtab), "class table upload");
+    dm_status st = ensure_ranked(g, s);
+    if (st != DM_OK) return st;
+    A.rp = g->urp.as<int64_t>();
+    A.col = g->ucol.as<int32_t>();
+    dmax = g->dmax > 0 ? g->dmax : 1;
+    A.table = dtab;
+    A.ncls = ncls;
+    int64_t off = 0;
+    for (int s2 = 1; s2 <= k - 1; ++s2) {
+      A.level_off[s2] = off;
+      A.level_cap[s2] = static_cast<int64_t>(s2) * dmax;
+      off += A.level_cap[s2];
+    }
+    A.lane_stride = off;
+  }
+  A.n = g->n;
+  A.k = k;
+  A.dmax = dmax;
+  const size_t lane_bytes = static_cast<size_t>(A.lane_stride) * (op == DM_OP_CLIQUE ? 4 : 5);
+  int per_cu = o.waves_per_cu ? static_cast<int>(o.waves_per_cu) : 16;
+  int grid = size_grid(per_cu, g->nnz);
+  const int64_t fit = static_cast<int64_t>(kDfsStackMax / (lane_bytes * kWave));
+  if (fit < 1) return fail(DM_E_NOMEM, "DM_IMPL_DFS: one wave's stacks exceed the cap");
+  if (fit < grid) grid = static_cast<int>(fit);
+  HIP_OR_RETURN(g->ctrl.ensure(ctrl_bytes()), "workspace");
+  HIP_OR_RETURN(g->out.ensure(sizeof(uint64_t) * ncls), "workspace");
+  HIP_OR_RETURN(g->dfs_stack.ensure(sizeof(int32_t) * static_cast<size_t>(A.lane_stride) * grid * kWave), "dfs stacks");
+  if (op == DM_OP_MOTIF)
+    HIP_OR_RETURN(g->dfs_mask.ensure(static_cast<size_t>(A.lane_stride) * grid * kWave), "dfs stacks");
+  char* c = g->ctrl.as<char>();
+  A.qhead = reinterpret_cast<unsigned long long*>(c + kCtrlHeads);
+  A.flags = reinterpret_cast<int*>(c + kCtrlFlags);
+  A.out = g->out.as<unsigned long long>();
+  A.stack = g->dfs_stack.as<int32_t>();
+  A.masks = op == DM_OP_MOTIF ? g->dfs_mask.as<uint8_t>() : nullptr;
+  HIP_OR_RETURN(launch_fill_u64(g->ctrl.as<unsigned long long>(), static_cast<int64_t>(ctrl_bytes() / 8), 0ull, s), "clear");
+  HIP_OR_RETURN(launch_fill_u64(A.out, ncls, o.bias, s), "clear");
+  if (g->n > 0)
+    HIP_OR_RETURN(op == DM_OP_CLIQUE ? launch_dfs_clique(A, grid, s) : launch_dfs_motif(A, grid, s), "dfs kernel");
+  int flags[2] = {0, 0};
+  HIP_OR_RETURN(hipMemcpyAsync(host_out, A.out, sizeof(uint64_t) * ncls, hipMemcpyDeviceToHost, s), "copy-back");
+  HIP_OR_RETURN(hipMemcpyAsync(flags, A.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, s), "copy-back");
+  HIP_OR_RETURN(hipStreamSynchronize(s), "dfs kernel");
+  return check_flags(flags);
+}
+
+}  // namespace
+
 extern "C" dm_status dm_count_cliques(dm_graph* g, int k, uint64_t* out_count, const dm_options* opt) {
   if (!g || !out_count) return fail(DM_E_ARG, "null graph or output");
   if (k < 1 || k > kMaxK) return fail(DM_E_K, "clique k must be in 1..32");
@@ -926,10 +1048,15 @@ extern "C" dm_status dm_count_cliques(dm_graph* g, int k, uint64_t* out_count, c
   if (st != DM_OK) return st;
   if ((o.sched & DM_SCHED_LEARNED) && !o.mlp) return fail(DM_E_MODEL, "DM_SCHED_LEARNED needs mlp parameters");
   hipStream_t s = pick_stream(g, o.stream);
+  uint64_t c = 0;
+  if (o.sched & DM_IMPL_DFS) {
+    st = run_dfs(g, DM_OP_CLIQUE, k, o, s, &c, 1);
+    if (st == DM_OK) *out_count = c;
+    return st;
+  }
   apply_tuning(DM_OP_CLIQUE, k, &o);
   Prepared P;
   st = prepare(g, DM_OP_CLIQUE, k, o, s, nullptr, 1, &P);
-  uint64_t c = 0;
   if (st == DM_OK) st = run_prepared(P, s, &c);
   if (st == DM_OK) *out_count = c;
   return st;
@@ -945,8 +1072,13 @@ extern "C" dm_status dm_count_motifs(dm_graph* g, int k, uint64_t* out_counts, s
   if (st != DM_OK) return st;
   if ((o.sched & DM_SCHED_LEARNED) && !o.mlp) return fail(DM_E_MODEL, "DM_SCHED_LEARNED needs mlp parameters");
   hipStream_t s = pick_stream(g, o.stream);
-  apply_tuning(DM_OP_MOTIF, k, &o);
   std::vector<uint64_t> tmp(T->ncls);
+  if (o.sched & DM_IMPL_DFS) {
+    st = run_dfs(g, DM_OP_MOTIF, k, o, s, tmp.data(), T->ncls);
+    if (st == DM_OK) std::memcpy(out_counts, tmp.data(), sizeof(uint64_t) * T->ncls);
+    return st;
+  }
+  apply_tuning(DM_OP_MOTIF, k, &o);
   Prepared P;
   st = prepare(g, DM_OP_MOTIF, k, o, s, nullptr, 1, &P);
   if (st == DM_OK) st = run_prepared(P, s, tmp.data());
@@ -1163,6 +1295,8 @@ extern "C" dm_status dm_batch(dm_graph* const* gs, int32_t num_graphs, int op, i
   dm_status st = read_opt(opt, &o);
   if (st != DM_OK) return st;
   if (o.roots) return fail(DM_E_ARG, "root lists are not supported in batches");
+  if (o.sched & DM_SCHED_COST) return fail(DM_E_ARG, "cost ordering takes one graph's costs; not for batches");
+  if (o.sched & DM_IMPL_DFS) return fail(DM_E_ARG, "DM_IMPL_DFS runs single graphs");
   if ((o.sched & DM_SCHED_LEARNED) && !o.mlp) return fail(DM_E_MODEL, "DM_SCHED_LEARNED needs mlp parameters");
   return batch_run(gs, num_graphs, op, k, width, o, out_counts);
 }
@@ -1296,6 +1430,8 @@ extern "C" dm_status dm_autotune(dm_graph* const* gs, int32_t num_graphs, int op
   dm_status st = read_opt(opt, &o);
   if (st != DM_OK) return st;
   if (o.roots) return fail(DM_E_ARG, "tuning runs over every root");
+  if ((o.sched & DM_SCHED_COST) && num_graphs > 1) return fail(DM_E_ARG, "cost ordering takes one graph's costs");
+  if (o.sched & DM_IMPL_DFS) return fail(DM_E_ARG, "the tuner times the wave kernels");
   if ((o.sched & DM_SCHED_LEARNED) && !o.mlp) return fail(DM_E_MODEL, "DM_SCHED_LEARNED needs mlp parameters");
   Tuning t;
   if (num_graphs == 1) {

@@ -48,7 +48,7 @@ struct CliqueLds {
 
 __device__ __forceinline__ size_t align16(size_t x) { return (x + 15) & ~static_cast<size_t>(15); }
 
-constexpr int kLocalMax = 128;    // roots with at most this many out-neighbours use their rows in place
+constexpr int kLocalMax = kCliqueLocalRows;  // roots with at most this many out-neighbours use their rows in place
 constexpr int kReindexMax = 128;  // larger roots re-index candidate sets of at most this many members
 
 __device__ CliqueLds carve(unsigned char* smem, int dmax, int W, int k) {
@@ -895,7 +895,9 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4)))
   const int lane = lane_id();
   const int wave_gid = blockIdx.x;
   CliqueLds L = carve(smem, A.dmax, A.W, A.k);
-  uint64_t* rows_g = reinterpret_cast<uint64_t*>(A.rows_global) + static_cast<size_t>(wave_gid) * A.W * A.dmax;
+  // (no region when every root's rows are in LDS or in the row cache)
+  uint64_t* rows_g = A.rows_global ? reinterpret_cast<uint64_t*>(A.rows_global) + static_cast<size_t>(wave_gid) * A.W * A.dmax
+                                   : nullptr;
   WaveAcc WA;
   WA.acc = 0;
   WA.cur_g = -1;

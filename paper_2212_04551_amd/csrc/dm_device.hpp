@@ -161,7 +161,13 @@ struct Sched {
   int idle_trigger;           // donate only when at least this many waves are idle
   int period;                 // DFS steps between donation checks
   int waves;                  // waves in the launch
+  uint64_t wait_limit;        // wall-clock ticks an idle wave may wait for work before it gives up
+  int* flags;                 // flags[1] |= kFlagWaitLimit when a wave gives up
 };
+
+// flags[1] bit set by a wave that gave up waiting (the launch's counts are
+// then incomplete and the call fails)
+constexpr int kFlagWaitLimit = 8;
 
 // A unit of work: root vertex, its stats row, the traversal depth the task
 // starts at, the iteration range at that depth, and the prefix choices.
@@ -425,6 +431,15 @@ __device__ __forceinline__ bool sched_next(const Sched& S, SchedIter& it, int wa
     }
     int data = 0;
     if ((st & 0xffffffffull) == 0 || !sched_take(S, &data, wave_gid)) {
+      // bounded wait: a wave idle for longer than the limit leaves the loop
+      // and flags the launch, so a scheduler fault ends the kernel with an
+      // error instead of keeping the GPU busy
+      const uint64_t waited = wall_clock64() - it.t0;
+      if (uniu64(waited) > S.wait_limit) {
+        if (lane_id() == 0) atomicOr(S.flags + 1, kFlagWaitLimit);
+        it.t_idle += waited;
+        return false;
+      }
       __builtin_amdgcn_s_sleep(16);
       continue;
     }

@@ -14,6 +14,10 @@ namespace dm {
 constexpr int kMlpNet = 4 * 64 + 64 + 64 * 64 + 64 + 64 + 1;  // 4545 weights
 constexpr int kMlpBlob = kMlpNet + 8;                          // + feature mean[4], std[4]
 
+// Roots with at most this many out-neighbours keep their bitmap rows in LDS;
+// wider roots read them from the graph's row cache or a per-wave global region.
+constexpr int kCliqueLocalRows = 128;
+
 // Arguments of the persistent k-clique kernel (graph in rank space, DAG CSR).
 struct CliqueArgs {
   const int64_t* rp;       // DAG row offsets, n+1
@@ -60,7 +64,29 @@ struct MotifArgs {
   Sched S;
 };
 
+// Arguments of the one-lane-per-traversal ablation kernels (dm_dfs.hip).
+constexpr int kDfsMaxK = 16;
+struct DfsArgs {
+  const int64_t* rp;       // cliques: DAG CSR in rank space; motifs: undirected CSR in rank space
+  const int32_t* col;
+  int32_t n;
+  int k;
+  int dmax;                // largest (out-)degree
+  unsigned long long* out; // one counter (cliques) or ncls counters (motifs)
+  int* flags;              // [0] overflow, [1] capacity / dictionary errors
+  unsigned long long* qhead;  // next root
+  int32_t* stack;          // per-lane stacks, lane_stride entries each
+  uint8_t* masks;          // motifs: mask byte per stack entry
+  int64_t lane_stride;
+  const uint8_t* table;    // motifs: canonical-relabeling dictionary
+  int ncls;
+  int64_t level_off[kDfsMaxK + 1];  // motifs: start of level s in a lane's stack
+  int64_t level_cap[kDfsMaxK + 1];
+};
+
 // kernel launchers (return hipSuccess or the launch error)
+hipError_t launch_dfs_clique(const DfsArgs& a, int grid, hipStream_t s);
+hipError_t launch_dfs_motif(const DfsArgs& a, int grid, hipStream_t s);
 hipError_t launch_clique(const CliqueArgs& a, int grid, size_t lds_bytes, hipStream_t s);
 size_t clique_lds_bytes(int dmax, int W, int k);
 hipError_t clique_occupancy(size_t lds_bytes, int* blocks_per_cu);

@@ -21,14 +21,17 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "lib", "libdumato_mi.so")
 
 DM_OK, DM_E_ARG, DM_E_CSR, DM_E_K, DM_E_OVERFLOW, DM_E_NOMEM, DM_E_HIP, DM_E_BUFSZ, DM_E_MODEL = range(9)
-DM_CSR_HOST, DM_CSR_DEVICE, DM_CSR_TRUSTED = 0, 1, 2
+DM_CSR_HOST, DM_CSR_DEVICE, DM_CSR_TRUSTED, DM_CSR_ORIENT = 0, 1, 2, 4
 DM_SCHED_PLAIN, DM_SCHED_LEARNED, DM_SCHED_AUTOTUNE, DM_RECORD_ROOTS, DM_NO_DONATION = 0, 1, 2, 4, 8
+DM_SCHED_COST = 16
+DM_IMPL_DFS = 32
 DM_OP_CLIQUE, DM_OP_MOTIF = 0, 1
 DM_MLP_NET = 4 * 64 + 64 + 64 * 64 + 64 + 64 + 1  # 4 -> 64 -> 64 -> 1 weights
 DM_MLP_NPARAMS = DM_MLP_NET + 8                     # + feature mean[4], std[4]
 
 EXPORTS = [
-    "dm_load_csr", "dm_free", "dm_graph_info", "dm_count_cliques", "dm_motif_num_classes",
+    "dm_load_csr", "dm_free", "dm_graph_info", "dm_count_cliques",
+    "dm_motif_num_classes",
     "dm_motif_class_mask", "dm_motif_class_table", "dm_count_motifs", "dm_batch", "dm_strerror",
     "dm_last_error", "dm_features", "dm_mlp_init", "dm_mlp_fit_normalizer", "dm_mlp_forward", "dm_mlp_targets",
     "dm_mlp_loss_grad", "dm_mlp_adam_step", "dm_mlp_train", "dm_autotune",
@@ -55,6 +58,8 @@ class dm_options(ctypes.Structure):
         ("wave_stats", ctypes.c_void_p),
         ("wave_stats_len", ctypes.c_uint32),
         ("counter_bias", ctypes.c_uint64),
+        ("wait_limit_us", ctypes.c_uint32),
+        ("root_cost", ctypes.c_void_p),
     ]
 
 
@@ -148,7 +153,8 @@ def _stream(s) -> Optional[int]:
 
 
 def make_options(sched: int = 0, stream=None, chunk: int = 0, rebalance: float = 0.0, waves_per_cu: int = 0,
-                 mlp=None, roots=None, root_stats=None, wave_stats=None, counter_bias: int = 0):
+                 mlp=None, roots=None, root_stats=None, wave_stats=None, counter_bias: int = 0,
+                 wait_limit_us: int = 0, root_cost=None):
     """Build a dm_options struct; returns (struct, keep-alive list)."""
     keep = []
     o = dm_options()
@@ -171,7 +177,12 @@ def make_options(sched: int = 0, stream=None, chunk: int = 0, rebalance: float =
         o.wave_stats = _ptr(wave_stats)
         o.wave_stats_len = int(wave_stats.numel() // 4) if hasattr(wave_stats, "numel") else int(wave_stats.size // 4)
     o.counter_bias = counter_bias
+    o.wait_limit_us = wait_limit_us
+    if root_cost is not None:
+        o.root_cost = _ptr(root_cost)
+        o.sched |= DM_SCHED_COST
     keep.append(mlp)
+    keep.append(root_cost)
     return o, keep
 
 
@@ -197,7 +208,8 @@ class DMGraph:
             pass
 
 
-def load_csr(n: int, row_ptr, col, device: bool = False, trusted: bool = False, stream=None) -> DMGraph:
+def load_csr(n: int, row_ptr, col, device: bool = False, trusted: bool = False, stream=None,
+             orient: bool = False) -> DMGraph:
     """dm_load_csr on numpy arrays (host) or torch CUDA tensors (device=True)."""
     if not device:
         row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
@@ -205,6 +217,7 @@ def load_csr(n: int, row_ptr, col, device: bool = False, trusted: bool = False, 
         if col.size == 0:
             col = np.zeros(1, dtype=np.int32)
     flags = (DM_CSR_DEVICE if device else DM_CSR_HOST) | (DM_CSR_TRUSTED if trusted else 0)
+    flags |= DM_CSR_ORIENT if orient else 0
     h = ctypes.c_void_p(None)
     _check(lib().dm_load_csr(n, _ptr(row_ptr), _ptr(col), flags, _stream(stream), ctypes.byref(h)))
     return DMGraph(h.value)

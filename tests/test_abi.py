@@ -30,11 +30,22 @@ def test_library_exports_every_declared_symbol():
     assert set(names) == set(dm.EXPORTS)
 
 
-def test_options_struct_layout():
-    # matches the C layout: 13 fields, pointer-aligned, 88 bytes on LP64
-    assert ctypes.sizeof(dm.dm_options) == 88
-    assert dm.dm_options.counter_bias.offset == 80
-    assert dm.dm_options.mlp.offset == 32
+def test_options_struct_layout(tmp_path):
+    """The ctypes mirror of dm_options has the C struct's size and field
+    offsets, as the host C compiler lays them out from include/dm.h."""
+    fields = [f[0] for f in dm.dm_options._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "dm.h"\nint main(void){\n'
+                   '  printf("%zu\\n", sizeof(dm_options));\n'
+                   + "".join(f'  printf("%zu\\n", offsetof(dm_options, {f}));\n' for f in fields)
+                   + "  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    vals = [int(x) for x in subprocess.check_output([str(exe)]).split()]
+    assert vals[0] == ctypes.sizeof(dm.dm_options)
+    for f, off in zip(fields, vals[1:]):
+        assert getattr(dm.dm_options, f).offset == off, f
 
 
 @pytest.mark.parametrize("k", [3, 4, 5, 6])
