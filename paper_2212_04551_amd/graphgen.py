@@ -170,6 +170,39 @@ def from_dense(adj: np.ndarray) -> Graph:
     return from_edges(a.shape[0], iu)
 
 
+def hub_graph(roots: int, base: int, hub_degree: int, seed: int) -> Graph:
+    """Sparse base with three high-degree hubs and a few low-rank roots.
+
+    Vertices 0..roots-1 are the roots: each is adjacent to the three hubs only
+    (degree 3, the lowest (degree, id) ranks).  Vertices roots..roots+base-1
+    form a cycle plus a seeded perfect matching (degree 3 each, ranked above
+    the roots).  The hubs are the last three vertices: hub 0 ~ hub 1 and
+    hub 1 ~ hub 2 are edges, hub 0 and hub 2 are not; each hub is adjacent to
+    `hub_degree` seeded base vertices, 10% of them shared with the next hub.
+    A traversal made of a root and two (three) hubs has a list of about
+    2 (3) x hub_degree entries above the root."""
+    rng = np.random.default_rng(seed)
+    n = roots + base + 3
+    hubs = [roots + base, roots + base + 1, roots + base + 2]
+    edges = []
+    b = np.arange(roots, roots + base)
+    edges += [(int(b[i]), int(b[(i + 1) % base])) for i in range(base)]
+    perm = rng.permutation(b)
+    edges += [(int(perm[2 * i]), int(perm[2 * i + 1])) for i in range(base // 2)]
+    for r in range(roots):
+        edges += [(r, h) for h in hubs]
+    edges += [(hubs[0], hubs[1]), (hubs[1], hubs[2])]
+    prev = None
+    for h in hubs:
+        own = rng.choice(b, hub_degree, replace=False)
+        if prev is not None:
+            own[: hub_degree // 10] = prev[: hub_degree // 10]
+        own = np.unique(own)
+        edges += [(int(x), h) for x in own]
+        prev = rng.permutation(own)
+    return from_edges(n, edges)
+
+
 def complete(n: int) -> Graph:
     return from_edges(n, [(i, j) for i in range(n) for j in range(i + 1, n)])
 

@@ -134,12 +134,13 @@ def test_training_lowers_loss_and_learned_counts_are_exact():
     pred = dm.mlp_forward(p, F).cpu().numpy()
     tgt = T.cpu().numpy()
     assert np.corrcoef(pred, tgt)[0, 1] > 0.8
-    # learned ordering: identical counts, cliques and motifs
-    assert np.array_equal(dm.count_motifs(h, 4, sched=dm.DM_SCHED_LEARNED, mlp=p), ref)
-    assert np.array_equal(dm.count_motifs(h, 5, sched=dm.DM_SCHED_LEARNED, mlp=p), dm.count_motifs(h, 5))
+    # learned ordering: the oracle's counts, cliques and motifs
+    assert np.array_equal(ref, O.motif_count(g, 4, threads=8))
+    assert np.array_equal(dm.count_motifs(h, 4, sched=dm.DM_SCHED_LEARNED, mlp=p), O.motif_count(g, 4, threads=8))
+    assert np.array_equal(dm.count_motifs(h, 5, sched=dm.DM_SCHED_LEARNED, mlp=p), O.motif_count(g, 5, threads=8))
     for k in (3, 4, 5, 6):
         assert dm.count_cliques(h, k, sched=dm.DM_SCHED_LEARNED, mlp=p) == O.clique_count(g, k, threads=8)
-    assert dm.count_cliques(h, 5, sched=dm.DM_SCHED_LEARNED | dm.DM_NO_DONATION, mlp=p) == dm.count_cliques(h, 5)
+    assert dm.count_cliques(h, 5, sched=dm.DM_SCHED_LEARNED | dm.DM_NO_DONATION, mlp=p) == O.clique_count(g, 5, threads=8)
     with pytest.raises(dm.DMError) as e:
         dm.count_cliques(h, 4, sched=dm.DM_SCHED_LEARNED, mlp=p, roots=np.arange(10))
     assert e.value.status == dm.DM_E_ARG
@@ -171,3 +172,31 @@ def test_learned_queue_cache_follows_parameter_changes():
     check(chunk=3)
     check(waves_per_cu=1)
     assert np.array_equal(dm.count_motifs(h, 4, sched=dm.DM_SCHED_LEARNED, mlp=p), O.motif_count(g, 4, threads=8))
+
+
+def test_cost_ordering_by_recorded_sizes_is_exact():
+    """DM_SCHED_COST orders and chunks the roots by caller-given costs (here the
+    recorded tree sizes, the ordering a perfect predictor would give): counts
+    and per-root records stay exact; it excludes DM_SCHED_LEARNED, root lists
+    and batches."""
+    import torch
+    g = gg.chung_lu(6000, 30000, 2.2, 300.0, 21)[0]
+    h = dm.load_graph(g)
+    tot, leaves, nodes, reads = O.clique_count(g, 5, per_root=True, threads=8)
+    stats = torch.zeros((g.n, 3), dtype=torch.int64, device="cuda")
+    assert dm.count_cliques(h, 5, root_stats=stats) == tot
+    cost = dm.mlp_targets(stats)
+    st2 = torch.zeros((g.n, 3), dtype=torch.int64, device="cuda")
+    assert dm.count_cliques(h, 5, root_cost=cost, root_stats=st2) == tot
+    s = st2.cpu().numpy().astype(np.uint64)
+    assert np.array_equal(s[:, 0], nodes) and np.array_equal(s[:, 1], leaves) and np.array_equal(s[:, 2], reads)
+    assert dm.count_cliques(h, 5, root_cost=cost, chunk=2) == tot
+    assert np.array_equal(dm.count_motifs(h, 4, root_cost=cost), O.motif_count(g, 4, threads=8))
+    p = dm.mlp_new(0)
+    for kw in (dict(sched=dm.DM_SCHED_LEARNED, mlp=p), dict(roots=np.arange(10))):
+        with pytest.raises(dm.DMError) as e:
+            dm.count_cliques(h, 5, root_cost=cost, **kw)
+        assert e.value.status == dm.DM_E_ARG
+    with pytest.raises(dm.DMError) as e:
+        dm.batch([h, h], dm.DM_OP_CLIQUE, 3, root_cost=cost)
+    assert e.value.status == dm.DM_E_ARG

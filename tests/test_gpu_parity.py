@@ -244,18 +244,24 @@ def test_clique_record_mode():
         assert np.array_equal(st[:, 2], reads)
 
 
-def test_motif_record_mode_leaves_and_nodes():
+def test_motif_record_mode():
+    """Per-root leaves, tree nodes and adjacency entries read (the degree of
+    the last vertex of each expanded set's canonical order) equal the
+    oracle's, on a preferential-attachment graph and on a Chung-Lu graph."""
     import torch
-    g = gg.barabasi_albert(800, 3, 4)
-    h = dm.load_graph(g)
-    for k in (3, 4, 5):
-        stats = torch.zeros((g.n, 3), dtype=torch.int64, device="cuda")
-        c = dm.count_motifs(h, k, root_stats=stats)
-        st = stats.cpu().numpy().astype(np.uint64)
-        c2, leaves, nodes, _ = O.motif_count(g, k, per_root=True, threads=8)
-        assert np.array_equal(c, c2)
-        assert np.array_equal(st[:, 1], leaves)
-        assert np.array_equal(st[:, 0], nodes)
+    for g in (gg.barabasi_albert(800, 3, 4), gg.chung_lu(3000, 12000, 2.2, 80.0, 6)[0]):
+        h = dm.load_graph(g)
+        for k in (3, 4, 5, 6):
+            if k == 6 and g.n == 800:
+                continue
+            stats = torch.zeros((g.n, 3), dtype=torch.int64, device="cuda")
+            c = dm.count_motifs(h, k, root_stats=stats)
+            st = stats.cpu().numpy().astype(np.uint64)
+            c2, leaves, nodes, reads = O.motif_count(g, k, per_root=True, threads=8)
+            assert np.array_equal(c, c2), k
+            assert np.array_equal(st[:, 1], leaves), k
+            assert np.array_equal(st[:, 0], nodes), k
+            assert np.array_equal(st[:, 2], reads), k
 
 
 # ------------------------------------------------------------------ schedule invariance
@@ -435,6 +441,26 @@ def test_overflow_detected():
     assert e.value.status == dm.DM_E_OVERFLOW
 
 
+def test_wait_limit_gives_up_with_an_error():
+    """The idle wait of the persistent grid is bounded.  With a host-set limit
+    of 1 microsecond, waves left without work while K_40's 12-clique roots
+    still run stop waiting; every wave exits, the call fails with DM_E_HIP,
+    and the next call with the default limit is exact."""
+    h = dm.load_graph(gg.complete(40))
+    with pytest.raises(dm.DMError) as e:
+        dm.count_cliques(h, 12, wait_limit_us=1)
+    assert e.value.status == dm.DM_E_HIP
+    assert "wait limit" in str(e.value)
+    assert dm.count_cliques(h, 12) == math.comb(40, 12)
+    hs = dm.load_graph(gg.star(600))
+    with pytest.raises(dm.DMError) as e:
+        dm.count_motifs(hs, 5, wait_limit_us=1)
+    assert e.value.status == dm.DM_E_HIP
+    exp = np.zeros(21, np.uint64)
+    exp[int(np.nonzero(O.motif_brute(gg.star(4), 5))[0][0])] = math.comb(600, 4)
+    assert np.array_equal(dm.count_motifs(hs, 5), exp)
+
+
 # ------------------------------------------------------------------ graph replay and autotuning
 
 def test_batch_graph_replays_match_eager():
@@ -465,3 +491,37 @@ def test_autotune_picks_valid_knobs_and_keeps_counts():
     t1 = dm.autotune([h], dm.DM_OP_CLIQUE, 5)
     assert t1["ms"] > 0
     assert dm.count_cliques(h, 5, sched=dm.DM_SCHED_AUTOTUNE) == O.clique_count(g, 5, threads=8)
+
+
+# ------------------------------------------------------------------ one lane per traversal (ablation)
+
+@pytest.mark.parametrize("name,make", RANDOM, ids=[r[0] for r in RANDOM])
+def test_dfs_ablation_matches_oracle(name, make):
+    """DM_IMPL_DFS (each lane enumerates one root's tree alone) gives the
+    oracle's clique and motif counts."""
+    g = make(1)
+    h = dm.load_graph(g)
+    for k in range(3, 8):
+        assert dm.count_cliques(h, k, sched=dm.DM_IMPL_DFS) == O.clique_count(g, k, threads=8), (name, k)
+    kmax = {"er": 4, "sbm": 5}.get(name, 5)
+    for k in range(3, kmax + 1):
+        assert np.array_equal(dm.count_motifs(h, k, sched=dm.DM_IMPL_DFS), O.motif_count(g, k, threads=8)), (name, k)
+
+
+def test_dfs_ablation_closed_forms_and_options():
+    h = dm.load_graph(gg.complete(24))
+    for k in (1, 2, 3, 9, 12, 16):
+        assert dm.count_cliques(h, k, sched=dm.DM_IMPL_DFS) == math.comb(24, k), k
+    parts = [3] * 300  # out-degrees up to 897
+    assert dm.count_cliques(dm.load_graph(gg.complete_multipartite(parts)), 4, sched=dm.DM_IMPL_DFS) == _esym(parts, 4)
+    hs = dm.load_graph(gg.star(300))
+    exp = np.zeros(6, np.uint64)
+    exp[int(np.nonzero(O.motif_brute(gg.star(3), 4))[0][0])] = math.comb(300, 3)
+    assert np.array_equal(dm.count_motifs(hs, 4, sched=dm.DM_IMPL_DFS | dm.DM_NO_DONATION), exp)
+    with pytest.raises(dm.DMError) as e:
+        dm.count_cliques(h, 17, sched=dm.DM_IMPL_DFS)
+    assert e.value.status == dm.DM_E_K
+    for kw in (dict(roots=np.arange(5)), dict(chunk=0, sched=dm.DM_IMPL_DFS | dm.DM_SCHED_AUTOTUNE)):
+        with pytest.raises(dm.DMError) as e:
+            dm.count_cliques(h, 4, **dict(dict(sched=dm.DM_IMPL_DFS), **kw))
+        assert e.value.status == dm.DM_E_ARG
