@@ -48,6 +48,8 @@ def _load():
     L.or_num_connected_labelled.argtypes = [ctypes.c_int]
     L.or_class_of_code.restype = ctypes.c_int
     L.or_class_of_code.argtypes = [ctypes.c_int, u32]
+    L.or_canon_methods_agree.restype = ctypes.c_int
+    L.or_canon_methods_agree.argtypes = [ctypes.c_int]
     L.or_clique_brute.restype = ctypes.c_int
     L.or_clique_brute.argtypes = [i32, vp, vp, ctypes.c_int, vp, vp]
     L.or_motif_brute.restype = ctypes.c_int
@@ -106,6 +108,12 @@ def class_canon(k: int) -> np.ndarray:
 
 def num_connected_labelled(k: int) -> int:
     return int(_load().or_num_connected_labelled(k))
+
+
+def canon_methods_agree(k: int) -> bool:
+    """The orbit-labelling method (used for k = 7) reproduces the per-code
+    minimum over all k! relabellings on every code on k <= 6 vertices."""
+    return _load().or_canon_methods_agree(k) == 1
 
 
 def class_of_code(k: int, code: int) -> int:

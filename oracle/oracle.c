@@ -56,8 +56,9 @@
 #include <string.h>
 #include <time.h>
 
-#define OR_MAXK 8          /* motif classification up to k = 8 (table 2^27 for k=8 not built) */
-#define OR_MAX_MOTIF_K 6   /* class tables are built for k <= 6 */
+#define OR_MAXK 8          /* vertex arrays sized for up to 8 traversal vertices */
+#define OR_MAX_MOTIF_K 7   /* class tables are built for k <= 7 */
+#define OR_MAX_CLASSES 853 /* classes of connected graphs on 7 vertices */
 
 /* ====================================================================== */
 /* canonical codes                                                         */
@@ -148,6 +149,56 @@ static int cmp_canon(const void* a, const void* b) {
     return x < y ? -1 : (x > y ? 1 : 0);
 }
 
+/* canonical code of every connected code, by one of two methods:
+   - per code: the minimum over all k! relabellings (or_canon);
+   - by orbits: codes are visited in increasing order; the first connected
+     code not yet labelled is the smallest member of its orbit (every smaller
+     code is labelled already, and relabelling maps an orbit onto itself), so
+     all k! relabellings of it are labelled with it.
+   The second visits each class once instead of each code, which is what
+   makes k = 7 (2^21 codes, 853 classes) affordable.  canon_of[c] =
+   0xffffffff for disconnected codes; returns the number of connected codes. */
+static int64_t canon_table(int k, uint32_t* canon_of, int by_orbits) {
+    const uint32_t ncodes = 1u << (k * (k - 1) / 2);
+    int64_t n_conn = 0;
+    if (!by_orbits) {
+        for (uint32_t c = 0; c < ncodes; ++c) {
+            if (!connected_code(k, c)) { canon_of[c] = 0xffffffffu; continue; }
+            n_conn++;
+            canon_of[c] = or_canon(k, c);
+        }
+        return n_conn;
+    }
+    const uint32_t unset = 0xfffffffeu;
+    for (uint32_t c = 0; c < ncodes; ++c) canon_of[c] = unset;
+    for (uint32_t c = 0; c < ncodes; ++c) {
+        if (canon_of[c] != unset) continue;
+        if (!connected_code(k, c)) { canon_of[c] = 0xffffffffu; continue; }
+        unsigned char adj[OR_MAXK][OR_MAXK];
+        adj_from_code(k, c, adj);
+        int p[OR_MAXK];
+        for (int i = 0; i < k; ++i) p[i] = i;
+        do {
+            uint32_t d = 0;
+            for (int i = 1; i < k; ++i)
+                for (int t = 0; t < i; ++t)
+                    if (adj[t][i]) {
+                        int a = p[t], b = p[i];
+                        d |= 1u << (a < b ? pair_bit(a, b) : pair_bit(b, a));
+                    }
+            canon_of[d] = c;
+        } while (next_perm(p, k));
+    }
+    for (uint32_t c = 0; c < ncodes; ++c)
+        if (canon_of[c] != 0xffffffffu) n_conn++;
+    return n_conn;
+}
+
+static int cmp_u32(const void* a, const void* b) {
+    uint32_t x = *(const uint32_t*)a, y = *(const uint32_t*)b;
+    return x < y ? -1 : (x > y ? 1 : 0);
+}
+
 static const class_info* classes(int k) {
     if (k < 1 || k > OR_MAX_MOTIF_K) return NULL;
     pthread_mutex_lock(&g_cls_lock);
@@ -155,33 +206,53 @@ static const class_info* classes(int k) {
     if (!ci->ready) {
         uint32_t ncodes = 1u << (k * (k - 1) / 2);
         uint32_t* canon_of = (uint32_t*)malloc(sizeof(uint32_t) * ncodes);
+        ci->n_connected = canon_table(k, canon_of, k >= 7);
+        /* classes: the distinct canonical codes (each is its own canon) */
         uint32_t* uniq = (uint32_t*)malloc(sizeof(uint32_t) * ncodes);
         int nu = 0;
-        ci->n_connected = 0;
-        for (uint32_t c = 0; c < ncodes; ++c) {
-            if (!connected_code(k, c)) { canon_of[c] = 0xffffffffu; continue; }
-            ci->n_connected++;
-            uint32_t cc = or_canon(k, c);
-            canon_of[c] = cc;
-            if (cc == c) uniq[nu++] = cc; /* the minimum of an orbit is its own canon */
-        }
+        for (uint32_t c = 0; c < ncodes; ++c)
+            if (canon_of[c] == c) uniq[nu++] = c;
         qsort(uniq, (size_t)nu, sizeof(uint32_t), cmp_canon);
         ci->ncls = nu;
         ci->canon = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(nu > 0 ? nu : 1));
         memcpy(ci->canon, uniq, sizeof(uint32_t) * (size_t)nu);
+        /* canonical code -> class id, through a code-sorted copy */
+        typedef struct { uint32_t code; int16_t cls; } pair_t;
+        pair_t* byc = (pair_t*)malloc(sizeof(pair_t) * (size_t)(nu > 0 ? nu : 1));
+        for (int q = 0; q < nu; ++q) { byc[q].code = ci->canon[q]; byc[q].cls = (int16_t)q; }
+        qsort(byc, (size_t)nu, sizeof(pair_t), cmp_u32);  /* code is the first member */
         ci->class_of_code = (int16_t*)malloc(sizeof(int16_t) * ncodes);
         for (uint32_t c = 0; c < ncodes; ++c) {
             ci->class_of_code[c] = -1;
             if (canon_of[c] == 0xffffffffu) continue;
-            for (int q = 0; q < nu; ++q)
-                if (ci->canon[q] == canon_of[c]) { ci->class_of_code[c] = (int16_t)q; break; }
+            int lo = 0, hi = nu - 1;
+            while (lo < hi) {
+                int mid = (lo + hi) / 2;
+                if (byc[mid].code < canon_of[c]) lo = mid + 1; else hi = mid;
+            }
+            ci->class_of_code[c] = byc[lo].cls;
         }
+        free(byc);
         free(canon_of);
         free(uniq);
         ci->ready = 1;
     }
     pthread_mutex_unlock(&g_cls_lock);
     return ci;
+}
+
+/* 1 when the orbit method and the per-code minimum give the same canonical
+   code for every code on k vertices (k <= 6), 0 otherwise, -1 if unsupported */
+int or_canon_methods_agree(int k) {
+    if (k < 1 || k > 6) return -1;
+    uint32_t ncodes = 1u << (k * (k - 1) / 2);
+    uint32_t* a = (uint32_t*)malloc(sizeof(uint32_t) * ncodes);
+    uint32_t* b = (uint32_t*)malloc(sizeof(uint32_t) * ncodes);
+    int64_t na = canon_table(k, a, 0), nb = canon_table(k, b, 1);
+    int same = na == nb && memcmp(a, b, sizeof(uint32_t) * ncodes) == 0;
+    free(a);
+    free(b);
+    return same;
 }
 
 /* number of classes of connected graphs on k vertices, -1 if unsupported */
@@ -343,7 +414,7 @@ typedef struct {
     /* reduction */
     pthread_mutex_t lock;
     uint64_t total;
-    uint64_t counts[128];
+    uint64_t counts[OR_MAX_CLASSES];
     int overflow;
 } job_t;
 
@@ -544,7 +615,7 @@ typedef struct {
     int32_t* ext[OR_MAXK + 1];  /* extension list per depth */
     int32_t* blocked;           /* # of sub vertices adjacent to x, or in sub (n entries) */
     uint64_t leaves, nodes, reads;
-    uint64_t counts[128];       /* per class, the current root only */
+    uint64_t counts[OR_MAX_CLASSES]; /* per class, the current root only */
     int ovf;
     root_clock rc;
 } esu_ctx;

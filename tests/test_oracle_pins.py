@@ -60,7 +60,7 @@ def class_of_pattern(k, H):
 
 # ------------------------------------------------------------------ class tables
 
-@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6, 7])
 def test_class_counts_match_published_sequences(k):
     classes, labelled = _golden_counts()[k]
     assert O.num_classes(k) == classes
@@ -85,6 +85,56 @@ def test_classes_are_exactly_the_atlas_connected_graphs(k):
             prev = int(canon[q - 1])
             assert (bin(prev).count("1"), prev) < (bin(int(c)).count("1"), int(c))
     assert len(hit) == len(atlas)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6])
+def test_orbit_labelling_equals_per_code_minimum(k):
+    """The class table for k = 7 is built by labelling whole orbits; on every
+    code on k <= 6 vertices that method gives the per-code minimum."""
+    assert O.canon_methods_agree(k)
+
+
+def _wl(H):
+    return nx.weisfeiler_lehman_graph_hash(H, iterations=3)
+
+
+def test_k7_classes_are_exactly_the_atlas_connected_graphs():
+    """k = 7: the 853 classes are the 853 connected 7-vertex graphs of the
+    networkx atlas, one each (VF2 within Weisfeiler-Lehman hash buckets)."""
+    k = 7
+    atlas = [G for G in nx.graph_atlas_g() if G.number_of_nodes() == k and nx.is_connected(G)]
+    buckets = {}
+    for i, A in enumerate(atlas):
+        buckets.setdefault(_wl(A), []).append(i)
+    canon = O.class_canon(k)
+    assert len(canon) == len(atlas) == 853
+    hit = set()
+    for q, c in enumerate(canon):
+        H = graph_of_code(k, int(c))
+        matches = [i for i in buckets.get(_wl(H), []) if nx.is_isomorphic(H, atlas[i])]
+        assert len(matches) == 1, q
+        hit.add(matches[0])
+        if q:
+            prev = int(canon[q - 1])
+            assert (bin(prev).count("1"), prev) < (bin(int(c)).count("1"), int(c))
+    assert len(hit) == len(atlas)
+
+
+def test_k7_class_of_code_agrees_with_vf2():
+    k = 7
+    reps = [graph_of_code(k, int(c)) for c in O.class_canon(k)]
+    buckets = {}
+    for q, R in enumerate(reps):
+        buckets.setdefault(_wl(R), []).append(q)
+    rng = np.random.default_rng(107)
+    for code in rng.integers(0, 1 << 21, size=200):
+        code = int(code)
+        H = graph_of_code(k, code)
+        q = O.class_of_code(k, code)
+        if not nx.is_connected(H):
+            assert q == -1
+        else:
+            assert [r for r in buckets[_wl(H)] if nx.is_isomorphic(H, reps[r])] == [q]
 
 
 @pytest.mark.parametrize("k", [3, 4, 5])
@@ -297,6 +347,27 @@ def test_motif_k3_wedges_and_triangles(seed):
     assert c[wedge_cls] == wedges and c[tri_cls] == tri
 
 
+def test_motif_k7_classification_vf2_and_enumerators():
+    """k = 7 on an 11-vertex graph: every connected 7-subset is counted in the
+    class VF2 assigns it; brute force and ESU agree, and their total is the
+    number of connected 7-subsets."""
+    k = 7
+    g = gg.erdos_renyi(11, 24, 77)
+    G = to_nx(g)
+    reps = [graph_of_code(k, int(c)) for c in O.class_canon(k)]
+    buckets = {}
+    for q, R in enumerate(reps):
+        buckets.setdefault(_wl(R), []).append(q)
+    exp = np.zeros(len(reps), np.uint64)
+    for S in itertools.combinations(range(g.n), k):
+        H = G.subgraph(S)
+        if nx.is_connected(H):
+            exp[[q for q in buckets[_wl(H)] if nx.is_isomorphic(H, reps[q])][0]] += 1
+    assert exp.sum() > 100
+    assert np.array_equal(O.motif_brute(g, k), exp)
+    assert np.array_equal(O.motif_count(g, k), exp)
+
+
 @pytest.mark.parametrize("k", [3, 4, 5])
 def test_motif_brute_vs_vf2_classification(k):
     """Every connected k-subset is classified into the class VF2 says it is in."""
@@ -449,7 +520,7 @@ def test_budget_stops_a_heavy_root():
     assert list(done) == [False, True] and per[1].sum() == ml[1] == 1
 
 
-@pytest.mark.parametrize("k", [3, 4, 5])
+@pytest.mark.parametrize("k", [3, 4, 5, 6, 7])
 def test_motif_star_identity(k):
     """sum_v C(d_v, k-1) = sum_H c_H * sigma_H, sigma_H = #vertices adjacent to all others."""
     g = gg.erdos_renyi(120, 700, 9)
@@ -466,7 +537,7 @@ def test_motif_invariances():
     g = gg.erdos_renyi(60, 200, 2)
     h = gg.erdos_renyi(45, 180, 3)
     rng = np.random.default_rng(1)
-    for k in (3, 4, 5):
+    for k in (3, 4, 5, 7):
         a = O.motif_count(g, k)
         assert np.array_equal(a, O.motif_count(gg.relabel(g, rng.permutation(g.n)), k))
         u, _ = gg.disjoint_union([g, h])
@@ -481,7 +552,7 @@ def test_motif_invariances():
 def test_motif_sum_equals_connected_sets():
     g = gg.erdos_renyi(14, 30, 21)
     G = to_nx(g)
-    for k in (3, 4, 5, 6):
+    for k in (3, 4, 5, 6, 7):
         exp = sum(1 for S in itertools.combinations(range(g.n), k) if nx.is_connected(G.subgraph(S)))
         assert int(O.motif_count(g, k).sum()) == exp
 
