@@ -137,7 +137,7 @@ dm_status dm_graph_info(const dm_graph* g, int32_t* n, int64_t* nnz);
  */
 dm_status dm_count_cliques(dm_graph* g, int k, uint64_t* out_count, const dm_options* opt);
 
-/* Number of connected k-vertex classes: 2, 6, 21, 112 for k = 3..6; -1 otherwise. */
+/* Number of connected k-vertex classes: 2, 6, 21, 112, 853 for k = 3..7; -1 otherwise. */
 int dm_motif_num_classes(int k);
 
 /*
@@ -153,13 +153,23 @@ dm_status dm_motif_class_mask(int k, int cls, uint32_t* upper_tri_mask);
  * a traversal code c of 2^(k(k-1)/2 - 1) values (edge v0-v1 implied; vertex
  * v_i, i >= 2, stores its edges to v_0..v_{i-1} in bits i(i-1)/2 - 1 + t),
  * is the class id, or 0xFF when some v_i has no edge to its predecessors.
- * `len` must be at least 2^(k(k-1)/2 - 1).  Host-only; needs no GPU.
+ * `len` must be at least 2^(k(k-1)/2 - 1).  k in 3..6 (class ids fit a byte).
+ * Host-only; needs no GPU.  Errors: DM_E_K, DM_E_ARG, DM_E_BUFSZ.
  */
 dm_status dm_motif_class_table(int k, uint8_t* out, size_t len);
 
 /*
+ * The same dictionary with 16-bit class ids, for k in 3..7 (k = 7: 2^20
+ * entries, 853 classes); unreachable codes hold 0xFFFF.  This is the table
+ * the motif kernels read (Section IV-C gives its size for a pattern of k
+ * vertices as 2^(k(k-1)/2 - 1) codes).  Host-only; needs no GPU.
+ * Errors: DM_E_K, DM_E_ARG, DM_E_BUFSZ.
+ */
+dm_status dm_motif_class_table16(int k, uint16_t* out, size_t len);
+
+/*
  * Per-class counts of connected induced k-vertex subgraphs (Section IV-E,
- * motif counting; Alg. 4 right).  out_counts[cls] for cls < ncls(k); k in 3..6.
+ * motif counting; Alg. 4 right).  out_counts[cls] for cls < ncls(k); k in 3..7.
  * Each subgraph is enumerated once, from its lowest (degree, id) vertex (the
  * same root rule as cliques; per-root records and root lists use it).
  * Errors: DM_E_ARG, DM_E_K, DM_E_BUFSZ (out_len < ncls), DM_E_OVERFLOW,

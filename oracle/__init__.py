@@ -48,6 +48,8 @@ def _load():
     L.or_num_connected_labelled.argtypes = [ctypes.c_int]
     L.or_class_of_code.restype = ctypes.c_int
     L.or_class_of_code.argtypes = [ctypes.c_int, u32]
+    L.or_class_of_codes.restype = None
+    L.or_class_of_codes.argtypes = [ctypes.c_int, vp, i64, vp]
     L.or_canon_methods_agree.restype = ctypes.c_int
     L.or_canon_methods_agree.argtypes = [ctypes.c_int]
     L.or_clique_brute.restype = ctypes.c_int
@@ -119,6 +121,14 @@ def canon_methods_agree(k: int) -> bool:
 def class_of_code(k: int, code: int) -> int:
     """Class id of a full edge bitmap on k vertices, or -1 if disconnected."""
     return int(_load().or_class_of_code(k, code))
+
+
+def class_of_codes(k: int, codes) -> np.ndarray:
+    """class_of_code over an array of full edge bitmaps."""
+    c = np.ascontiguousarray(codes, dtype=np.int64)
+    out = np.empty(c.size, dtype=np.int64)
+    _load().or_class_of_codes(k, c.ctypes.data, c.size, out.ctypes.data)
+    return out
 
 
 def code_of(adj: np.ndarray) -> int:

@@ -281,6 +281,11 @@ int or_class_of_code(int k, uint32_t code) {
     return ci->class_of_code[code];
 }
 
+/* the same for an array of codes (out[i] = class of codes[i], or -1) */
+void or_class_of_codes(int k, const int64_t* codes, int64_t n, int64_t* out) {
+    for (int64_t i = 0; i < n; ++i) out[i] = or_class_of_code(k, (uint32_t)codes[i]);
+}
+
 /* ====================================================================== */
 /* graph helpers                                                           */
 /* ====================================================================== */

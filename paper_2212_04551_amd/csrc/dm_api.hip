@@ -66,7 +66,7 @@ namespace {
 struct ClassTables {
   int ncls = 0;
   std::vector<uint32_t> canon;   // class -> canonical full bitmap
-  std::vector<uint8_t> table;    // traversal code -> class (0xFF unreachable)
+  std::vector<uint16_t> table;   // traversal code -> class (kUnreachable: some v_i has no earlier neighbour)
 };
 
 inline int pair_index(int t, int i) { return i * (i - 1) / 2 + t; }  // t < i
@@ -152,7 +152,7 @@ ClassTables build_tables(int k) {
   for (int q = 0; q < T.ncls; ++q) id[reps[q]] = q;
   // traversal code t: full bitmap (t << 1) | 1 (edge v0-v1 implied)
   const uint32_t ntrav = 1u << (P - 1);
-  T.table.assign(ntrav, 0xFF);
+  T.table.assign(ntrav, kUnreachable);
   for (uint32_t t = 0; t < ntrav; ++t) {
     bool reach = true;
     for (int i = 2; i < k; ++i) {
@@ -161,7 +161,7 @@ ClassTables build_tables(int k) {
     }
     if (!reach) continue;
     const uint32_t full = (t << 1) | 1u;
-    T.table[t] = static_cast<uint8_t>(id.at(canon_of[full]));
+    T.table[t] = static_cast<uint16_t>(id.at(canon_of[full]));
   }
   return T;
 }
@@ -170,7 +170,7 @@ std::mutex g_tables_lock;
 ClassTables* g_tables[8] = {nullptr};
 
 const ClassTables* tables(int k) {
-  if (k < 3 || k > 6) return nullptr;
+  if (k < 3 || k > kMotifMaxK) return nullptr;
   std::lock_guard<std::mutex> lk(g_tables_lock);
   if (!g_tables[k]) g_tables[k] = new ClassTables(build_tables(k));
   return g_tables[k];
@@ -178,9 +178,9 @@ const ClassTables* tables(int k) {
 
 // device copies of the dictionary, per (device, k)
 std::mutex g_dev_tables_lock;
-std::map<std::pair<int, int>, uint8_t*> g_dev_tables;
+std::map<std::pair<int, int>, uint16_t*> g_dev_tables;
 
-hipError_t device_table(int k, uint8_t** out) {
+hipError_t device_table(int k, uint16_t** out) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
@@ -192,10 +192,11 @@ hipError_t device_table(int k, uint8_t** out) {
     return hipSuccess;
   }
   const ClassTables* T = tables(k);
-  uint8_t* p = nullptr;
-  e = hipMalloc(&p, T->table.size());
+  uint16_t* p = nullptr;
+  const size_t bytes = T->table.size() * sizeof(uint16_t);
+  e = hipMalloc(&p, bytes);
   if (e != hipSuccess) return e;
-  e = hipMemcpy(p, T->table.data(), T->table.size(), hipMemcpyHostToDevice);
+  e = hipMemcpy(p, T->table.data(), bytes, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     (void)hipFree(p);
     return e;
@@ -214,18 +215,28 @@ extern "C" int dm_motif_num_classes(int k) {
 
 extern "C" dm_status dm_motif_class_mask(int k, int cls, uint32_t* mask) {
   const ClassTables* T = tables(k);
-  if (!T) return fail(DM_E_K, "motif k must be in 3..6");
+  if (!T) return fail(DM_E_K, "motif k must be in 3..7");
   if (!mask || cls < 0 || cls >= T->ncls) return fail(DM_E_ARG, "class id out of range or null output");
   *mask = T->canon[cls];
   return DM_OK;
 }
 
 extern "C" dm_status dm_motif_class_table(int k, uint8_t* out, size_t len) {
-  const ClassTables* T = tables(k);
-  if (!T) return fail(DM_E_K, "motif k must be in 3..6");
+  const ClassTables* T = k <= 6 ? tables(k) : nullptr;
+  if (!T) return fail(DM_E_K, "8-bit class table: k must be in 3..6");
   if (!out) return fail(DM_E_ARG, "null output");
   if (len < T->table.size()) return fail(DM_E_BUFSZ, "table needs 2^(k(k-1)/2-1) bytes");
-  std::memcpy(out, T->table.data(), T->table.size());
+  for (size_t i = 0; i < T->table.size(); ++i)
+    out[i] = T->table[i] == kUnreachable ? 0xFF : static_cast<uint8_t>(T->table[i]);
+  return DM_OK;
+}
+
+extern "C" dm_status dm_motif_class_table16(int k, uint16_t* out, size_t len) {
+  const ClassTables* T = tables(k);
+  if (!T) return fail(DM_E_K, "motif k must be in 3..7");
+  if (!out) return fail(DM_E_ARG, "null output");
+  if (len < T->table.size()) return fail(DM_E_BUFSZ, "table needs 2^(k(k-1)/2-1) entries");
+  std::memcpy(out, T->table.data(), T->table.size() * sizeof(uint16_t));
   return DM_OK;
 }
 
@@ -802,14 +813,14 @@ dm_status prepare_clique(dm_graph* g, int k, const Opt& o, hipStream_t s, const 
 dm_status prepare_motif(dm_graph* g, int k, const Opt& o, hipStream_t s, const int32_t* root_graph, int ngraphs,
                         Prepared* P) {
   const ClassTables* T = tables(k);
-  uint8_t* dtab = nullptr;
+  uint16_t* dtab = nullptr;
   HIP_OR_RETURN(device_table(k, &dtab), "class table upload");
   dm_status st = ensure_ranked(g, s);
   if (st != DM_OK) return st;
   const int dmax = g->dmax > 0 ? g->dmax : 1;
   const size_t lds = motif_lds_bytes(k, T->ncls);
   int per_cu = 0;
-  HIP_OR_RETURN(motif_occupancy(lds, &per_cu), "occupancy");
+  HIP_OR_RETURN(motif_occupancy(k, lds, &per_cu), "occupancy");
   if (per_cu < 1) per_cu = 1;
   if (per_cu > 16) per_cu = 16;  // the extension stacks live in global memory; bound the footprint
   if (o.waves_per_cu && static_cast<int>(o.waves_per_cu) < per_cu) per_cu = static_cast<int>(o.waves_per_cu);
@@ -990,7 +1001,7 @@ dm_status run_dfs(dm_graph* g, int op, int k, const Opt& o, hipStream_t s, uint6
     dmax = g->ddmax > 0 ? g->ddmax : 1;
     A.lane_stride = static_cast<int64_t>(k > 3 ? k - 3 : 1) * dmax;
   } else {
-    uint8_t* dtab = nullptr;
+    uint16_t* dtab = nullptr;
     HIP_OR_RETURN(device_table(k, &dtab), "class table upload");
     dm_status st = ensure_ranked(g, s);
     if (st != DM_OK) return st;
@@ -1065,7 +1076,7 @@ extern "C" dm_status dm_count_cliques(dm_graph* g, int k, uint64_t* out_count, c
 extern "C" dm_status dm_count_motifs(dm_graph* g, int k, uint64_t* out_counts, size_t out_len, const dm_options* opt) {
   if (!g || !out_counts) return fail(DM_E_ARG, "null graph or output");
   const ClassTables* T = tables(k);
-  if (!T) return fail(DM_E_K, "motif k must be in 3..6");
+  if (!T) return fail(DM_E_K, "motif k must be in 3..7");
   if (out_len < static_cast<size_t>(T->ncls)) return fail(DM_E_BUFSZ, "out_len < number of classes");
   Opt o;
   dm_status st = read_opt(opt, &o);
@@ -1285,7 +1296,7 @@ extern "C" dm_status dm_batch(dm_graph* const* gs, int32_t num_graphs, int op, i
     if (k < 1 || k > kMaxK) return fail(DM_E_K, "clique k must be in 1..32");
   } else {
     const ClassTables* T = tables(k);
-    if (!T) return fail(DM_E_K, "motif k must be in 3..6");
+    if (!T) return fail(DM_E_K, "motif k must be in 3..7");
     width = T->ncls;
   }
   if (out_len < static_cast<size_t>(num_graphs) * width) return fail(DM_E_BUFSZ, "out_len < num_graphs * width");

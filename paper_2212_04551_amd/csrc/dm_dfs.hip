@@ -154,7 +154,7 @@ __global__ void __launch_bounds__(64) dfs_motif_kernel(DfsArgs A) {
       if (s == k - 1) {
         const int c = code[s] | (s >= 2 ? static_cast<int>(mx << (s * (s - 1) / 2 - 1)) : 0);
         const int cls = A.table[c];
-        if (cls == 0xFF) atomicOr(A.flags + 1, 2);
+        if (cls == kUnreachable) atomicOr(A.flags + 1, 2);
         else atomicAdd(&cnt[cls], 1ull);
         continue;
       }

@@ -14,6 +14,12 @@ namespace dm {
 constexpr int kMlpNet = 4 * 64 + 64 + 64 * 64 + 64 + 64 + 1;  // 4545 weights
 constexpr int kMlpBlob = kMlpNet + 8;                          // + feature mean[4], std[4]
 
+// Largest motif size: the canonical-relabeling dictionary of k = 7 has
+// 2^20 entries of 16-bit class ids (853 classes); entries whose code some
+// v_i reaches with no edge to its predecessors hold kUnreachable.
+constexpr int kMotifMaxK = 7;
+constexpr uint16_t kUnreachable = 0xFFFF;
+
 // Roots with at most this many out-neighbours keep their bitmap rows in LDS;
 // wider roots read them from the graph's row cache or a per-wave global region.
 constexpr int kCliqueLocalRows = 128;
@@ -48,7 +54,7 @@ struct MotifArgs {
   int k;
   int dmax;                // largest degree
   int ncls;
-  const uint8_t* table;    // canonical-relabeling dictionary, 2^(k(k-1)/2-1) entries
+  const uint16_t* table;   // canonical-relabeling dictionary, 2^(k(k-1)/2-1) entries
   unsigned long long* out; // [graphs][ncls]
   const int32_t* root_graph;
   int* flags;
@@ -78,7 +84,7 @@ struct DfsArgs {
   int32_t* stack;          // per-lane stacks, lane_stride entries each
   uint8_t* masks;          // motifs: mask byte per stack entry
   int64_t lane_stride;
-  const uint8_t* table;    // motifs: canonical-relabeling dictionary
+  const uint16_t* table;   // motifs: canonical-relabeling dictionary
   int ncls;
   int64_t level_off[kDfsMaxK + 1];  // motifs: start of level s in a lane's stack
   int64_t level_cap[kDfsMaxK + 1];
@@ -93,7 +99,7 @@ hipError_t clique_occupancy(size_t lds_bytes, int* blocks_per_cu);
 
 hipError_t launch_motif(const MotifArgs& a, int grid, size_t lds_bytes, hipStream_t s);
 size_t motif_lds_bytes(int k, int ncls);
-hipError_t motif_occupancy(size_t lds_bytes, int* blocks_per_cu);
+hipError_t motif_occupancy(int k, size_t lds_bytes, int* blocks_per_cu);
 
 // graph preparation
 hipError_t launch_validate(const int64_t* rp, const int32_t* col, int32_t n, int64_t nnz, int* flag,

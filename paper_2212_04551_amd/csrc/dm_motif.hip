@@ -58,10 +58,11 @@ namespace dm {
 
 namespace {
 
-constexpr int kMotifMaxK = 7;
 constexpr int kSuf = kMotifMaxK + 1;
 
-constexpr int kBins = 16;  // masks of a (k-2)-traversal entry, k <= 6
+// kBins (a template parameter below) = the number of masks an entry of a
+// (k-2)-traversal's list can have, 2^(k-2): 16 for k <= 6 and 32 for k = 7
+// (the kernel is instantiated for both).
 // A leaf-level range is donated only when this many entries are untried: the
 // taker re-extends the whole prefix first.
 constexpr int kLeafDonateMin = 128;
@@ -114,6 +115,7 @@ struct MotifLds {
 
 __device__ __forceinline__ int off_of(int i) { return i * (i - 1) / 2 - 1; }  // bitmap field of v_i, i >= 2
 
+template <int kBins>
 __device__ MotifLds carve(unsigned char* smem, int ncls) {
   MotifLds L;
   size_t off = 0;
@@ -269,6 +271,7 @@ __device__ void extend_level(const MotifArgs& A, const MotifLds& L, MotifWave& M
 // Count every leaf below the traversal tr (|tr| = s = k-2) whose x is an entry
 // of [lo, hi) of tr's list.  Between slices of 64 entries the untried part of
 // the range may be donated (a task at depth s).  Returns the final hi.
+template <int kBins>
 __device__ __forceinline__ int leaf_level(const MotifArgs& A, const MotifLds& L, MotifWave& MW, int s, int lo, int hi,
                           const Task& t, int wave_gid, uint64_t& nodes_l, uint64_t& leaves_l, uint64_t& reads_l) {
   const int lane = lane_id();
@@ -489,7 +492,7 @@ __device__ __forceinline__ int leaf_level(const MotifArgs& A, const MotifLds& L,
   const int fy = off_of(s + 1);
   auto add_class = [&](int code, uint64_t h) {
     const int cls = A.table[code];
-    if (cls == 0xFF) {
+    if (cls == kUnreachable) {
       atomicOr(A.flags + 1, 2);
     } else {
       const unsigned long long old = atomicAdd(&L.cnt[cls], static_cast<unsigned long long>(h));
@@ -533,6 +536,7 @@ __device__ __forceinline__ int next_canonical(const MotifArgs& A, const MotifLds
   return -1;
 }
 
+template <int kBins>
 __device__ __forceinline__ void run_task(const MotifArgs& A, const MotifLds& L, MotifWave& MW, const Task& t, int wave_gid) {
   const int lane = lane_id();
   const int k = A.k;
@@ -581,7 +585,7 @@ __device__ __forceinline__ void run_task(const MotifArgs& A, const MotifLds& L, 
   const int hi0 = t.hi < L.esize[s0] ? t.hi : L.esize[s0];
 
   if (s0 == k - 2) {
-    leaf_level(A, L, MW, s0, t.lo, hi0, t, wave_gid, nodes_l, leaves_l, reads_l);
+    leaf_level<kBins>(A, L, MW, s0, t.lo, hi0, t, wave_gid, nodes_l, leaves_l, reads_l);
   } else if (hi0 > t.lo) {
     int s = s0;
     if (lane == 0) { L.cursor[s] = t.lo; L.endv[s] = hi0; }
@@ -602,7 +606,7 @@ __device__ __forceinline__ void run_task(const MotifArgs& A, const MotifLds& L, 
       }
       extend_level(A, L, MW, s, idx, x);
       if (s + 1 == k - 2) {
-        leaf_level(A, L, MW, s + 1, 0, L.esize[s + 1], t, wave_gid, nodes_l, leaves_l, reads_l);
+        leaf_level<kBins>(A, L, MW, s + 1, 0, L.esize[s + 1], t, wave_gid, nodes_l, leaves_l, reads_l);
       } else {
         ++s;
         if (lane == 0) { L.cursor[s] = 0; L.endv[s] = L.esize[s]; }
@@ -642,11 +646,12 @@ __device__ __forceinline__ void run_task(const MotifArgs& A, const MotifLds& L, 
 }
 
 // 4 waves per SIMD (128 VGPRs): enough waves to cover the lookups' latency
+template <int kBins>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) motif_kernel(MotifArgs A) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int lane = lane_id();
   const int wave_gid = blockIdx.x;
-  MotifLds L = carve(smem, A.ncls);
+  MotifLds L = carve<kBins>(smem, A.ncls);
   MotifWave MW;
   MW.cur_g = -1;
   MW.ovf = 0;
@@ -663,7 +668,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4)))
   sched_begin(A.S, it);
   Task t;
   while (sched_next(A.S, it, wave_gid, L.tr, &t)) {
-    run_task(A, L, MW, t, wave_gid);
+    run_task<kBins>(A, L, MW, t, wave_gid);
     MW.tasks++;
   }
   sched_end(A.S);
@@ -682,10 +687,12 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4)))
 
 }  // namespace
 
+int motif_bins(int k) { return k <= 6 ? 16 : 32; }
+
 size_t motif_lds_bytes(int k, int ncls) {
-  (void)k;
+  const size_t nb = static_cast<size_t>(motif_bins(k));
   auto a16 = [](size_t x) { return (x + 15) & ~static_cast<size_t>(15); };
-  size_t off = a16(static_cast<size_t>(ncls) * 8) + a16(kBins * kBins * 8) + a16(kBins * 8) + a16(2 * kBins * 4);
+  size_t off = a16(static_cast<size_t>(ncls) * 8) + a16(nb * nb * 8) + a16(nb * 8) + a16(2 * nb * 4);
   off += a16((kWave + 1) * 8) + a16(kWave * 8) + a16(kWave * 4);
   off += 2 * a16(kSuf * 4) + a16(kSuf * kSuf * 4) + 3 * a16(kSuf * 4);
   off += a16(kLeafLds * 4) + a16(kLeafLds) + a16(kFilterWords * 4) + 16 + a16(kWave * 4);
@@ -693,12 +700,17 @@ size_t motif_lds_bytes(int k, int ncls) {
   return off;
 }
 
-hipError_t motif_occupancy(size_t lds_bytes, int* blocks_per_cu) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, motif_kernel, 64, lds_bytes);
+hipError_t motif_occupancy(int k, size_t lds_bytes, int* blocks_per_cu) {
+  return motif_bins(k) == 16
+             ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, motif_kernel<16>, 64, lds_bytes)
+             : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, motif_kernel<32>, 64, lds_bytes);
 }
 
 hipError_t launch_motif(const MotifArgs& a, int grid, size_t lds_bytes, hipStream_t s) {
-  hipLaunchKernelGGL(motif_kernel, dim3(grid), dim3(64), lds_bytes, s, a);
+  if (motif_bins(a.k) == 16)
+    hipLaunchKernelGGL(motif_kernel<16>, dim3(grid), dim3(64), lds_bytes, s, a);
+  else
+    hipLaunchKernelGGL(motif_kernel<32>, dim3(grid), dim3(64), lds_bytes, s, a);
   return hipGetLastError();
 }
 

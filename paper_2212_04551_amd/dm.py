@@ -32,7 +32,8 @@ DM_MLP_NPARAMS = DM_MLP_NET + 8                     # + feature mean[4], std[4]
 EXPORTS = [
     "dm_load_csr", "dm_free", "dm_graph_info", "dm_count_cliques",
     "dm_motif_num_classes",
-    "dm_motif_class_mask", "dm_motif_class_table", "dm_count_motifs", "dm_batch", "dm_strerror",
+    "dm_motif_class_mask", "dm_motif_class_table", "dm_motif_class_table16", "dm_count_motifs",
+    "dm_batch", "dm_strerror",
     "dm_last_error", "dm_features", "dm_mlp_init", "dm_mlp_fit_normalizer", "dm_mlp_forward", "dm_mlp_targets",
     "dm_mlp_loss_grad", "dm_mlp_adam_step", "dm_mlp_train", "dm_autotune",
 ]
@@ -95,6 +96,8 @@ def lib():
     L.dm_motif_class_mask.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(u32)]
     L.dm_motif_class_table.restype = ctypes.c_int
     L.dm_motif_class_table.argtypes = [ctypes.c_int, vp, ctypes.c_size_t]
+    L.dm_motif_class_table16.restype = ctypes.c_int
+    L.dm_motif_class_table16.argtypes = [ctypes.c_int, vp, ctypes.c_size_t]
     L.dm_count_motifs.restype = ctypes.c_int
     L.dm_count_motifs.argtypes = [vp, ctypes.c_int, vp, ctypes.c_size_t, ctypes.POINTER(dm_options)]
     L.dm_batch.restype = ctypes.c_int
@@ -261,6 +264,13 @@ def motif_class_table(k: int) -> np.ndarray:
     n = 1 << (k * (k - 1) // 2 - 1)
     out = np.zeros(n, dtype=np.uint8)
     _check(lib().dm_motif_class_table(k, out.ctypes.data, n))
+    return out
+
+
+def motif_class_table16(k: int) -> np.ndarray:
+    n = 1 << (k * (k - 1) // 2 - 1)
+    out = np.zeros(n, dtype=np.uint16)
+    _check(lib().dm_motif_class_table16(k, out.ctypes.data, n))
     return out
 
 

@@ -72,10 +72,37 @@ def test_dictionary_matches_oracle_on_every_code(k, reachable):
     assert hit == reachable
 
 
+@pytest.mark.parametrize("k", [3, 4, 5, 6, 7])
+def test_16bit_dictionary_matches_oracle_on_every_code(k):
+    """The 16-bit dictionary the kernels read (k = 7: 2^20 codes, 853
+    classes) against the oracle's class of every full bitmap (t<<1)|1;
+    for k <= 6 it equals the 8-bit table (0xFF -> 0xFFFF)."""
+    T = dm.motif_class_table16(k)
+    assert T.dtype == np.uint16 and T.size == 1 << (k * (k - 1) // 2 - 1)
+    assert dm.motif_num_classes(k) == O.num_classes(k)
+    canon = O.class_canon(k)
+    for c in range(0, len(canon), max(1, len(canon) // 64)):
+        assert dm.motif_class_mask(k, c) == int(canon[c])
+    t = np.arange(T.size, dtype=np.int64)
+    reach = np.ones(T.size, dtype=bool)
+    for i in range(2, k):
+        reach &= ((t >> (i * (i - 1) // 2 - 1)) & ((1 << i) - 1)) != 0
+    assert (T[~reach] == 0xFFFF).all()
+    exp = O.class_of_codes(k, (t[reach] << 1) | 1)
+    assert np.array_equal(T[reach].astype(np.int64), exp)
+    if k <= 6:
+        T8 = dm.motif_class_table(k)
+        assert np.array_equal(np.where(T8 == 0xFF, 0xFFFF, T8.astype(np.uint16)), T)
+
+
 def test_unsupported_k():
-    assert dm.motif_num_classes(2) == -1 and dm.motif_num_classes(7) == -1
+    assert dm.motif_num_classes(2) == -1 and dm.motif_num_classes(8) == -1
+    assert dm.motif_num_classes(7) == 853
     with pytest.raises(dm.DMError) as e:
         dm.motif_class_table(7)
+    assert e.value.status == dm.DM_E_K
+    with pytest.raises(dm.DMError) as e:
+        dm.motif_class_table16(8)
     assert e.value.status == dm.DM_E_K
     with pytest.raises(dm.DMError) as e:
         dm.motif_class_mask(4, 6)

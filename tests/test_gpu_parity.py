@@ -408,7 +408,7 @@ def test_error_paths():
         with pytest.raises(dm.DMError) as e:
             dm.count_cliques(h, bad_k)
         assert e.value.status == dm.DM_E_K
-    for bad_k in (2, 7):
+    for bad_k in (2, 8):
         with pytest.raises(dm.DMError) as e:
             dm.count_motifs(h, bad_k)
         assert e.value.status == dm.DM_E_K
