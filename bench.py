@@ -24,10 +24,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 KS = (3, 4, 5, 6, 7, 8)
-# HBM bytes of the k=8 clique_kernel launch from rocprofv3 (2.0 x FETCH_SIZE +
-# 1.0 x WRITE_SIZE, factors from a copy kernel of known size), valid only for
-# the kernel source they were taken on.
-TRAFFIC = {"source_sha": "d75f273089e93618", "bytes_per_launch": 2.0 * 771431.9 * 1024 + 410721.7 * 1024}
+# Counters of the k=8 clique_kernel launch on the benchmark graph, from
+# rocprofv3 --pmc passes over `bench.py --steps 1 --warmup 0 --no-cpu-baseline
+# --no-extras` (the profile named below): VALU wave instructions per launch
+# (SQ_INSTS_VALU) and HBM bytes per launch (FETCH_SIZE and WRITE_SIZE, each
+# scaled by what the counter reads for a device copy of known size).  Valid
+# only for the kernel source they were taken on.
+CLIQUE_K8 = {"source_sha": None, "valu_insts": None, "hbm_bytes": None,
+             "profile": "profiles/clique_kernel_cl1m_k8_counters.md"}
 
 
 def kernel_source_sha(kernel: str = "dm_clique.hip") -> str:
@@ -51,30 +55,64 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def cpu_info():
+    """Host CPU: logical CPUs, the CPUs this process may run on, the model."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    aff = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    return {"nproc": os.cpu_count() or 1, "affinity": aff, "model": model}
+
+
+# The GPU host's share of CPUs per GPU: the oracle never runs more threads.
+HOST_THREADS_CAP = 16
+
+
 def cpu_baseline(g, budget_s: float, seed: int = 0):
     """The oracle (plain rank-ordered backtracking) on a bounded sample: for each
     k, the roots of one seeded uniform permutation are enumerated in order for
-    budget/6 seconds of wall-clock time (threads abandon their current root at
-    the deadline; everything found until then is counted)."""
+    a fixed wall-clock slice (threads abandon their current root at the
+    deadline; everything found until then is counted).  Run on every CPU this
+    process may use (at most HOST_THREADS_CAP), then on one thread."""
     import oracle as O
 
-    threads = min(os.cpu_count() or 1, 16)
+    info = cpu_info()
+    threads = max(1, min(info["affinity"], HOST_THREADS_CAP))
     order = np.random.default_rng(seed).permutation(g.n).astype(np.int32)
-    per_k = budget_s / len(KS)
-    found, used, roots = 0, 0.0, {}
-    for k in KS:
-        f, started, el = O.clique_timed(g, k, order, threads, per_k)
-        found += f
-        used += el
-        roots[k] = started
-        log(f"cpu baseline k={k}: {f} cliques from {started} roots in {el:.2f}s")
+
+    def run(nthreads, per_k):
+        found, used, roots = 0, 0.0, {}
+        for k in KS:
+            f, started, el = O.clique_timed(g, k, order, nthreads, per_k)
+            found += f
+            used += el
+            roots[k] = started
+            log(f"cpu baseline ({nthreads} threads) k={k}: {f} cliques from {started} roots in {el:.2f}s")
+        return (found / used if used > 0 else 0.0), roots
+
+    multi_s = 0.8 * budget_s / len(KS)
+    single_s = 0.2 * budget_s / len(KS)
+    v_multi, roots_multi = run(threads, multi_s)
+    v_single, roots_single = run(1, single_s)
     return {
-        "value": found / used if used > 0 else 0.0,
+        "value": v_multi,
         "unit": "subgraphs/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": f"each k=3..8: roots of one seeded uniform permutation enumerated in order for {per_k:.1f}s "
-                  f"wall-clock on {threads} threads (roots begun per k: {roots}); same graph as the GPU run",
+        "sample": f"each k=3..8: roots of one seeded uniform permutation enumerated in order for {multi_s:.1f}s "
+                  f"wall-clock on {threads} threads (roots begun per k: {roots_multi}); same graph as the GPU run",
+        "single_thread_value": v_single,
+        "single_thread_sample": f"the same permutation, {single_s:.1f}s per k on 1 thread (roots begun: {roots_single})",
+        "nproc": info["nproc"],
+        "affinity_cpus": info["affinity"],
+        "cpu_model": info["model"],
+        "threads_note": f"all CPUs this process may use, capped at {HOST_THREADS_CAP} (the GPU host's CPU share per GPU)",
     }
 
 
@@ -220,35 +258,69 @@ def wl_cl1m_clique(args):
     total = sum(counts.values())
     value = total / (ms_per_step / 1e3)
 
-    # dominant launch: k = 8.  Its algorithmic work is one 64-bit AND + one
-    # popcount (4 32-bit ops) per tree node, i.e. per j-clique for j = 2..7;
-    # the j-clique counts are the step's own outputs (j = 2: m).
+    # dominant launch: k = 8.  Its roofline is the VALU issue rate: the
+    # launch's VALU instructions (SQ_INSTS_VALU, counted by rocprofv3 on this
+    # kernel source and workload) x 64 lanes / the launch's HIP-event time.
     kmax = max(KS)
     per_k_ms = {k: float(np.mean([a.elapsed_time(b) for a, b in events[k]])) for k in KS}
-    nodes = g.m + sum(counts[j] for j in range(3, kmax))
-    ops = 4.0 * nodes
-    achieved = ops / (per_k_ms[kmax] / 1e3) / 1e12
+    t8 = per_k_ms[kmax] / 1e3
     out = base_record(value, ms_per_step, args.steps, args.warmup,
                       "k-clique counting k=3..8, Chung-Lu n=1e6 m=2e7 gamma=2.1 wmax=1e4 seed 0, "
                       "degree-ordered DAG, plain persistent kernel",
                       {"n": g.n, "m": g.m, "k": list(KS), "counts": {str(k): int(v) for k, v in counts.items()},
                        "per_k_ms": per_k_ms, "schedule": "plain"})
-    out["roofline"] = {
-        "bound": "alu",
-        "kernel": "clique_kernel (k=8 launch)",
-        "achieved": achieved,
-        "peak": ALU_PEAK_TOPS,
-        "unit": "TOP/s",
-        "frac": achieved / ALU_PEAK_TOPS,
-        "traffic": TRAFFIC["bytes_per_launch"] if kernel_source_sha() == TRAFFIC["source_sha"] else None,
-        "work": f"4 int32 ops x {nodes} tree nodes",
+    fresh = kernel_source_sha() == CLIQUE_K8["source_sha"]
+    # Section IV's byte model (each tree node reads its newest vertex's row
+    # offsets and out-list once), as a lower bound from the step's own counts:
+    # nodes = every j-clique for j = 1..7 (j = 1: n, j = 2: m), and an out-list
+    # of a j-clique's newest vertex holds at least its extensions, so the list
+    # entries read are at least the (j+1)-clique count.
+    nodes = g.n + g.m + sum(counts[j] for j in range(3, kmax))
+    entries = g.m + sum(counts[j] for j in range(3, kmax + 1))
+    b_model = 8.0 * nodes + 4.0 * entries
+    byte_model = {
+        "bytes_lower_bound": b_model, "achieved_GBs": b_model / t8 / 1e9,
+        "frac_of_hbm_peak": b_model / t8 / 1e9 / HBM_PEAK_GBS,
+        "why_not_binding": "each root's bitmap rows are built once (row cache) and every deeper level is an AND + "
+                           "popcount over rows held in LDS or L2, so the adjacency reads the model charges per node "
+                           "never reach HBM; the counted HBM traffic is the 'traffic' field",
     }
+    if fresh:
+        lane_ops = 64.0 * CLIQUE_K8["valu_insts"]
+        achieved = lane_ops / t8 / 1e12
+        out["roofline"] = {
+            "bound": "alu", "kernel": "clique_kernel (k=8 launch)",
+            "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TOP/s", "frac": achieved / ALU_PEAK_TOPS,
+            "traffic": CLIQUE_K8["hbm_bytes"],
+            "basis": f"SQ_INSTS_VALU = {CLIQUE_K8['valu_insts']:.4g} wave instructions per launch x 64 lanes "
+                     f"({CLIQUE_K8['profile']}) / this run's HIP-event launch time {per_k_ms[kmax]:.1f} ms",
+            "byte_model": byte_model,
+        }
+    else:
+        # counters stale: the kernel changed since they were taken; fall back
+        # to a stated model of 4 VALU ops (64-bit AND + popcount) per j-clique
+        # node, j = 2..7, and no traffic figure
+        ops = 4.0 * (nodes - g.n)
+        achieved = ops / t8 / 1e12
+        out["roofline"] = {
+            "bound": "alu", "kernel": "clique_kernel (k=8 launch)",
+            "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TOP/s", "frac": achieved / ALU_PEAK_TOPS,
+            "traffic": None,
+            "basis": "model (counters stale for this kernel source): 4 int32 ops x j-clique nodes, j = 2..7",
+            "byte_model": byte_model,
+        }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, args.cpu_budget)
+    if not args.no_extras:
+        del rp, col
+        torch.cuda.empty_cache()
+        out["configs"] = extra_configs(args)
     return out
 
 
-def wl_er516_motif(args):
+def measure_er516(args):
+    """Induced 4-motifs on G(516, 1200) seed 0, plain: per-call time including
+    the device-to-device load of the CSR (launch-latency bound)."""
     import torch
     from paper_2212_04551_amd import dm
     from paper_2212_04551_amd import graphgen as gg
@@ -263,10 +335,18 @@ def wl_er516_motif(args):
         h.close()
         return c
 
-    c, ms = timed_steps(step, max(args.steps, 20), args.warmup, "er516")
-    return base_record(int(c.sum()) / (ms / 1e3), ms, max(args.steps, 20), args.warmup,
+    steps = max(args.steps, 20)
+    c, ms = timed_steps(step, steps, max(args.warmup, 1), "er516")
+    return {"value": int(c.sum()) / (ms / 1e3), "unit": "subgraphs/s", "ms_per_call": ms, "calls": steps,
+            "subgraphs": int(c.sum()), "counts": [int(x) for x in c], "schedule": "plain",
+            "note": "launch-latency bound: 35k subgraphs per call, load of the CSR included"}
+
+
+def wl_er516_motif(args):
+    r = measure_er516(args)
+    return base_record(r["value"], r["ms_per_call"], r["calls"], args.warmup,
                        "induced 4-motif counting, G(n=516, m=1200) seed 0, plain",
-                       {"counts": [int(x) for x in c], "note": "launch-latency bound: 35k subgraphs per step"})
+                       {"counts": r["counts"], "note": r["note"]})
 
 
 def wl_cl100k_learned(args):
@@ -382,75 +462,188 @@ def wl_cl100k_motif_sample(args):
     return out
 
 
-def wl_batch4096(args):
-    import torch
+def measure_batch4096(args, steps):
+    """Batched induced 5-motifs over 4096 graphs: the autotuned captured
+    batch launch against one plain call per graph (both warm: every graph's
+    rank-renamed copy and the batch's union exist before timing)."""
     from paper_2212_04551_amd import dm
     from paper_2212_04551_amd import graphgen as gg
 
     t0 = time.perf_counter()
     graphs = [gg.batch_graph(i) for i in range(4096)]
-    calib = [gg.batch_graph(4096 + i) for i in range(512)]
+    calib = [gg.batch_graph(4096 + i) for i in range(256)]
     hs = [dm.load_graph(g) for g in graphs]
     hc = [dm.load_graph(g) for g in calib]
-    log(f"4096 + 512 graphs generated and loaded in {time.perf_counter() - t0:.1f}s; "
+    log(f"4096 + 256 graphs generated and loaded in {time.perf_counter() - t0:.1f}s; "
         f"n total {sum(g.n for g in graphs)}, m total {sum(g.m for g in graphs)}")
     t1 = time.perf_counter()
     tune = dm.autotune(hc, dm.DM_OP_MOTIF, 5)
     t_tune = time.perf_counter() - t1
-    log(f"autotuned on 512 calibration graphs in {t_tune:.1f}s: {tune}")
+    log(f"autotuned on 256 calibration graphs (seeds 4096..4351) in {t_tune:.1f}s: {tune}")
+    t2 = time.perf_counter()
+    first = dm.batch(hs, dm.DM_OP_MOTIF, 5, sched=dm.DM_SCHED_AUTOTUNE)  # builds the union, captures the launch
+    t_setup = time.perf_counter() - t2
+    cb, ms_batch = timed_steps(lambda: dm.batch(hs, dm.DM_OP_MOTIF, 5, sched=dm.DM_SCHED_AUTOTUNE),
+                               steps, 1, "batch autotuned")
+    cbu, ms_untuned = timed_steps(lambda: dm.batch(hs, dm.DM_OP_MOTIF, 5), steps, 1, "batch untuned")
 
     def plain():
         return np.stack([dm.count_motifs(h, 5) for h in hs])
 
-    t2 = time.perf_counter()
-    first = dm.batch(hs, dm.DM_OP_MOTIF, 5, sched=dm.DM_SCHED_AUTOTUNE)  # builds union + captures the graph
-    t_setup = time.perf_counter() - t2
-    cb, ms_batch = timed_steps(lambda: dm.batch(hs, dm.DM_OP_MOTIF, 5, sched=dm.DM_SCHED_AUTOTUNE),
-                               args.steps, args.warmup, "batch autotuned")
-    cpl, ms_plain = timed_steps(plain, 1, 0, "plain per-graph")
-    assert np.array_equal(cb, cpl) and np.array_equal(first, cb), "batch counts differ from per-graph counts"
-    cbu, ms_batch_untuned = timed_steps(lambda: dm.batch(hs, dm.DM_OP_MOTIF, 5), args.steps, args.warmup,
-                                        "batch untuned")
+    cpl, ms_plain = timed_steps(plain, 1, 1, "plain per-graph")
+    assert np.array_equal(cb, cpl) and np.array_equal(first, cb) and np.array_equal(cbu, cb), \
+        "batch counts differ from per-graph counts"
     n_sub = int(cb.sum())
-    return base_record(n_sub / (ms_batch / 1e3), ms_batch, args.steps, args.warmup,
+    return {"value": n_sub / (ms_batch / 1e3), "unit": "subgraphs/s", "subgraphs": n_sub,
+            "batched_autotuned_ms": ms_batch, "batched_untuned_ms": ms_untuned, "plain_per_graph_ms": ms_plain,
+            "plain_value": n_sub / (ms_plain / 1e3), "speedup_vs_plain": ms_plain / ms_batch,
+            "tuning": tune, "tune_s": t_tune, "tuned_on": "256 calibration graphs, seeds 4096..4351",
+            "first_call_setup_s": t_setup}
+
+
+def wl_batch4096(args):
+    r = measure_batch4096(args, args.steps)
+    return base_record(r["value"], r["batched_autotuned_ms"], args.steps, 1,
                        "batched induced 5-motif counting over 4096 graphs (n~U{20..2000}; even: G(n,m) d~U[4,16); "
                        "odd: BA m0~U{2..6}), one hipGraph-captured persistent launch, autotuned vs plain per-graph",
-                       {"subgraphs": n_sub, "plain_per_graph_ms": ms_plain, "batched_untuned_ms": ms_batch_untuned,
-                        "speedup_vs_plain": ms_plain / ms_batch, "tuning": tune, "tune_s": t_tune,
-                        "first_call_setup_s": t_setup})
+                       {k: v for k, v in r.items() if k not in ("value", "unit")})
 
 
-def wl_sbm_largek(args):
+def measure_sbm(args, steps):
+    """Large-k cliques (k = 10..12) on the 200 x 60 planted-community SBM,
+    seed 0: plain against learned ordering + autotuned knobs.  The MLP is
+    trained on tree sizes recorded on seeds 1..10 (k = 12); the knobs are
+    tuned per k on seed 11 with the learned queue.  Counts are 0 here, so the
+    throughput is tree nodes per second: the nodes the counting launch expands
+    in its wave DFS (wave_stats; nodes expanded inside the per-lane solver are
+    not counted, so this is a lower bound on the nodes it visits)."""
     import torch
     from paper_2212_04551_amd import dm
     from paper_2212_04551_amd import graphgen as gg
 
     make = lambda sd: gg.sbm(200, 60, 0.45, 0.0005, sd)
     model, tinfo = train_model(make, range(1, 11), "clique", 12, epochs=args.epochs, batch=1024)
+    hcal = dm.load_graph(make(11))
     g = make(0)
     h = dm.load_graph(g)
-    tune = dm.autotune([h], dm.DM_OP_CLIQUE, 12, sched=dm.DM_SCHED_LEARNED, mlp=model)
+    ws = torch.zeros(256 * 32 * 4, dtype=torch.int64, device="cuda")
     per = {}
     tot_plain = tot_learned = 0.0
     nodes_total = 0
     for k in (10, 11, 12):
-        # tree nodes below k: every j-clique, j = 1..k-1
-        nodes = sum(dm.count_cliques(h, j) for j in range(1, k))
-        cp, msp = timed_steps(lambda: dm.count_cliques(h, k), args.steps, args.warmup, f"sbm k={k} plain")
+        tune = dm.autotune([hcal], dm.DM_OP_CLIQUE, k, sched=dm.DM_SCHED_LEARNED, mlp=model)
+        ws.zero_()
+        cp, msp = timed_steps(lambda: dm.count_cliques(h, k, wave_stats=ws), steps, 1, f"sbm k={k} plain")
+        nodes = int(ws.view(-1, 4)[:, 2].sum().item())  # the last launch's (each launch overwrites its rows)
         cl, msl = timed_steps(lambda: dm.count_cliques(h, k, sched=dm.DM_SCHED_LEARNED | dm.DM_SCHED_AUTOTUNE,
-                                                       mlp=model), args.steps, args.warmup, f"sbm k={k} learned")
+                                                       mlp=model), steps, 1, f"sbm k={k} learned")
         assert cp == cl
-        per[str(k)] = {"count": int(cp), "tree_nodes": int(nodes), "plain_ms": msp, "learned_autotuned_ms": msl}
+        per[str(k)] = {"count": int(cp), "dfs_nodes": nodes, "plain_ms": msp, "learned_autotuned_ms": msl,
+                       "speedup": msp / msl, "tuning": tune}
         tot_plain += msp
         tot_learned += msl
         nodes_total += nodes
-    out = base_record(nodes_total / (tot_learned / 1e3), tot_learned, args.steps, args.warmup,
+    return {"value": nodes_total / (tot_learned / 1e3), "unit": "tree nodes/s (wave DFS nodes, lower bound)",
+            "plain_value": nodes_total / (tot_plain / 1e3), "speedup_vs_plain": tot_plain / tot_learned,
+            "per_k": per, "training": tinfo, "tuned_on": "seed 11 (training seeds 1..10, evaluation seed 0)"}
+
+
+def wl_sbm_largek(args):
+    r = measure_sbm(args, args.steps)
+    out = base_record(r["value"], sum(v["learned_autotuned_ms"] for v in r["per_k"].values()), args.steps, 1,
                       "k-clique counting k=10..12, SBM 200 blocks x 60, p_in 0.45, p_out 0.0005, seed 0; "
                       "learned + autotuned vs plain; value is tree nodes/s (the counts are 0 or near 0)",
-                      {"per_k": per, "tuning": tune, "training": tinfo,
-                       "plain_value_nodes_per_s": nodes_total / (tot_plain / 1e3),
-                       "speedup_vs_plain": tot_plain / tot_learned})
-    out["unit"] = "tree nodes/s"
+                      {k: v for k, v in r.items() if k not in ("value", "unit")})
+    out["unit"] = r["unit"]
+    return out
+
+
+def wl_ablation(args):
+    """Section V-A ablation on MI355X: DFS (one lane per traversal,
+    DM_IMPL_DFS), WC (wave per traversal, static schedule: DM_NO_DONATION) and
+    OPT (wave per traversal with in-kernel donation, the default), timed with
+    HIP events on the benchmark graphs: cliques k = 3..6 on the 10^6-vertex
+    Chung-Lu graph, motifs k = 3, 4 on the 10^5-vertex Chung-Lu graph (weight
+    cap 1414) and k = 5 at weight cap 200.  Counts must agree across the
+    three.  A DFS run longer than --ablation-limit seconds stops the DFS
+    column for the larger k of that series (marked null)."""
+    import torch
+    from paper_2212_04551_amd import dm
+    from paper_2212_04551_amd import graphgen as gg
+
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        r = fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return r, e0.elapsed_time(e1)
+
+    impls = (("DFS", dm.DM_IMPL_DFS), ("WC", dm.DM_NO_DONATION), ("OPT", dm.DM_SCHED_PLAIN))
+    only = set(args.ablation_only.split(",")) if args.ablation_only else None
+    rows = []
+    series = [("clique", "cl1m", lambda: gg.chung_lu(1_000_000, 20_000_000, 2.1, 1.0e4, args.seed)[0], (3, 4, 5, 6)),
+              ("motif", "cl100k_cap1414", lambda: gg.chung_lu(100_000, 1_000_000, 2.3, 1414.0, args.seed)[0], (3, 4)),
+              ("motif", "cl100k_cap200", lambda: gg.chung_lu(100_000, 1_000_000, 2.3, 200.0, args.seed)[0], (5,))]
+    for op, gname, make, ks in series:
+        g = make()
+        h = dm.load_graph(g, orient=(op == "clique"), rank=(op == "motif"))
+        dfs_ok = True
+        for k in ks:
+            row = {"op": op, "graph": gname, "k": k}
+            ref = None
+            for name, flag in impls:
+                if only and f"{op}{k}{name}" not in only:
+                    continue
+                if name == "DFS" and not dfs_ok:
+                    row[name + "_ms"] = None
+                    continue
+                fn = (lambda f=flag: dm.count_cliques(h, k, sched=f, stream=stream)) if op == "clique" else \
+                     (lambda f=flag: dm.count_motifs(h, k, sched=f, stream=stream))
+                fn()  # warm-up (row cache, dictionary, workspace)
+                c, ms = timed(fn)
+                tot = int(c) if op == "clique" else int(np.asarray(c).sum())
+                if ref is None:
+                    ref = c
+                assert np.array_equal(np.asarray(c), np.asarray(ref)), (op, k, name)
+                row[name + "_ms"] = ms
+                row["subgraphs"] = tot
+                log(f"ablation {op} {gname} k={k} {name}: {ms:.1f} ms ({tot} subgraphs)")
+                if name == "DFS" and ms > 1e3 * args.ablation_limit:
+                    dfs_ok = False
+            for a, b in (("DFS", "WC"), ("WC", "OPT"), ("DFS", "OPT")):
+                if row.get(a + "_ms") and row.get(b + "_ms"):
+                    row[f"{a}/{b}"] = row[a + "_ms"] / row[b + "_ms"]
+            rows.append(row)
+        h.close()
+        del g
+    best = [r for r in rows if r.get("OPT_ms")]
+    tot_sub = sum(r["subgraphs"] for r in best)
+    tot_ms = sum(r["OPT_ms"] for r in best)
+    out = base_record(tot_sub / (tot_ms / 1e3) if tot_ms else 0.0, tot_ms, 1, 1,
+                      "ablation (Section V-A): DFS one lane per traversal vs WC wave per traversal without load "
+                      "balancing vs OPT with in-kernel donation; cliques k=3..6 on Chung-Lu n=1e6 m=2e7, motifs "
+                      "k=3,4 on Chung-Lu n=1e5 m=1e6 cap 1414 and k=5 at cap 200",
+                      {"rows": rows})
+    return out
+
+
+def extra_configs(args):
+    """The other configurations, measured once each after the headline's timed
+    steps (never inside them): G(516, 1200) 4-motifs (plain), the 4096-graph
+    batched 5-motifs (batched + autotuned vs plain per-graph) and the SBM
+    large-k cliques (learned + autotuned vs plain)."""
+    out = {}
+    for name, fn in (("er516_motif4_plain", lambda: measure_er516(args)),
+                     ("batch4096_motif5_batched_vs_plain", lambda: measure_batch4096(args, 2)),
+                     ("sbm200x60_clique_k10_12_learned_vs_plain", lambda: measure_sbm(args, 3))):
+        t = time.perf_counter()
+        out[name] = fn()
+        log(f"{name}: done in {time.perf_counter() - t:.1f}s")
     return out
 
 
@@ -461,6 +654,7 @@ WORKLOADS = {
     "cl100k-motif5-sample": wl_cl100k_motif_sample,
     "batch4096-motif5": wl_batch4096,
     "sbm-clique-largek": wl_sbm_largek,
+    "ablation": wl_ablation,
 }
 
 
@@ -473,6 +667,12 @@ def main():
     ap.add_argument("--workload", default="cl1m-clique", choices=sorted(WORKLOADS))
     ap.add_argument("--epochs", type=int, default=20, help="MLP training epochs (learned workloads)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--ablation-limit", type=float, default=60.0,
+                    help="ablation: seconds after which DFS runs stop for larger k")
+    ap.add_argument("--ablation-only", default="",
+                    help="ablation: comma list of op+k+impl to run, e.g. clique6DFS,motif4WC (profiling)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="default workload: skip the other configurations measured after the headline")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one device copy of 1 GiB (counter calibration for profiles)")
