@@ -59,8 +59,10 @@ enum {
     DM_CSR_HOST = 0,    /* row_ptr / col are host pointers */
     DM_CSR_DEVICE = 1,  /* row_ptr / col are device pointers (copied device-to-device) */
     DM_CSR_TRUSTED = 2, /* skip validation (caller guarantees the conventions above) */
-    DM_CSR_ORIENT = 4   /* also build the (degree, id) orientation used by clique counting
+    DM_CSR_ORIENT = 4,  /* also build the (degree, id) orientation used by clique counting
                            now, instead of at the first clique call */
+    DM_CSR_RANK = 8     /* also build the orientation and the rank-renamed graph used by
+                           motif counting now (dm_count_motifs_static needs it) */
 };
 
 /* dm_options.sched bits */
@@ -177,6 +179,29 @@ dm_status dm_motif_class_table16(int k, uint16_t* out, size_t len);
  */
 dm_status dm_count_motifs(dm_graph* g, int k, uint64_t* out_counts, size_t out_len,
                           const dm_options* opt);
+
+/*
+ * dm_count_motifs without device allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same counts and errors as
+ * dm_count_motifs; the graph must carry its rank-renamed copy
+ * (dm_load_csr with DM_CSR_RANK, or an earlier dm_count_motifs call).
+ * Every device buffer of the launch (dictionary, scheduler words, class
+ * counters, per-wave extension stacks) lives in one library-owned static
+ * device array of 64 MiB per GPU, held until the process ends; the persistent
+ * grid shrinks to the waves whose stacks fit in it, and a graph whose single
+ * wave needs more (about 5 (k-1)(k-2)/2 + 4 bytes per unit of maximum degree,
+ * i.e. a maximum degree above about 1.1 million at k = 5) is rejected with
+ * DM_E_NOMEM.  Plain root queue over every root only: DM_SCHED_LEARNED,
+ * DM_SCHED_COST, DM_IMPL_DFS and root lists give DM_E_ARG; root_stats,
+ * wave_stats, chunk, rebalance, waves_per_cu, DM_NO_DONATION and
+ * DM_SCHED_AUTOTUNE knobs work as in dm_count_motifs.  NULL stream = the
+ * handle's own stream.  Calls share the device's array: the library
+ * serialises its own calls, but calls that overlap on one GPU from other
+ * processes or loaded copies of the library race.
+ */
+dm_status dm_count_motifs_static(dm_graph* g, int k, uint64_t* out_counts, size_t out_len,
+                                 const dm_options* opt);
 
 /*
  * Count many graphs in one persistent launch.  op is DM_OP_CLIQUE (one count

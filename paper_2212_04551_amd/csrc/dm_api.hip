@@ -323,13 +323,14 @@ static bool host_validate(int32_t n, const int64_t* rp, const int32_t* col, std:
 }
 
 static dm_status ensure_dag(dm_graph* g, hipStream_t s);
+static dm_status ensure_ranked(dm_graph* g, hipStream_t s);
 
 extern "C" dm_status dm_load_csr(int32_t n, const int64_t* row_ptr, const int32_t* col, uint32_t flags, void* stream,
                                  dm_graph** out) {
   if (!out) return fail(DM_E_ARG, "null output handle");
   *out = nullptr;
   if (n < 0 || !row_ptr || (!col && n > 0)) return fail(DM_E_ARG, "n < 0 or null CSR array");
-  if (flags & ~7u) return fail(DM_E_ARG, "unknown flag");
+  if (flags & ~15u) return fail(DM_E_ARG, "unknown flag");
   const bool on_device = flags & DM_CSR_DEVICE;
   const bool trusted = flags & DM_CSR_TRUSTED;
   int64_t nnz = 0;
@@ -380,8 +381,8 @@ extern "C" dm_status dm_load_csr(int32_t n, const int64_t* row_ptr, const int32_
     return bail(fail(DM_E_CSR, buf));
   }
   g->dmax = hostw[1];
-  if (flags & DM_CSR_ORIENT) {
-    const dm_status st = ensure_dag(g, s);
+  if (flags & (DM_CSR_ORIENT | DM_CSR_RANK)) {
+    const dm_status st = (flags & DM_CSR_RANK) ? ensure_ranked(g, s) : ensure_dag(g, s);
     if (st != DM_OK) return bail(st);
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return bail(hip_fail(e, "dm_load_csr: orient"));
@@ -1095,6 +1096,143 @@ extern "C" dm_status dm_count_motifs(dm_graph* g, int k, uint64_t* out_counts, s
   if (st == DM_OK) st = run_prepared(P, s, tmp.data());
   if (st == DM_OK) std::memcpy(out_counts, tmp.data(), sizeof(uint64_t) * T->ncls);
   return st;
+}
+
+// ====================================================================== motif counting without allocation
+
+namespace {
+
+// Device memory of dm_count_motifs_static: the dictionary, the scheduler's
+// control block, the class counters and the per-wave extension stacks of one
+// launch.  Every device the library runs on holds its own copy until the
+// process ends.  Host code never passes `scratch` itself (in host code the
+// name is only a stand-in): it uses the address hipGetSymbolAddress returns
+// for the current device, looked up once per device.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_lock;
+unsigned char* g_scratch_ptr[kMaxDevices] = {nullptr};
+int g_scratch_table_k[kMaxDevices] = {0};  // dictionary currently held by the device's scratch
+
+constexpr size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+// The layout starts with room for the largest dictionary (k = 7: 2^20
+// 16-bit ids), then the control block; the counters (up to 853) and the
+// per-wave stacks follow, sized per call.
+constexpr size_t kScratchTable = 0;
+constexpr size_t kScratchCtrl = align256(sizeof(uint16_t) << 20);
+
+}  // namespace
+
+extern "C" dm_status dm_count_motifs_static(dm_graph* g, int k, uint64_t* out_counts, size_t out_len,
+                                            const dm_options* opt) {
+  if (!g || !out_counts) return fail(DM_E_ARG, "null graph or output");
+  const ClassTables* T = tables(k);
+  if (!T) return fail(DM_E_K, "motif k must be in 3..7");
+  if (out_len < static_cast<size_t>(T->ncls)) return fail(DM_E_BUFSZ, "out_len < number of classes");
+  Opt o;
+  dm_status st = read_opt(opt, &o);
+  if (st != DM_OK) return st;
+  if (o.sched & (DM_SCHED_LEARNED | DM_SCHED_COST | DM_IMPL_DFS) || o.roots)
+    return fail(DM_E_ARG, "dm_count_motifs_static runs the plain root queue over every root (no learned or "
+                          "cost ordering, root list or DFS ablation)");
+  if (!g->ranked)
+    return fail(DM_E_ARG, "dm_count_motifs_static needs the rank-renamed graph: load it with DM_CSR_RANK "
+                          "(or count its motifs once with dm_count_motifs)");
+  int dev = 0;
+  HIP_OR_RETURN(hipGetDevice(&dev), "dm_count_motifs_static: device");
+  if (dev < 0 || dev >= kMaxDevices) return fail(DM_E_ARG, "device ordinal beyond the library's table");
+  std::lock_guard<std::mutex> lk(g_scratch_lock);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIP_OR_RETURN(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "dm_count_motifs_static: scratch address");
+    g_scratch_ptr[dev] = static_cast<unsigned char*>(p);
+  }
+  unsigned char* base = g_scratch_ptr[dev];
+  hipStream_t s = o.stream ? o.stream : g->own;
+  apply_tuning(DM_OP_MOTIF, k, &o);
+
+  // layout: table | control block | counters | per-wave stacks
+  const size_t off_out = kScratchCtrl + align256(ctrl_bytes());
+  const size_t off_waves = off_out + align256(sizeof(uint64_t) * 853);
+  const int dmax = g->dmax > 0 ? g->dmax : 1;
+  int64_t cap_total = 0;
+  int64_t level_off[8] = {0}, level_cap[8] = {0};
+  for (int s2 = 1; s2 <= k - 2 && s2 < 8; ++s2) {
+    level_off[s2] = cap_total;
+    level_cap[s2] = static_cast<int64_t>(s2) * dmax;
+    cap_total += level_cap[s2];
+  }
+  const size_t vert_bytes = sizeof(int32_t) * static_cast<size_t>(cap_total);
+  const size_t per_wave = vert_bytes + static_cast<size_t>(cap_total) + sizeof(int32_t) * static_cast<size_t>(dmax);
+  const size_t room = kScratchBytes - off_waves - 3 * 256;
+  const int64_t fit = static_cast<int64_t>(room / per_wave);
+  if (fit < 1) {
+    char buf[192];
+    std::snprintf(buf, sizeof buf,
+                  "one wave's extension stack (%zu bytes for max degree %d at k = %d) exceeds the %zu-byte static "
+                  "scratch; use dm_count_motifs", per_wave, dmax, k, kScratchBytes);
+    return fail(DM_E_NOMEM, buf);
+  }
+  const size_t lds = motif_lds_bytes(k, T->ncls);
+  int per_cu = 0;
+  HIP_OR_RETURN(motif_occupancy(k, lds, &per_cu), "occupancy");
+  if (per_cu < 1) per_cu = 1;
+  if (per_cu > 16) per_cu = 16;
+  if (o.waves_per_cu && static_cast<int>(o.waves_per_cu) < per_cu) per_cu = static_cast<int>(o.waves_per_cu);
+  int grid = size_grid(per_cu, g->nnz);
+  if (fit < grid) grid = static_cast<int>(fit);
+  const size_t off_vert = off_waves;
+  const size_t off_mask = align256(off_vert + vert_bytes * grid);
+  const size_t off_new = align256(off_mask + static_cast<size_t>(cap_total) * grid);
+
+  if (g_scratch_table_k[dev] != k) {
+    g_scratch_table_k[dev] = 0;
+    HIP_OR_RETURN(hipMemcpyAsync(base + kScratchTable, T->table.data(), T->table.size() * sizeof(uint16_t),
+                                 hipMemcpyHostToDevice, s),
+                  "dm_count_motifs_static: dictionary");
+    g_scratch_table_k[dev] = k;
+  }
+  char* ctrl = reinterpret_cast<char*>(base + kScratchCtrl);
+  MotifArgs A;
+  std::memset(&A, 0, sizeof A);
+  for (int s2 = 0; s2 < 8; ++s2) {
+    A.level_off[s2] = level_off[s2];
+    A.level_cap[s2] = level_cap[s2];
+  }
+  Sched S = make_sched_at(ctrl, o, grid, g->n, nullptr, g->order.as<int32_t>());
+  A.rp = g->urp.as<int64_t>();
+  A.col = g->ucol.as<int32_t>();
+  A.n = g->n;
+  A.k = k;
+  A.dmax = dmax;
+  A.ncls = T->ncls;
+  A.table = reinterpret_cast<const uint16_t*>(base + kScratchTable);
+  A.out = reinterpret_cast<unsigned long long*>(base + off_out);
+  A.root_graph = nullptr;
+  A.flags = reinterpret_cast<int*>(ctrl + kCtrlFlags);
+  A.root_stats = reinterpret_cast<unsigned long long*>(o.root_stats);
+  A.wave_stats = reinterpret_cast<unsigned long long*>(o.wave_stats);
+  A.wave_stats_len = static_cast<int>(o.wave_stats_len);
+  A.ext_vert = reinterpret_cast<int32_t*>(base + off_vert);
+  A.ext_mask = reinterpret_cast<uint8_t*>(base + off_mask);
+  A.new_buf = reinterpret_cast<int32_t*>(base + off_new);
+  A.wave_ext_cap = cap_total;
+  A.S = S;
+  // clears by fill kernels, the persistent kernel, copies of counters and flags
+  int flags[2] = {0, 0};
+  hipError_t e = launch_fill_u64(reinterpret_cast<unsigned long long*>(ctrl), static_cast<int64_t>(ctrl_bytes() / 8),
+                                 0ull, s);
+  if (e == hipSuccess) e = launch_fill_u64(A.out, T->ncls, o.bias, s);
+  if (e == hipSuccess && A.root_stats) e = launch_fill_u64(A.root_stats, 3 * static_cast<int64_t>(g->n), 0ull, s);
+  if (e == hipSuccess && g->n > 0) e = launch_motif(A, grid, lds, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(out_counts, A.out, sizeof(uint64_t) * T->ncls, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(flags, A.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "dm_count_motifs_static: kernel / copy-back");
+  return check_flags(flags);
 }
 
 // ====================================================================== batching

@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "lib", "libdumato_mi.so")
 
 DM_OK, DM_E_ARG, DM_E_CSR, DM_E_K, DM_E_OVERFLOW, DM_E_NOMEM, DM_E_HIP, DM_E_BUFSZ, DM_E_MODEL = range(9)
-DM_CSR_HOST, DM_CSR_DEVICE, DM_CSR_TRUSTED, DM_CSR_ORIENT = 0, 1, 2, 4
+DM_CSR_HOST, DM_CSR_DEVICE, DM_CSR_TRUSTED, DM_CSR_ORIENT, DM_CSR_RANK = 0, 1, 2, 4, 8
 DM_SCHED_PLAIN, DM_SCHED_LEARNED, DM_SCHED_AUTOTUNE, DM_RECORD_ROOTS, DM_NO_DONATION = 0, 1, 2, 4, 8
 DM_SCHED_COST = 16
 DM_IMPL_DFS = 32
@@ -33,7 +33,7 @@ EXPORTS = [
     "dm_load_csr", "dm_free", "dm_graph_info", "dm_count_cliques",
     "dm_motif_num_classes",
     "dm_motif_class_mask", "dm_motif_class_table", "dm_motif_class_table16", "dm_count_motifs",
-    "dm_batch", "dm_strerror",
+    "dm_count_motifs_static", "dm_batch", "dm_strerror",
     "dm_last_error", "dm_features", "dm_mlp_init", "dm_mlp_fit_normalizer", "dm_mlp_forward", "dm_mlp_targets",
     "dm_mlp_loss_grad", "dm_mlp_adam_step", "dm_mlp_train", "dm_autotune",
 ]
@@ -100,6 +100,8 @@ def lib():
     L.dm_motif_class_table16.argtypes = [ctypes.c_int, vp, ctypes.c_size_t]
     L.dm_count_motifs.restype = ctypes.c_int
     L.dm_count_motifs.argtypes = [vp, ctypes.c_int, vp, ctypes.c_size_t, ctypes.POINTER(dm_options)]
+    L.dm_count_motifs_static.restype = ctypes.c_int
+    L.dm_count_motifs_static.argtypes = [vp, ctypes.c_int, vp, ctypes.c_size_t, ctypes.POINTER(dm_options)]
     L.dm_batch.restype = ctypes.c_int
     L.dm_batch.argtypes = [ctypes.POINTER(vp), i32, ctypes.c_int, ctypes.c_int, vp, ctypes.c_size_t,
                            ctypes.POINTER(dm_options)]
@@ -212,7 +214,7 @@ class DMGraph:
 
 
 def load_csr(n: int, row_ptr, col, device: bool = False, trusted: bool = False, stream=None,
-             orient: bool = False) -> DMGraph:
+             orient: bool = False, rank: bool = False) -> DMGraph:
     """dm_load_csr on numpy arrays (host) or torch CUDA tensors (device=True)."""
     if not device:
         row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
@@ -221,6 +223,7 @@ def load_csr(n: int, row_ptr, col, device: bool = False, trusted: bool = False, 
             col = np.zeros(1, dtype=np.int32)
     flags = (DM_CSR_DEVICE if device else DM_CSR_HOST) | (DM_CSR_TRUSTED if trusted else 0)
     flags |= DM_CSR_ORIENT if orient else 0
+    flags |= DM_CSR_RANK if rank else 0
     h = ctypes.c_void_p(None)
     _check(lib().dm_load_csr(n, _ptr(row_ptr), _ptr(col), flags, _stream(stream), ctypes.byref(h)))
     return DMGraph(h.value)
@@ -282,6 +285,19 @@ def count_motifs(g: DMGraph, k: int, **opt) -> np.ndarray:
     _check_stats(g, opt)
     o, keep = make_options(**opt)
     _check(lib().dm_count_motifs(g.handle, k, out.ctypes.data, ncls, ctypes.byref(o)))
+    del keep
+    return out
+
+
+def count_motifs_static(g: DMGraph, k: int, **opt) -> np.ndarray:
+    """dm_count_motifs_static: the motif count with no device allocation."""
+    ncls = motif_num_classes(k)
+    if ncls < 0:
+        _check(DM_E_K)
+    out = np.zeros(ncls, dtype=np.uint64)
+    _check_stats(g, opt)
+    o, keep = make_options(**opt)
+    _check(lib().dm_count_motifs_static(g.handle, k, out.ctypes.data, ncls, ctypes.byref(o)))
     del keep
     return out
 
