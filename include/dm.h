@@ -218,6 +218,34 @@ dm_status dm_count_motifs_static(dm_graph* g, int k, uint64_t* out_counts, size_
 dm_status dm_batch(dm_graph* const* gs, int32_t num_graphs, int op, int k, uint64_t* out_counts,
                    size_t out_len, const dm_options* opt);
 
+/*
+ * Receives one batch of listed subgraphs: `rows` holds `nrows` rows of
+ * `width` int32 in host memory, valid only during the call.
+ */
+typedef void (*dm_sink_fn)(const int32_t* rows, uint64_t nrows, int width, void* user);
+
+/*
+ * aggregate_store (Section IV-C, Aggregate; Table II): list the subgraphs
+ * themselves instead of counting them.  op = DM_OP_CLIQUE: every k-clique
+ * (k in 1..32), a row of k original vertex ids in (degree, id) rank order.
+ * op = DM_OP_MOTIF: every connected induced k-subgraph (k in 3..7), a row of
+ * its k original vertex ids in canonical traversal order (Section IV-E: the
+ * lowest-(degree, id) vertex first, then each time the lowest vertex adjacent
+ * to those before it) followed by its class id (dm_motif_class_mask's
+ * numbering; row width k + 1).  Each subgraph appears exactly once; the order
+ * of rows is unspecified.  The kernel writes rows into a ring of pinned host
+ * memory (8 blocks of 65,536 rows) and `sink` is called on the calling thread
+ * with consecutive rows of one block while the kernel runs; a block is reused
+ * only after the sink has returned for all its rows, so a slow sink stalls
+ * the kernel (an idle wait longer than opt->wait_limit_us fails the call with
+ * DM_E_HIP).  *out_total = rows delivered.  Options: stream, waves-per-CU and
+ * wait limit; plain root queue over every root only (other sched bits, root
+ * lists and records give DM_E_ARG).
+ * Errors: DM_E_ARG, DM_E_K, DM_E_NOMEM, DM_E_HIP.
+ */
+dm_status dm_list(dm_graph* g, int op, int k, dm_sink_fn sink, void* user, uint64_t* out_total,
+                  const dm_options* opt);
+
 /* ---------------------------------------------------------------------------
  * Learned root ordering (an addition to the paper's method; it only orders and
  * chunks the initial root queue and never changes a count).  The model is a

@@ -167,6 +167,69 @@ def motif_brute(g, k: int, per_root: bool = False):
     return (out, pr[:g.n]) if per_root else out
 
 
+# ------------------------------------------------------------------ listings
+
+def _adjsets(g):
+    return [set(int(x) for x in g.col[g.row_ptr[v]:g.row_ptr[v + 1]]) for v in range(g.n)]
+
+
+def clique_list(g, k: int) -> np.ndarray:
+    """Every k-clique (Section IV-C aggregate_store: the subgraphs themselves
+    rather than their number) as a row of its k vertex ids in ascending order,
+    rows sorted.  Backtracking over increasing ids: a set grows only by a
+    larger vertex adjacent to all its members, so each clique appears once.
+    Pure Python: small graphs only."""
+    adj = _adjsets(g)
+    rows = []
+
+    def grow(sub, cand):
+        if len(sub) == k:
+            rows.append(tuple(sub))
+            return
+        for u in sorted(cand):
+            grow(sub + [u], {w for w in cand if w > u and w in adj[u]})
+
+    if k >= 1:
+        for v in range(g.n):
+            grow([v], {w for w in adj[v] if w > v})
+    out = np.array(sorted(rows), dtype=np.int64).reshape(-1, k)
+    return out
+
+
+def motif_list(g, k: int) -> np.ndarray:
+    """Every connected induced k-subset (Section IV-E, motif counting; listed
+    as aggregate_store would) as a row of its k vertex ids in ascending order
+    followed by its class id (class_of_code of its adjacency in that order),
+    rows sorted.  Connected sets are grown from their smallest vertex by
+    adding any larger neighbour of the set, duplicates removed by set
+    membership.  Pure Python: small graphs only."""
+    adj = _adjsets(g)
+    found = set()
+    for r in range(g.n):
+        frontier = {frozenset([r])}
+        for _ in range(k - 1):
+            nxt = set()
+            for S in frontier:
+                nb = set()
+                for v in S:
+                    nb |= adj[v]
+                for w in nb:
+                    if w > r and w not in S:
+                        nxt.add(S | {w})
+            frontier = nxt
+        found |= frontier
+    rows = []
+    for S in found:
+        vs = sorted(S)
+        a = np.zeros((k, k), dtype=np.uint8)
+        for i in range(k):
+            for j in range(i + 1, k):
+                if vs[j] in adj[vs[i]]:
+                    a[i, j] = a[j, i] = 1
+        rows.append(tuple(vs) + (class_of_code(k, code_of(a)),))
+    return np.array(sorted(rows), dtype=np.int64).reshape(-1, k + 1)
+
+
 # ------------------------------------------------------------------ L2
 
 def _roots(roots):

@@ -9,12 +9,14 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cstdio>
 #include <cstring>
 #include <map>
 #include <mutex>
 #include <numeric>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "dm.h"
@@ -859,6 +861,7 @@ dm_status prepare_motif(dm_graph* g, int k, const Opt& o, hipStream_t s, const i
   A.ext_mask = g->ext_mask.as<uint8_t>();
   A.new_buf = g->newbuf.as<int32_t>();
   A.wave_ext_cap = cap_total;
+  A.leaf_lds = 1;
   A.S = S;
   P->clique = false;
   P->grid = grid;
@@ -1219,6 +1222,7 @@ extern "C" dm_status dm_count_motifs_static(dm_graph* g, int k, uint64_t* out_co
   A.ext_mask = reinterpret_cast<uint8_t*>(base + off_mask);
   A.new_buf = reinterpret_cast<int32_t*>(base + off_new);
   A.wave_ext_cap = cap_total;
+  A.leaf_lds = 1;
   A.S = S;
   // clears by fill kernels, the persistent kernel, copies of counters and flags
   int flags[2] = {0, 0};
@@ -1233,6 +1237,178 @@ extern "C" dm_status dm_count_motifs_static(dm_graph* g, int k, uint64_t* out_co
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, "dm_count_motifs_static: kernel / copy-back");
   return check_flags(flags);
+}
+
+// ====================================================================== listing (aggregate_store)
+
+namespace {
+
+constexpr int kRingBlocks = 8;
+constexpr int kRingRowsPerBlock = 1 << 16;
+
+// pinned host memory of one listing call
+struct HostRing {
+  int32_t* rows = nullptr;
+  unsigned* valid = nullptr;
+  unsigned long long* freed = nullptr;
+  ~HostRing() {
+    if (rows) (void)hipHostFree(rows);
+    if (valid) (void)hipHostFree(valid);
+    if (freed) (void)hipHostFree(freed);
+  }
+};
+
+}  // namespace
+
+extern "C" dm_status dm_list(dm_graph* g, int op, int k, dm_sink_fn sink, void* user, uint64_t* out_total,
+                             const dm_options* opt) {
+  if (!g || !sink || !out_total) return fail(DM_E_ARG, "null graph, sink or output");
+  if (op != DM_OP_CLIQUE && op != DM_OP_MOTIF) return fail(DM_E_ARG, "unknown op");
+  const ClassTables* T = nullptr;
+  if (op == DM_OP_CLIQUE) {
+    if (k < 1 || k > kMaxK) return fail(DM_E_K, "clique k must be in 1..32");
+  } else {
+    T = tables(k);
+    if (!T) return fail(DM_E_K, "motif k must be in 3..7");
+  }
+  Opt o;
+  dm_status st = read_opt(opt, &o);
+  if (st != DM_OK) return st;
+  if ((o.sched & ~static_cast<uint32_t>(DM_NO_DONATION | DM_SCHED_AUTOTUNE)) || o.roots)
+    return fail(DM_E_ARG, "dm_list runs the plain root queue over every root, with no records, learned or cost "
+                          "ordering, root list or DFS ablation");
+  hipStream_t s = pick_stream(g, o.stream);
+  const int width = op == DM_OP_CLIQUE ? k : k + 1;
+  const int64_t slots = static_cast<int64_t>(kRingRowsPerBlock) * kRingBlocks;
+  HostRing H;
+  HIP_OR_RETURN(hipHostMalloc(reinterpret_cast<void**>(&H.rows), sizeof(int32_t) * slots * width, hipHostMallocCoherent),
+                "dm_list: ring");
+  HIP_OR_RETURN(hipHostMalloc(reinterpret_cast<void**>(&H.valid), sizeof(unsigned) * slots, hipHostMallocCoherent),
+                "dm_list: ring");
+  HIP_OR_RETURN(hipHostMalloc(reinterpret_cast<void**>(&H.freed), sizeof(unsigned long long) * kRingBlocks,
+                              hipHostMallocCoherent),
+                "dm_list: ring");
+  std::memset(H.valid, 0, sizeof(unsigned) * slots);
+  std::memset(H.freed, 0, sizeof(unsigned long long) * kRingBlocks);
+  // the persistent grid leaves most wave slots of each CU free: the host
+  // drains while the kernel runs, and nothing else must be starved of a CU
+  const int grid = size_grid(4, g->nnz);
+  HIP_OR_RETURN(g->ctrl.ensure(ctrl_bytes()), "workspace");
+  HIP_OR_RETURN(g->out.ensure(sizeof(unsigned long long)), "workspace");
+  char* c = g->ctrl.as<char>();
+  Opt ol = o;
+  ol.sched |= DM_NO_DONATION;  // listing launches take roots from the queue only
+  Ring R;
+  R.rows = H.rows;
+  R.valid = H.valid;
+  R.freed = H.freed;
+  R.reserve = g->out.as<unsigned long long>();
+  R.width = width;
+  R.rows_per_block = kRingRowsPerBlock;
+  R.nblocks = kRingBlocks;
+  R.wait_limit = wait_ticks(o.wait_limit_us);
+  R.flags = reinterpret_cast<int*>(c + kCtrlFlags);
+  HIP_OR_RETURN(launch_fill_u64(g->ctrl.as<unsigned long long>(), static_cast<int64_t>(ctrl_bytes() / 8), 0ull, s),
+                "clear");
+  HIP_OR_RETURN(launch_fill_u64(R.reserve, 1, 0ull, s), "clear");
+  if (op == DM_OP_CLIQUE) {
+    st = ensure_dag(g, s);
+    if (st != DM_OK) return st;
+    CliqueListArgs A;
+    std::memset(&A, 0, sizeof A);
+    A.rp = g->drp.as<int64_t>();
+    A.col = g->dcol.as<int32_t>();
+    A.n = g->n;
+    A.k = k;
+    A.dmax = g->ddmax > 0 ? g->ddmax : 1;
+    HIP_OR_RETURN(g->ext_vert.ensure(sizeof(int32_t) * static_cast<size_t>(grid) * (k > 1 ? k - 1 : 1) * A.dmax),
+                  "workspace");
+    A.stack = g->ext_vert.as<int32_t>();
+    A.flags = R.flags;
+    A.S = make_sched(g, ol, grid, g->n, nullptr, nullptr);
+    R.order = g->order.as<int32_t>();
+    A.R = R;
+    if (g->n > 0) HIP_OR_RETURN(launch_list_cliques(A, grid, s), "listing kernel");
+  } else {
+    uint16_t* dtab = nullptr;
+    HIP_OR_RETURN(device_table(k, &dtab), "class table upload");
+    st = ensure_ranked(g, s);
+    if (st != DM_OK) return st;
+    MotifArgs A;
+    std::memset(&A, 0, sizeof A);
+    const int dmax = g->dmax > 0 ? g->dmax : 1;
+    int64_t cap_total = 0;
+    for (int s2 = 1; s2 <= k - 1 && s2 < 8; ++s2) {
+      A.level_off[s2] = cap_total;
+      A.level_cap[s2] = static_cast<int64_t>(s2) * dmax;
+      cap_total += A.level_cap[s2];
+    }
+    HIP_OR_RETURN(g->ext_vert.ensure(sizeof(int32_t) * static_cast<size_t>(grid) * cap_total), "workspace");
+    HIP_OR_RETURN(g->ext_mask.ensure(static_cast<size_t>(grid) * cap_total), "workspace");
+    HIP_OR_RETURN(g->newbuf.ensure(sizeof(int32_t) * static_cast<size_t>(grid) * dmax), "workspace");
+    A.rp = g->urp.as<int64_t>();
+    A.col = g->ucol.as<int32_t>();
+    A.n = g->n;
+    A.k = k;
+    A.dmax = dmax;
+    A.ncls = T->ncls;
+    A.table = dtab;
+    A.flags = R.flags;
+    A.ext_vert = g->ext_vert.as<int32_t>();
+    A.ext_mask = g->ext_mask.as<uint8_t>();
+    A.new_buf = g->newbuf.as<int32_t>();
+    A.wave_ext_cap = cap_total;
+    A.leaf_lds = 0;
+    A.S = make_sched(g, ol, grid, g->n, nullptr, nullptr);
+    R.order = g->order.as<int32_t>();
+    if (g->n > 0) HIP_OR_RETURN(launch_list_motifs(A, R, grid, motif_list_lds_bytes(), s), "listing kernel");
+  }
+  // drain: deliver rows in order as their valid words appear; a block is
+  // handed back to the kernel once all its rows of a generation are delivered
+  uint64_t tail = 0, reserved = 0;
+  int flags[2] = {0, 0};
+  bool done = false;
+  int stalls = 0;
+  const volatile unsigned* valid = H.valid;
+  for (;;) {
+    uint64_t r = tail;
+    const uint64_t block_end = (tail / kRingRowsPerBlock + 1) * kRingRowsPerBlock;
+    while (r < block_end && valid[r % slots] == static_cast<unsigned>(r / slots + 1)) ++r;
+    if (r > tail) {
+      std::atomic_thread_fence(std::memory_order_acquire);
+      sink(H.rows + static_cast<int64_t>(tail % slots) * width, r - tail, width, user);
+      tail = r;
+      if (tail == block_end) {
+        const uint64_t last = tail - 1;
+        const int b = static_cast<int>((last % slots) / kRingRowsPerBlock);
+        std::atomic_thread_fence(std::memory_order_release);
+        __atomic_store_n(H.freed + b, static_cast<unsigned long long>(last / slots + 1), __ATOMIC_RELEASE);
+      }
+      continue;
+    }
+    if (done) {
+      // every reserved row is written before the kernel ends, unless a wave
+      // gave up waiting (flagged); rows that never show up fail the call
+      if (tail >= reserved || flags[1]) break;
+      if (++stalls > 50000) return fail(DM_E_HIP, "dm_list: reserved rows never became visible to the host");
+      std::this_thread::sleep_for(std::chrono::microseconds(20));
+      continue;
+    }
+    const hipError_t q = hipStreamQuery(s);
+    if (q == hipSuccess) {
+      HIP_OR_RETURN(hipMemcpyAsync(&reserved, R.reserve, sizeof(uint64_t), hipMemcpyDeviceToHost, s), "copy-back");
+      HIP_OR_RETURN(hipMemcpyAsync(flags, R.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, s), "copy-back");
+      HIP_OR_RETURN(hipStreamSynchronize(s), "copy-back");
+      done = true;
+      continue;
+    }
+    if (q != hipErrorNotReady) return hip_fail(q, "listing kernel");
+    std::this_thread::sleep_for(std::chrono::microseconds(20));
+  }
+  st = check_flags(flags);
+  if (st != DM_OK) return st;
+  *out_total = tail;
+  return DM_OK;
 }
 
 // ====================================================================== batching

@@ -67,6 +67,7 @@ struct MotifArgs {
   int64_t wave_ext_cap;    // entries per wave in ext_vert / ext_mask
   int64_t level_off[8];    // start of level s inside a wave's region
   int64_t level_cap[8];
+  int leaf_lds;            // the (k-2)-level list may be built straight into LDS (counting)
   Sched S;
 };
 
@@ -90,6 +91,79 @@ struct DfsArgs {
   int64_t level_cap[kDfsMaxK + 1];
 };
 
+// Listing ring (aggregate_store): rows of `width` int32 written by the kernel
+// straight into pinned host memory and drained by the calling host thread.
+// Row r occupies slot r mod (rows_per_block * nblocks) of generation
+// r / (rows_per_block * nblocks); a wave writes a row only once the host has
+// drained that slot's block of the previous generation (freed[block] >= gen),
+// then stores valid[slot] = gen + 1 (a plain system-scope store after a
+// system-scope release fence, so no host-memory read-modify-write is needed).
+struct Ring {
+  int32_t* rows;                     // host-pinned [slots][width]
+  unsigned* valid;                   // host-pinned [slots]
+  const unsigned long long* freed;   // host-pinned [nblocks]
+  unsigned long long* reserve;       // device: rows reserved so far
+  const int32_t* order;              // rank -> original vertex id
+  int width;
+  int rows_per_block;
+  int nblocks;
+  uint64_t wait_limit;               // wall-clock ticks a wave may wait for the host
+  int* flags;                        // flags[1] |= kFlagWaitLimit when a wave gives up
+};
+
+// Wave-uniform: hand `c` (1..64) rows to the ring.  Row i (lane i's row) is
+// order[prefix[0..np-1]], order[last of lane i], then `extra` of lane i when
+// width == np + 2.  All lanes must be active.  Returns false when the wave
+// gave up waiting for the host (the launch is then flagged).
+__device__ __forceinline__ bool ring_emit(const Ring& R, const int* prefix, int np, int last, int extra, int c) {
+  const int lane = lane_id();
+  long long base = 0;
+  if (lane == 0) base = static_cast<long long>(add_u64_relaxed(R.reserve, static_cast<unsigned long long>(c)));
+  base = uni64(base);
+  const long long slots = static_cast<long long>(R.rows_per_block) * R.nblocks;
+  // wait until the host has drained the previous generation of each block
+  // the rows land in (at most two blocks: c <= 64 <= rows_per_block)
+  for (long long r = base; r < base + c;) {
+    const long long gen = r / slots;
+    const int b = static_cast<int>((r % slots) / R.rows_per_block);
+    const uint64_t t0 = wall_clock64();
+    for (;;) {
+      unsigned long long fr = 0;
+      if (lane == 0)
+        fr = __hip_atomic_load(const_cast<unsigned long long*>(R.freed + b), __ATOMIC_ACQUIRE,
+                               __HIP_MEMORY_SCOPE_SYSTEM);
+      if (static_cast<long long>(uniu64(fr)) >= gen) break;
+      if (uniu64(wall_clock64() - t0) > R.wait_limit) {
+        if (lane == 0) atomicOr(R.flags + 1, kFlagWaitLimit);
+        return false;
+      }
+      __builtin_amdgcn_s_sleep(32);
+    }
+    r = (r / R.rows_per_block + 1) * R.rows_per_block;  // next block boundary
+  }
+  const int w = R.width;
+  for (int j = lane; j < kWave * w; j += kWave) {
+    const int row = j / w, colw = j - row * w;
+    const int lv = __shfl(last, row < kWave ? row : 0, kWave);
+    const int ex = __shfl(extra, row < kWave ? row : 0, kWave);
+    if (row < c) {
+      int v;
+      if (colw < np) v = R.order[prefix[colw]];
+      else if (colw == np) v = R.order[lv];
+      else v = ex;
+      const long long slot = (base + row) % slots;
+      R.rows[slot * w + colw] = v;
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+  if (lane < c) {
+    const long long r = base + lane;
+    __hip_atomic_store(R.valid + (r % slots), static_cast<unsigned>(r / slots + 1), __ATOMIC_RELEASE,
+                       __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+  return true;
+}
+
 // kernel launchers (return hipSuccess or the launch error)
 hipError_t launch_dfs_clique(const DfsArgs& a, int grid, hipStream_t s);
 hipError_t launch_dfs_motif(const DfsArgs& a, int grid, hipStream_t s);
@@ -98,6 +172,22 @@ size_t clique_lds_bytes(int dmax, int W, int k);
 hipError_t clique_occupancy(size_t lds_bytes, int* blocks_per_cu);
 
 hipError_t launch_motif(const MotifArgs& a, int grid, size_t lds_bytes, hipStream_t s);
+// listing (aggregate_store): cliques on the DAG, one wave per root; motifs
+// with the motif kernel's extension steps down to |tr| = k-1
+struct CliqueListArgs {
+  const int64_t* rp;   // DAG CSR in rank space
+  const int32_t* col;
+  int32_t n;
+  int k;
+  int dmax;            // largest out-degree
+  int32_t* stack;      // per-wave level lists, (k-1) * dmax entries per wave
+  int* flags;
+  Sched S;
+  Ring R;
+};
+hipError_t launch_list_cliques(const CliqueListArgs& a, int grid, hipStream_t s);
+hipError_t launch_list_motifs(const MotifArgs& a, const Ring& R, int grid, size_t lds_bytes, hipStream_t s);
+size_t motif_list_lds_bytes();
 size_t motif_lds_bytes(int k, int ncls);
 hipError_t motif_occupancy(int k, size_t lds_bytes, int* blocks_per_cu);
 

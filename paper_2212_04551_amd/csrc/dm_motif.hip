@@ -220,7 +220,7 @@ __device__ void extend_level(const MotifArgs& A, const MotifLds& L, MotifWave& M
     nn = A.dmax;
   }
   // the leaf level's list goes straight to LDS when it fits
-  const bool to_lds = s + 1 == A.k - 2 && static_cast<int64_t>(ns) - 1 + nn <= kLeafLds;
+  const bool to_lds = A.leaf_lds && s + 1 == A.k - 2 && static_cast<int64_t>(ns) - 1 + nn <= kLeafLds;
   int32_t* Nv = to_lds ? L.ev : MW.vert + A.level_off[s + 1];
   uint8_t* Nm = to_lds ? L.em : MW.mask + A.level_off[s + 1];
   const int64_t cap = to_lds ? kLeafLds : A.level_cap[s + 1];
@@ -685,6 +685,111 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4)))
   }
 }
 
+// ---------------------------------------------------------------- listing (aggregate_store)
+
+// Every connected induced k-subgraph rooted at t.root, handed to the ring as
+// (traversal order vertices, class id): the upper levels are the counting
+// kernel's extension steps, carried down to |tr| = k-1, where each canonical
+// entry y of the list completes one k-subgraph whose pattern is the
+// traversal's code plus y's mask in v_{k-1}'s field (Section IV-C bitmap).
+__device__ bool list_task(const MotifArgs& A, const Ring& R, const MotifLds& L, MotifWave& MW, const Task& t) {
+  const int lane = lane_id();
+  const int k = A.k;
+  const int v0 = t.root;
+  const int64_t b0 = A.rp[v0];
+  const int d0 = static_cast<int>(A.rp[v0 + 1] - b0);
+  const int skip = uni(lower_bound_g(A.col + b0, d0, v0 + 1));
+  {
+    int32_t* E1 = MW.vert + A.level_off[1];
+    uint8_t* M1 = MW.mask + A.level_off[1];
+    for (int i = lane; i < d0 - skip; i += kWave) {
+      E1[i] = A.col[b0 + skip + i];
+      M1[i] = 1;
+    }
+    if (lane == 0) {
+      L.esize[1] = d0 - skip;
+      L.tr[0] = v0;
+      L.code[1] = 0;
+      L.sufmax[1 * kSuf + 0] = -1;
+      L.cursor[1] = 0;
+      L.endv[1] = d0 - skip;
+    }
+  }
+  wave_sync();
+  int s = 1;
+  for (;;) {
+    if (s == k - 1) {
+      const int32_t* E = MW.vert + A.level_off[s];
+      const uint8_t* Em = MW.mask + A.level_off[s];
+      const int ns = L.esize[s];
+      const unsigned low = (1u << s) - 1u;
+      for (int c = 0; c < ns; c += kWave) {
+        const int j = c + lane;
+        const int y = j < ns ? E[j] : 0;
+        const unsigned m = j < ns ? Em[j] : 0u;
+        const bool ok = j < ns && canonical(L, s, y, m);
+        int cls = 0;
+        if (ok) {
+          cls = A.table[L.code[s] | static_cast<int>((m & low) << off_of(s))];
+          if (cls == kUnreachable) atomicOr(A.flags + 1, 2);
+        }
+        const uint64_t bl = ballot(ok);
+        if (ok) {
+          L.mark[mbcnt(bl)] = y;
+          L.sl_mask[mbcnt(bl)] = cls;
+        }
+        wave_sync();
+        const int cnt = __popcll(bl);
+        if (cnt) {
+          const int yy = lane < cnt ? L.mark[lane] : 0;
+          const int cc = lane < cnt ? L.sl_mask[lane] : 0;
+          if (!ring_emit(R, L.tr, k - 1, yy, cc, cnt)) return false;
+        }
+        wave_sync();
+      }
+      if (s == 1) break;
+      --s;
+      continue;
+    }
+    const int idx = next_canonical(A, L, MW, s, L.cursor[s], L.endv[s]);
+    if (idx < 0) {
+      if (s == 1) break;
+      --s;
+      continue;
+    }
+    const int x = MW.vert[A.level_off[s] + idx];
+    if (lane == 0) L.cursor[s] = idx + 1;
+    extend_level(A, L, MW, s, idx, x);
+    ++s;
+    if (lane == 0) {
+      L.cursor[s] = 0;
+      L.endv[s] = L.esize[s];
+    }
+    wave_sync();
+  }
+  return true;
+}
+
+__global__ void __launch_bounds__(64) list_motifs_kernel(MotifArgs A, Ring R) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int wave_gid = blockIdx.x;
+  MotifLds L = carve<16>(smem, 1);
+  MotifWave MW;
+  MW.cur_g = -1;
+  MW.ovf = 0;
+  MW.nodes = 0;
+  MW.tasks = 0;
+  MW.vert = A.ext_vert + static_cast<size_t>(wave_gid) * A.wave_ext_cap;
+  MW.mask = A.ext_mask + static_cast<size_t>(wave_gid) * A.wave_ext_cap;
+  MW.nbuf = A.new_buf + static_cast<size_t>(wave_gid) * A.dmax;
+  SchedIter it;
+  sched_begin(A.S, it);
+  Task t;
+  bool ok = true;
+  while (ok && sched_next(A.S, it, wave_gid, L.tr, &t)) ok = list_task(A, R, L, MW, t);
+  sched_end(A.S);
+}
+
 }  // namespace
 
 int motif_bins(int k) { return k <= 6 ? 16 : 32; }
@@ -704,6 +809,13 @@ hipError_t motif_occupancy(int k, size_t lds_bytes, int* blocks_per_cu) {
   return motif_bins(k) == 16
              ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, motif_kernel<16>, 64, lds_bytes)
              : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, motif_kernel<32>, 64, lds_bytes);
+}
+
+size_t motif_list_lds_bytes() { return motif_lds_bytes(3, 1); }
+
+hipError_t launch_list_motifs(const MotifArgs& a, const Ring& R, int grid, size_t lds_bytes, hipStream_t s) {
+  hipLaunchKernelGGL(list_motifs_kernel, dim3(grid), dim3(64), lds_bytes, s, a, R);
+  return hipGetLastError();
 }
 
 hipError_t launch_motif(const MotifArgs& a, int grid, size_t lds_bytes, hipStream_t s) {

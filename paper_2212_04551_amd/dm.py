@@ -33,7 +33,7 @@ EXPORTS = [
     "dm_load_csr", "dm_free", "dm_graph_info", "dm_count_cliques",
     "dm_motif_num_classes",
     "dm_motif_class_mask", "dm_motif_class_table", "dm_motif_class_table16", "dm_count_motifs",
-    "dm_count_motifs_static", "dm_batch", "dm_strerror",
+    "dm_count_motifs_static", "dm_batch", "dm_list", "dm_strerror",
     "dm_last_error", "dm_features", "dm_mlp_init", "dm_mlp_fit_normalizer", "dm_mlp_forward", "dm_mlp_targets",
     "dm_mlp_loss_grad", "dm_mlp_adam_step", "dm_mlp_train", "dm_autotune",
 ]
@@ -62,6 +62,10 @@ class dm_options(ctypes.Structure):
         ("wait_limit_us", ctypes.c_uint32),
         ("root_cost", ctypes.c_void_p),
     ]
+
+
+# void (*dm_sink_fn)(const int32_t* rows, uint64_t nrows, int width, void* user)
+SINK_FN = ctypes.CFUNCTYPE(None, ctypes.POINTER(ctypes.c_int32), ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p)
 
 
 class DMError(RuntimeError):
@@ -102,6 +106,9 @@ def lib():
     L.dm_count_motifs.argtypes = [vp, ctypes.c_int, vp, ctypes.c_size_t, ctypes.POINTER(dm_options)]
     L.dm_count_motifs_static.restype = ctypes.c_int
     L.dm_count_motifs_static.argtypes = [vp, ctypes.c_int, vp, ctypes.c_size_t, ctypes.POINTER(dm_options)]
+    L.dm_list.restype = ctypes.c_int
+    L.dm_list.argtypes = [vp, ctypes.c_int, ctypes.c_int, SINK_FN, vp, ctypes.POINTER(ctypes.c_uint64),
+                          ctypes.POINTER(dm_options)]
     L.dm_batch.restype = ctypes.c_int
     L.dm_batch.argtypes = [ctypes.POINTER(vp), i32, ctypes.c_int, ctypes.c_int, vp, ctypes.c_size_t,
                            ctypes.POINTER(dm_options)]
@@ -299,6 +306,34 @@ def count_motifs_static(g: DMGraph, k: int, **opt) -> np.ndarray:
     o, keep = make_options(**opt)
     _check(lib().dm_count_motifs_static(g.handle, k, out.ctypes.data, ncls, ctypes.byref(o)))
     del keep
+    return out
+
+
+def list_subgraphs(g: DMGraph, op: int, k: int, sink=None, **opt):
+    """dm_list (aggregate_store).  With no `sink`, returns every row as one
+    int32 array [rows, width] (cliques: k vertex ids; motifs: k vertex ids in
+    traversal order, then the class id).  With a `sink(rows)` callable, hands
+    it each batch (a numpy view valid only during the call) and returns the
+    row count."""
+    parts = []
+
+    def _cb(ptr, nrows, width, _user):
+        arr = np.ctypeslib.as_array(ptr, shape=(int(nrows), int(width)))
+        if sink is None:
+            parts.append(arr.copy())
+        else:
+            sink(arr)
+
+    cb = SINK_FN(_cb)
+    total = ctypes.c_uint64(0)
+    o, keep = make_options(**opt)
+    _check(lib().dm_list(g.handle, op, k, cb, None, ctypes.byref(total), ctypes.byref(o)))
+    del keep
+    if sink is not None:
+        return int(total.value)
+    width = k if op == DM_OP_CLIQUE else k + 1
+    out = np.concatenate(parts) if parts else np.zeros((0, width), dtype=np.int32)
+    assert out.shape[0] == total.value
     return out
 
 

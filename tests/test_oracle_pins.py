@@ -575,3 +575,61 @@ def test_features_against_networkx_and_numpy(seed):
     tri = nx.triangles(G)
     assert np.array_equal(F[:, 3], [tri[v] for v in range(g.n)])
     assert np.array_equal(F[:, 3], np.diag(A @ A @ A) // 2)
+
+
+# ------------------------------------------------------------------ listings (aggregate_store)
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_clique_list_against_networkx_and_brute_force(seed):
+    """Every listed row is a distinct clique, their number equals L1 brute
+    force, and the set of rows equals networkx's enumeration of all cliques
+    of size k."""
+    g = gg.erdos_renyi(40, 260, seed)
+    G = to_nx(g)
+    by_size = {}
+    for c in nx.enumerate_all_cliques(G):
+        by_size.setdefault(len(c), set()).add(tuple(sorted(c)))
+    for k in (1, 2, 3, 4, 5):
+        rows = O.clique_list(g, k)
+        assert rows.shape == (O.clique_brute(g, k), k)
+        assert set(map(tuple, rows.tolist())) == by_size.get(k, set())
+        assert len({tuple(r) for r in rows.tolist()}) == len(rows)
+
+
+def test_clique_list_complete_graph():
+    rows = O.clique_list(gg.complete(9), 4)
+    assert [tuple(r) for r in rows.tolist()] == list(itertools.combinations(range(9), 4))
+
+
+@pytest.mark.parametrize("k", [3, 4, 5])
+def test_motif_list_against_brute_force_and_vf2(k):
+    """Rows are distinct connected k-subsets; their class histogram equals L1
+    brute force; each row's class agrees with VF2 against the class's
+    canonical graph."""
+    g = gg.barabasi_albert(30, 2, k)
+    G = to_nx(g)
+    rows = O.motif_list(g, k)
+    hist = np.bincount(rows[:, k], minlength=O.num_classes(k)).astype(np.uint64)
+    assert np.array_equal(hist, O.motif_brute(g, k))
+    assert len({tuple(r[:k]) for r in rows.tolist()}) == len(rows)
+    reps = {}
+    for cls, code in enumerate(O.class_canon(k)):
+        H = nx.Graph()
+        H.add_nodes_from(range(k))
+        for i in range(1, k):
+            for t in range(i):
+                if int(code) >> (i * (i - 1) // 2 + t) & 1:
+                    H.add_edge(t, i)
+        reps[cls] = H
+    for r in rows[:: max(1, len(rows) // 200)].tolist():
+        sub = G.subgraph(r[:k])
+        assert nx.is_connected(sub)
+        assert nx.is_isomorphic(sub, reps[r[k]])
+
+
+def test_motif_list_closed_forms():
+    rows = O.motif_list(gg.path(12), 4)
+    assert [tuple(r[:4]) for r in rows.tolist()] == [tuple(range(i, i + 4)) for i in range(9)]
+    rows = O.motif_list(gg.complete(7), 3)
+    assert [tuple(r[:3]) for r in rows.tolist()] == list(itertools.combinations(range(7), 3))
+    assert len(set(rows[:, 3].tolist())) == 1
