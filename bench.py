@@ -30,7 +30,9 @@ KS = (3, 4, 5, 6, 7, 8)
 # (SQ_INSTS_VALU) and HBM bytes per launch (FETCH_SIZE and WRITE_SIZE, each
 # scaled by what the counter reads for a device copy of known size).  Valid
 # only for the kernel source they were taken on.
-CLIQUE_K8 = {"source_sha": None, "valu_insts": None, "hbm_bytes": None,
+CLIQUE_K8 = {"source_sha": "2211e7bdb24cac1d", "valu_insts": 804065161215.0,
+             "active_lane_fraction": 33392213038493.0 / (64 * 804065161215.0),
+             "hbm_bytes": 2.0 * 837202.5625 * 1024 + 418480.125 * 1024,
              "profile": "profiles/clique_kernel_cl1m_k8_counters.md"}
 
 
@@ -45,8 +47,9 @@ def kernel_source_sha(kernel: str = "dm_clique.hip") -> str:
 # HBM bytes per launch of the motif kernel on the sampled 5-motif workload
 # (same scaling), valid only for the kernel source they were taken on.
 TRAFFIC_MOTIF = {"source_sha": "98e6d219ceea12ac", "bytes_per_launch": 2.0 * 233289032.6 * 1024 + 54953631.5 * 1024}
-# MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz issue 39.3e12 32-bit integer
-# VALU operations per second (bitwise AND and popcount are single-issue ops).
+# MI355X VALU issue peak: 256 CUs x 4 SIMDs, a wave64 VALU instruction takes
+# 4 cycles on a 16-lane SIMD, at 2.4 GHz: 6.14e11 wave instructions/s, i.e.
+# 39.3e12 lane operations/s.
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
 
@@ -293,7 +296,9 @@ def wl_cl1m_clique(args):
             "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TOP/s", "frac": achieved / ALU_PEAK_TOPS,
             "traffic": CLIQUE_K8["hbm_bytes"],
             "basis": f"SQ_INSTS_VALU = {CLIQUE_K8['valu_insts']:.4g} wave instructions per launch x 64 lanes "
-                     f"({CLIQUE_K8['profile']}) / this run's HIP-event launch time {per_k_ms[kmax]:.1f} ms",
+                     f"({CLIQUE_K8['profile']}) / this run's HIP-event launch time {per_k_ms[kmax]:.1f} ms; "
+                     f"peak = 1024 SIMDs x 2.4 GHz / 4 cycles per wave64 VALU instruction x 64 lanes",
+            "active_lane_fraction": CLIQUE_K8["active_lane_fraction"],
             "byte_model": byte_model,
         }
     else:
@@ -632,6 +637,108 @@ def wl_ablation(args):
     return out
 
 
+def greedy_makespan(sizes, waves):
+    """Greedy list scheduling of roots in the given order onto `waves`
+    waves (each idle wave takes the next root): the finish time of the last
+    wave, in the units of `sizes`.  What a launch without donation does."""
+    import heapq
+    h = [0.0] * waves
+    for s in sizes:
+        heapq.heappush(h, heapq.heappop(h) + float(s))
+    return max(h)
+
+
+def rank_order(g):
+    """Vertices in (degree, id) rank order: the plain queue's order."""
+    deg = g.degrees()
+    return np.lexsort((np.arange(g.n), deg))
+
+
+def wl_ordering(args):
+    """What the learned root order can gain, per configuration: the plain
+    queue (rank order), the MLP's order and the order by the recorded tree
+    sizes themselves (a perfect predictor, DM_SCHED_COST), each launched with
+    and without in-kernel donation; wave idle fractions from wave_stats; and,
+    from the recorded per-root tree nodes, the greedy makespan of each order
+    on the launch's waves beside the ideal max(total / waves, largest root)."""
+    import torch
+    from paper_2212_04551_amd import dm
+    from paper_2212_04551_amd import graphgen as gg
+
+    stream = torch.cuda.current_stream()
+    ws = torch.zeros(256 * 32 * 4, dtype=torch.int64, device="cuda")
+
+    def launch(h, op, k, **kw):
+        fn = dm.count_cliques if op == "clique" else dm.count_motifs
+        fn(h, k, stream=stream, **kw)  # warm (queues, caches)
+        ws.zero_()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        c = fn(h, k, stream=stream, wave_stats=ws, **kw)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        w = ws.view(-1, 4).cpu().numpy().astype(np.float64)
+        w = w[w[:, 0] + w[:, 1] > 0]
+        return c, e0.elapsed_time(e1), float(w[:, 1].sum() / max(1.0, w[:, :2].sum())), int(len(w))
+
+    def study(name, g, h, op, k, model, cost_k):
+        stats = torch.zeros((g.n, 3), dtype=torch.int64, device="cuda")
+        (dm.count_cliques if op == "clique" else dm.count_motifs)(h, cost_k, root_stats=stats)
+        nodes = stats[:, 0].cpu().numpy().astype(np.float64)
+        cost = dm.mlp_targets(stats)
+        pred = dm.mlp_forward(model, dm.features(h)).cpu().numpy()
+        row = {"op": op, "k": k, "cost_from_records_at_k": cost_k}
+        ref = None
+        for label, kw in (("plain", {}), ("mlp", dict(sched=dm.DM_SCHED_LEARNED, mlp=model)),
+                          ("recorded", dict(root_cost=cost))):
+            for don, flag in (("donation", 0), ("no_donation", dm.DM_NO_DONATION)):
+                kk = dict(kw)
+                kk["sched"] = kk.get("sched", 0) | flag
+                c, ms, idle, waves = launch(h, op, k, **kk)
+                if ref is None:
+                    ref = c
+                assert np.array_equal(np.asarray(c), np.asarray(ref)), (name, label, don)
+                row[f"{label}_{don}_ms"] = ms
+                row[f"{label}_{don}_idle"] = idle
+                row["waves"] = waves
+                log(f"ordering {name} k={k} {label} {don}: {ms:.2f} ms, idle {idle:.3f}")
+        W = row["waves"]
+        orders = {"plain": rank_order(g), "mlp": np.argsort(-pred, kind="stable"),
+                  "recorded": np.argsort(-nodes, kind="stable")}
+        mk = {lbl: greedy_makespan(nodes[o], W) for lbl, o in orders.items()}
+        ideal = max(nodes.sum() / W, nodes.max())
+        row.update({"sim_makespan_nodes": mk, "sim_ideal_nodes": ideal,
+                    "sim_headroom_plain": 1.0 - ideal / mk["plain"],
+                    "sim_mlp_share_of_headroom": (mk["plain"] - mk["mlp"]) / max(1e-9, mk["plain"] - ideal),
+                    "pred_vs_recorded_corr": float(np.corrcoef(pred, cost.cpu().numpy())[0, 1])})
+        return row
+
+    out = {}
+    # SBM large-k cliques: the MLP trained on seeds 1..10 at k = 12
+    make = lambda sd: gg.sbm(200, 60, 0.45, 0.0005, sd)
+    model, tinfo = train_model(make, range(1, 11), "clique", 12, epochs=args.epochs, batch=1024)
+    g = make(0)
+    h = dm.load_graph(g)
+    out["sbm200x60_k12"] = study("sbm", g, h, "clique", 12, model, 12)
+    out["sbm200x60_k12"]["training"] = tinfo
+    # cl1m k = 8 cliques: per-root trees at k = 8 are out of a recording run's
+    # reach (10^12 nodes visited one by one), so both the MLP (trained on
+    # seeds 1, 2, 10% root samples) and the recorded-size order use k = 5 trees
+    make = lambda sd: gg.chung_lu(1_000_000, 20_000_000, 2.1, 1.0e4, sd)[0]
+    model, tinfo = train_model(make, (1, 2), "clique", 5, epochs=args.epochs, sample=0.1)
+    g = make(0)
+    h = dm.load_graph(g)
+    out["cl1m_k8"] = study("cl1m", g, h, "clique", 8, model, 5)
+    out["cl1m_k8"]["training"] = tinfo
+    tot = sum(v["plain_donation_ms"] for v in out.values())
+    rec = base_record(0.0, tot, 1, 1, "root-order study: plain vs MLP vs recorded-size order, with and without "
+                      "donation (SBM 200x60 k=12; Chung-Lu n=1e6 k=8)", {"studies": out})
+    rec["value"] = None
+    return rec
+
+
 def extra_configs(args):
     """The other configurations, measured once each after the headline's timed
     steps (never inside them): G(516, 1200) 4-motifs (plain), the 4096-graph
@@ -655,6 +762,7 @@ WORKLOADS = {
     "batch4096-motif5": wl_batch4096,
     "sbm-clique-largek": wl_sbm_largek,
     "ablation": wl_ablation,
+    "ordering": wl_ordering,
 }
 
 
