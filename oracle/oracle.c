@@ -57,8 +57,8 @@
 #include <time.h>
 
 #define OR_MAXK 8          /* vertex arrays sized for up to 8 traversal vertices */
-#define OR_MAX_MOTIF_K 7   /* class tables are built for k <= 7 */
-#define OR_MAX_CLASSES 853 /* classes of connected graphs on 7 vertices */
+#define OR_MAX_MOTIF_K 8     /* class tables are built for k <= 8 */
+#define OR_MAX_CLASSES 11117 /* classes of connected graphs on 8 vertices */
 
 /* ====================================================================== */
 /* canonical codes                                                         */
@@ -156,7 +156,8 @@ static int cmp_canon(const void* a, const void* b) {
      code is labelled already, and relabelling maps an orbit onto itself), so
      all k! relabellings of it are labelled with it.
    The second visits each class once instead of each code, which is what
-   makes k = 7 (2^21 codes, 853 classes) affordable.  canon_of[c] =
+   makes k = 7 (2^21 codes, 853 classes) and k = 8 (2^28 codes, 11117
+   classes) affordable.  canon_of[c] =
    0xffffffff for disconnected codes; returns the number of connected codes. */
 static int64_t canon_table(int k, uint32_t* canon_of, int by_orbits) {
     const uint32_t ncodes = 1u << (k * (k - 1) / 2);
@@ -174,18 +175,19 @@ static int64_t canon_table(int k, uint32_t* canon_of, int by_orbits) {
     for (uint32_t c = 0; c < ncodes; ++c) {
         if (canon_of[c] != unset) continue;
         if (!connected_code(k, c)) { canon_of[c] = 0xffffffffu; continue; }
-        unsigned char adj[OR_MAXK][OR_MAXK];
-        adj_from_code(k, c, adj);
+        /* the code's edges as (t, i) pairs, relabelled by every permutation */
+        int et[32], ei[32], ne = 0;
+        for (int i = 1; i < k; ++i)
+            for (int t = 0; t < i; ++t)
+                if (c >> pair_bit(t, i) & 1u) { et[ne] = t; ei[ne] = i; ++ne; }
         int p[OR_MAXK];
         for (int i = 0; i < k; ++i) p[i] = i;
         do {
             uint32_t d = 0;
-            for (int i = 1; i < k; ++i)
-                for (int t = 0; t < i; ++t)
-                    if (adj[t][i]) {
-                        int a = p[t], b = p[i];
-                        d |= 1u << (a < b ? pair_bit(a, b) : pair_bit(b, a));
-                    }
+            for (int e = 0; e < ne; ++e) {
+                int a = p[et[e]], b = p[ei[e]];
+                d |= 1u << (a < b ? pair_bit(a, b) : pair_bit(b, a));
+            }
             canon_of[d] = c;
         } while (next_perm(p, k));
     }
@@ -208,8 +210,11 @@ static const class_info* classes(int k) {
         uint32_t* canon_of = (uint32_t*)malloc(sizeof(uint32_t) * ncodes);
         ci->n_connected = canon_table(k, canon_of, k >= 7);
         /* classes: the distinct canonical codes (each is its own canon) */
-        uint32_t* uniq = (uint32_t*)malloc(sizeof(uint32_t) * ncodes);
         int nu = 0;
+        for (uint32_t c = 0; c < ncodes; ++c)
+            if (canon_of[c] == c) nu++;
+        uint32_t* uniq = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(nu > 0 ? nu : 1));
+        nu = 0;
         for (uint32_t c = 0; c < ncodes; ++c)
             if (canon_of[c] == c) uniq[nu++] = c;
         qsort(uniq, (size_t)nu, sizeof(uint32_t), cmp_canon);

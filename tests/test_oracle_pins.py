@@ -60,7 +60,7 @@ def class_of_pattern(k, H):
 
 # ------------------------------------------------------------------ class tables
 
-@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6, 7, 8])
 def test_class_counts_match_published_sequences(k):
     classes, labelled = _golden_counts()[k]
     assert O.num_classes(k) == classes
@@ -364,6 +364,69 @@ def test_motif_k7_classification_vf2_and_enumerators():
         if nx.is_connected(H):
             exp[[q for q in buckets[_wl(H)] if nx.is_isomorphic(H, reps[q])][0]] += 1
     assert exp.sum() > 100
+    assert np.array_equal(O.motif_brute(g, k), exp)
+    assert np.array_equal(O.motif_count(g, k), exp)
+
+
+def test_k8_classes_distinct_ordered_and_vf2_consistent():
+    """k = 8 (11,117 classes, beyond the networkx atlas): every class code is
+    connected, is its own orbit minimum as sampled by random relabellings,
+    the classes are ordered by (edge count, code), no two classes are
+    isomorphic within Weisfeiler-Lehman buckets (VF2), and random codes are
+    classified as VF2 says."""
+    k = 8
+    canon = O.class_canon(k)
+    assert len(canon) == 11117
+    reps = [graph_of_code(k, int(c)) for c in canon]
+    assert all(nx.is_connected(R) for R in reps)
+    for q in range(1, len(canon)):
+        a, b = int(canon[q - 1]), int(canon[q])
+        assert (bin(a).count("1"), a) < (bin(b).count("1"), b)
+    buckets = {}
+    for q, R in enumerate(reps):
+        buckets.setdefault(_wl(R), []).append(q)
+    for qs in buckets.values():
+        for i in range(len(qs)):
+            for j in range(i + 1, len(qs)):
+                assert not nx.is_isomorphic(reps[qs[i]], reps[qs[j]])
+    rng = np.random.default_rng(108)
+    for q in rng.choice(len(canon), 40, replace=False):
+        c = int(canon[q])
+        for _ in range(20):
+            p = rng.permutation(k)
+            d = 0
+            for i in range(1, k):
+                for t in range(i):
+                    if c >> (i * (i - 1) // 2 + t) & 1:
+                        a, b = sorted((int(p[t]), int(p[i])))
+                        d |= 1 << (b * (b - 1) // 2 + a)
+            assert d >= c and O.class_of_code(k, d) == q
+    for code in rng.integers(0, 1 << 28, size=300):
+        code = int(code)
+        H = graph_of_code(k, code)
+        q = O.class_of_code(k, code)
+        if not nx.is_connected(H):
+            assert q == -1
+        else:
+            assert [r for r in buckets[_wl(H)] if nx.is_isomorphic(H, reps[r])] == [q]
+
+
+def test_motif_k8_classification_vf2_and_enumerators():
+    """k = 8 on an 11-vertex graph: every connected 8-subset is counted in the
+    class VF2 assigns it; brute force and ESU agree."""
+    k = 8
+    g = gg.erdos_renyi(11, 22, 78)
+    G = to_nx(g)
+    reps = [graph_of_code(k, int(c)) for c in O.class_canon(k)]
+    buckets = {}
+    for q, R in enumerate(reps):
+        buckets.setdefault(_wl(R), []).append(q)
+    exp = np.zeros(len(reps), np.uint64)
+    for S in itertools.combinations(range(g.n), k):
+        H = G.subgraph(S)
+        if nx.is_connected(H):
+            exp[[q for q in buckets[_wl(H)] if nx.is_isomorphic(H, reps[q])][0]] += 1
+    assert exp.sum() > 50
     assert np.array_equal(O.motif_brute(g, k), exp)
     assert np.array_equal(O.motif_count(g, k), exp)
 
