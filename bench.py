@@ -565,8 +565,11 @@ def wl_sbm_largek(args):
 
 def wl_ablation(args):
     """Section V-A ablation on MI355X: DFS (one lane per traversal,
-    DM_IMPL_DFS), WC (wave per traversal, static schedule: DM_NO_DONATION) and
-    OPT (wave per traversal with in-kernel donation, the default), timed with
+    DM_IMPL_DFS), WC (wave per traversal, static schedule: DM_NO_DONATION),
+    HOST (wave per traversal with the paper's own load balancing: the launch
+    stopped, its untried work copied to the host, split and relaunched,
+    DM_SCHED_HOST_BALANCE) and OPT (wave per traversal with in-kernel
+    donation, the default), timed with
     HIP events on the benchmark graphs: cliques k = 3..6 on the 10^6-vertex
     Chung-Lu graph, motifs k = 3, 4 on the 10^5-vertex Chung-Lu graph (weight
     cap 1414) and k = 5 at weight cap 200.  Counts must agree across the
@@ -588,7 +591,8 @@ def wl_ablation(args):
         torch.cuda.synchronize()
         return r, e0.elapsed_time(e1)
 
-    impls = (("DFS", dm.DM_IMPL_DFS), ("WC", dm.DM_NO_DONATION), ("OPT", dm.DM_SCHED_PLAIN))
+    impls = (("DFS", dm.DM_IMPL_DFS), ("WC", dm.DM_NO_DONATION), ("HOST", dm.DM_SCHED_HOST_BALANCE),
+             ("OPT", dm.DM_SCHED_PLAIN))
     only = set(args.ablation_only.split(",")) if args.ablation_only else None
     rows = []
     series = [("clique", "cl1m", lambda: gg.chung_lu(1_000_000, 20_000_000, 2.1, 1.0e4, args.seed)[0], (3, 4, 5, 6)),
@@ -616,11 +620,13 @@ def wl_ablation(args):
                     ref = c
                 assert np.array_equal(np.asarray(c), np.asarray(ref)), (op, k, name)
                 row[name + "_ms"] = ms
+                if name == "HOST":
+                    row["HOST_launches"] = dm.last_launch_count()
                 row["subgraphs"] = tot
                 log(f"ablation {op} {gname} k={k} {name}: {ms:.1f} ms ({tot} subgraphs)")
                 if name == "DFS" and ms > 1e3 * args.ablation_limit:
                     dfs_ok = False
-            for a, b in (("DFS", "WC"), ("WC", "OPT"), ("DFS", "OPT")):
+            for a, b in (("DFS", "WC"), ("WC", "OPT"), ("DFS", "OPT"), ("WC", "HOST"), ("HOST", "OPT")):
                 if row.get(a + "_ms") and row.get(b + "_ms"):
                     row[f"{a}/{b}"] = row[a + "_ms"] / row[b + "_ms"]
             rows.append(row)
@@ -631,7 +637,8 @@ def wl_ablation(args):
     tot_ms = sum(r["OPT_ms"] for r in best)
     out = base_record(tot_sub / (tot_ms / 1e3) if tot_ms else 0.0, tot_ms, 1, 1,
                       "ablation (Section V-A): DFS one lane per traversal vs WC wave per traversal without load "
-                      "balancing vs OPT with in-kernel donation; cliques k=3..6 on Chung-Lu n=1e6 m=2e7, motifs "
+                      "balancing vs HOST stop/copy/relaunch balancing vs OPT in-kernel donation; cliques k=3..6 on "
+                      "Chung-Lu n=1e6 m=2e7, motifs "
                       "k=3,4 on Chung-Lu n=1e5 m=1e6 cap 1414 and k=5 at cap 200",
                       {"rows": rows})
     return out

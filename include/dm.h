@@ -17,6 +17,8 @@
  *   - Graphs are simple and undirected (Section II): CSR with int64 row
  *     offsets `row_ptr[n+1]` and int32 column ids `col[nnz]`, every adjacency
  *     list sorted strictly ascending, no self-loops, both directions present.
+ *     Row offsets are 64-bit so that nnz may exceed 2^31 - 1 (graphs of more
+ *     than about 1.07e9 edges); vertex ids stay 32-bit.
  *   - Counts are exact uint64.  Any uint64 wrap, in a per-wave accumulator or
  *     in a global sum, returns DM_E_OVERFLOW; outputs are then unspecified.
  *   - Output arrays are caller-owned HOST memory unless stated otherwise.
@@ -75,17 +77,30 @@ enum {
     DM_SCHED_COST = 16,    /* order and chunk roots like DM_SCHED_LEARNED, by the caller's
                               per-vertex costs `root_cost` instead of the MLP's predictions
                               (e.g. recorded tree sizes: the ordering a perfect predictor gives) */
-    DM_IMPL_DFS = 32       /* ablation (Section V-A, the DFS implementation of Table III): one
+    DM_IMPL_DFS = 32,      /* ablation (Section V-A, the DFS implementation of Table III): one
                               lane per traversal instead of one wave, each lane taking roots from
                               a global counter; same counts.  Plain root order over every root
-                              only (with DM_NO_DONATION or nothing else), clique k <= 16. */
+                              only (with DM_NO_DONATION or nothing else), clique k <= 16, motif k <= 7. */
+    DM_SCHED_HOST_BALANCE = 64 /* the paper's own load balancing (Section IV-D): no in-kernel
+                              donation; once the queue is drained and fewer than a fraction
+                              `rebalance` of the waves are still busy (default 0.4 for cliques,
+                              0.1 for motifs, the paper's Section V-A thresholds) the launch
+                              stops, busy waves write their untried extensions as tasks, and the
+                              host splits those tasks and relaunches with them as the queue, until
+                              no work is left (at most 64 stopped launches; the last runs to the
+                              end).  Same counts.  Single-graph calls only; excludes
+                              DM_NO_DONATION. */
 };
 
 enum { DM_OP_CLIQUE = 0, DM_OP_MOTIF = 1 };
 
 /*
  * Options.  opt == NULL means all defaults (plain schedule).  `size` must be
- * sizeof(dm_options) so the struct can grow.
+ * sizeof(dm_options) so the struct can grow.  Besides the schedule, stream,
+ * chunk, rebalance threshold, model and per-root records, it carries the knobs
+ * the measurements need: resident waves per CU, explicit root lists (sampled
+ * parity), per-wave idle / busy statistics, an accumulator bias (overflow
+ * tests), the bound on idle waits, and caller-given root costs.
  */
 typedef struct {
     uint32_t size;
@@ -135,11 +150,19 @@ dm_status dm_graph_info(const dm_graph* g, int32_t* n, int64_t* nnz);
  * Number of k-cliques (Section IV-E, clique counting; Alg. 4 left).  The graph
  * is oriented once by (degree, id) rank and cached on the handle; each clique
  * is found from its lowest-rank vertex.  k in 1..32 (k=1 gives n, k=2 gives m).
+ * A wave keeps a root's out-list and its k+1 candidate bitsets in LDS, so the
+ * oriented graph's largest out-degree D must satisfy
+ * (8 + (k+1)/8) D + 5.4 KB <= 160 KB (D up to about 17,000 at k = 8 and
+ * 13,000 at k = 32; always met when m <= 8.5e7, since D <= sqrt(2m)), else
+ * DM_E_NOMEM.
  * Errors: DM_E_ARG, DM_E_K, DM_E_OVERFLOW, DM_E_NOMEM, DM_E_HIP, DM_E_MODEL.
  */
 dm_status dm_count_cliques(dm_graph* g, int k, uint64_t* out_count, const dm_options* opt);
 
-/* Number of connected k-vertex classes: 2, 6, 21, 112, 853 for k = 3..7; -1 otherwise. */
+/* Number of connected k-vertex classes: 2, 6, 21, 112, 853, 11117 for k = 3..8; -1 otherwise.
+ * (The first call for a k builds that k's dictionary on the host: for k = 8,
+ * 2^27 entries from an orbit labelling of all 2^28 labelled graphs, using all
+ * host threads and about 1.3 GiB of host memory for a few seconds.) */
 int dm_motif_num_classes(int k);
 
 /*
@@ -161,17 +184,19 @@ dm_status dm_motif_class_mask(int k, int cls, uint32_t* upper_tri_mask);
 dm_status dm_motif_class_table(int k, uint8_t* out, size_t len);
 
 /*
- * The same dictionary with 16-bit class ids, for k in 3..7 (k = 7: 2^20
- * entries, 853 classes); unreachable codes hold 0xFFFF.  This is the table
- * the motif kernels read (Section IV-C gives its size for a pattern of k
- * vertices as 2^(k(k-1)/2 - 1) codes).  Host-only; needs no GPU.
- * Errors: DM_E_K, DM_E_ARG, DM_E_BUFSZ.
+ * The same dictionary with 16-bit class ids, for k in 3..8 (k = 7: 2^20
+ * entries, 853 classes; k = 8: 2^27 entries, 11,117 classes); unreachable
+ * codes hold 0xFFFF.  This is the table the motif kernels read (Section IV-C
+ * gives its size for a pattern of k vertices as 2^(k(k-1)/2 - 1) codes).
+ * Host-only; needs no GPU.  Errors: DM_E_K, DM_E_ARG, DM_E_BUFSZ.
  */
 dm_status dm_motif_class_table16(int k, uint16_t* out, size_t len);
 
 /*
  * Per-class counts of connected induced k-vertex subgraphs (Section IV-E,
- * motif counting; Alg. 4 right).  out_counts[cls] for cls < ncls(k); k in 3..7.
+ * motif counting; Alg. 4 right).  out_counts[cls] for cls < ncls(k); k in 3..8
+ * (k = 8 keeps each wave's 11,117 class counters in global memory instead of
+ * LDS, and its dictionary takes 256 MiB of device memory).
  * Each subgraph is enumerated once, from its lowest (degree, id) vertex (the
  * same root rule as cliques; per-root records and root lists use it).
  * Errors: DM_E_ARG, DM_E_K, DM_E_BUFSZ (out_len < ncls), DM_E_OVERFLOW,
@@ -181,7 +206,7 @@ dm_status dm_count_motifs(dm_graph* g, int k, uint64_t* out_counts, size_t out_l
                           const dm_options* opt);
 
 /*
- * dm_count_motifs without device allocation, for callers that cannot
+ * dm_count_motifs (k in 3..7) without device allocation, for callers that cannot
  * allocate device memory (code under HIP graph capture, tight serving loops,
  * harnesses that forbid hipMalloc).  Same counts and errors as
  * dm_count_motifs; the graph must carry its rank-renamed copy
@@ -202,6 +227,31 @@ dm_status dm_count_motifs(dm_graph* g, int k, uint64_t* out_counts, size_t out_l
  */
 dm_status dm_count_motifs_static(dm_graph* g, int k, uint64_t* out_counts, size_t out_len,
                                  const dm_options* opt);
+
+/*
+ * Property filters (Section II: E(G, tr, k, P) keeps the subgraphs with
+ * property P; cliques and connected induced patterns are two such P).
+ *
+ * dm_induced_subgraph: a vertex property.  Makes a new handle holding the
+ * subgraph induced by the vertices with keep[v] != 0 (keep: host array of n
+ * bytes, e.g. "carries an allowed label"), vertices renumbered in id order
+ * (v becomes the number of kept vertices below it).  Every count or listing
+ * on it is the count or listing, on g, of the subgraphs all of whose
+ * vertices are kept.  The new handle is independent of g (free both).
+ * Errors: DM_E_ARG, DM_E_NOMEM, DM_E_HIP.
+ */
+dm_status dm_induced_subgraph(dm_graph* g, const uint8_t* keep, void* stream, dm_graph** out);
+
+/*
+ * dm_count_quasi_cliques: a pattern property.  The number of connected
+ * induced k-subgraphs with at least min_edges edges (k in 3..8, min_edges in
+ * 0..k(k-1)/2): the density-gamma quasi-cliques for min_edges =
+ * ceil(gamma k(k-1)/2); min_edges = k(k-1)/2 gives the k-cliques, min_edges
+ * <= k-1 every connected k-subgraph.  Computed by the motif kernel, summing the
+ * classes whose pattern has enough edges; options as dm_count_motifs.
+ * Errors: as dm_count_motifs, and DM_E_ARG for min_edges out of range.
+ */
+dm_status dm_count_quasi_cliques(dm_graph* g, int k, int min_edges, uint64_t* out_count, const dm_options* opt);
 
 /*
  * Count many graphs in one persistent launch.  op is DM_OP_CLIQUE (one count
@@ -228,7 +278,7 @@ typedef void (*dm_sink_fn)(const int32_t* rows, uint64_t nrows, int width, void*
  * aggregate_store (Section IV-C, Aggregate; Table II): list the subgraphs
  * themselves instead of counting them.  op = DM_OP_CLIQUE: every k-clique
  * (k in 1..32), a row of k original vertex ids in (degree, id) rank order.
- * op = DM_OP_MOTIF: every connected induced k-subgraph (k in 3..7), a row of
+ * op = DM_OP_MOTIF: every connected induced k-subgraph (k in 3..8), a row of
  * its k original vertex ids in canonical traversal order (Section IV-E: the
  * lowest-(degree, id) vertex first, then each time the lowest vertex adjacent
  * to those before it) followed by its class id (dm_motif_class_mask's
@@ -321,6 +371,11 @@ const char* dm_strerror(dm_status s);
 
 /* Text of the last error raised on the calling thread ("" if none). */
 const char* dm_last_error(void);
+
+/* Kernel launches made by the calling thread's last dm_count_cliques /
+ * dm_count_motifs call: 1, or more when DM_SCHED_HOST_BALANCE stopped and
+ * relaunched it. */
+int dm_last_launch_count(void);
 
 #ifdef __cplusplus
 }

@@ -230,6 +230,65 @@ def motif_list(g, k: int) -> np.ndarray:
     return np.array(sorted(rows), dtype=np.int64).reshape(-1, k + 1)
 
 
+# ------------------------------------------------------------------ property filters
+
+def quasi_clique_brute(g, k: int, min_edges: int) -> int:
+    """Connected k-subsets whose induced subgraph has at least min_edges
+    edges (Section II's property P as a density threshold), by the definition:
+    every k-subset is checked.  Pure Python: tiny graphs only."""
+    import itertools
+    adj = _adjsets(g)
+    cnt = 0
+    for S in itertools.combinations(range(g.n), k):
+        e = sum(1 for i in range(k) for j in range(i + 1, k) if S[j] in adj[S[i]])
+        if e < min_edges:
+            continue
+        seen, stack = {S[0]}, [S[0]]
+        while stack:
+            x = stack.pop()
+            for y in S:
+                if y not in seen and y in adj[x]:
+                    seen.add(y)
+                    stack.append(y)
+        cnt += len(seen) == k
+    return cnt
+
+
+def quasi_clique_count(g, k: int, min_edges: int, threads: int = 1) -> int:
+    """The same from the ESU class counts: the classes whose canonical
+    pattern has at least min_edges edges."""
+    c = motif_count(g, k, threads=threads)
+    edges = np.array([bin(int(x)).count("1") for x in class_canon(k)])
+    return int(c[edges >= min_edges].sum())
+
+
+def induced(g, keep) -> "object":
+    """The subgraph induced by the vertices with keep[v], renumbered in id
+    order (a Graph-like object with n, row_ptr, col)."""
+    keep = np.asarray(keep, dtype=bool)
+    newid = np.cumsum(keep) - keep
+    rows, cols = [], []
+    rp = [0]
+    for v in range(g.n):
+        if not keep[v]:
+            continue
+        nb = g.col[g.row_ptr[v]:g.row_ptr[v + 1]]
+        nb = nb[keep[nb]]
+        cols.append(newid[nb])
+        rp.append(rp[-1] + len(nb))
+    col = np.concatenate(cols).astype(np.int32) if cols else np.zeros(0, np.int32)
+
+    class _G:
+        pass
+
+    h = _G()
+    h.n = int(keep.sum())
+    h.row_ptr = np.array(rp, dtype=np.int64)
+    h.col = col
+    h.nnz = int(len(col))
+    return h
+
+
 # ------------------------------------------------------------------ L2
 
 def _roots(roots):

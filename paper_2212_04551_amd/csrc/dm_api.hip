@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <numeric>
 #include <string>
@@ -61,6 +62,11 @@ extern "C" const char* dm_strerror(dm_status s) {
 
 extern "C" const char* dm_last_error(void) { return g_last_error.c_str(); }
 
+// kernel launches of the calling thread's last counting call
+static thread_local int g_last_launches = 0;
+
+extern "C" int dm_last_launch_count(void) { return g_last_launches; }
+
 // ====================================================================== class tables
 
 namespace {
@@ -90,27 +96,40 @@ bool bitmap_connected(int k, uint32_t code) {
   return reach == (1u << k) - 1u;
 }
 
-// Canonical forms by orbit enumeration: every permutation of S_k is turned
-// into a map of bitmap positions (Heap's algorithm), each still-unlabelled
-// connected bitmap has its whole orbit generated, and the orbit minimum is
-// the canonical form of all its members.
+// run fn(t) for t in [0, n) on n host threads
+template <class F>
+void parallel_run(int n, F fn) {
+  std::vector<std::thread> th;
+  for (int t = 1; t < n; ++t) th.emplace_back(fn, t);
+  fn(0);
+  for (auto& x : th) x.join();
+}
+
+// Canonical forms by orbit enumeration.  Every permutation of S_k is turned
+// into a map of bitmap positions (Heap's algorithm).  Host threads scan
+// disjoint slices of the 2^(k(k-1)/2) labelled bitmaps; a connected bitmap
+// not yet labelled has its whole orbit generated and every member labelled
+// with the orbit minimum, the canonical form (two threads that reach the same
+// orbit write the same labels).  For k = 8 that is 2^28 bitmaps (a 1 GiB label
+// array, freed when the table is filled) and 11,117 orbits of up to 40,320
+// members.
 ClassTables build_tables(int k) {
   ClassTables T;
   const int P = k * (k - 1) / 2;
   const uint32_t ncodes = 1u << P;
-  std::vector<std::vector<uint8_t>> perm_maps;
+  std::vector<uint8_t> pm;  // permutation j: pm[j * P + b] = image of bitmap position b
   {
     std::vector<int> p(k), c(k, 0);
     std::iota(p.begin(), p.end(), 0);
     auto add = [&]() {
-      std::vector<uint8_t> m(P);
+      const size_t base = pm.size();
+      pm.resize(base + P);
       for (int i = 1; i < k; ++i)
         for (int t = 0; t < i; ++t) {
           int a = p[t], b = p[i];
           if (a > b) std::swap(a, b);
-          m[pair_index(t, i)] = static_cast<uint8_t>(pair_index(a, b));
+          pm[base + pair_index(t, i)] = static_cast<uint8_t>(pair_index(a, b));
         }
-      perm_maps.push_back(std::move(m));
     };
     add();
     int i = 0;
@@ -126,50 +145,72 @@ ClassTables build_tables(int k) {
       }
     }
   }
-  const uint32_t kNone = 0xffffffffu;
-  std::vector<uint32_t> canon_of(ncodes, kNone);
-  std::vector<uint32_t> reps;
-  std::vector<uint32_t> orbit;
-  for (uint32_t c = 0; c < ncodes; ++c) {
-    if (canon_of[c] != kNone || !bitmap_connected(k, c)) continue;
-    orbit.clear();
-    uint32_t best = c;
-    for (const auto& m : perm_maps) {
-      uint32_t d = 0;
-      for (int b = 0; b < P; ++b)
-        if ((c >> b) & 1u) d |= 1u << m[b];
-      orbit.push_back(d);
-      best = std::min(best, d);
+  const size_t nperm = pm.size() / P;
+  const uint32_t kUnset = 0xffffffffu, kDisconnected = 0xfffffffeu;
+  std::unique_ptr<std::atomic<uint32_t>[]> lab(new std::atomic<uint32_t>[ncodes]);
+  const unsigned hc = std::thread::hardware_concurrency();
+  const int nth = ncodes < (1u << 16) ? 1 : static_cast<int>(std::max(1u, std::min(16u, hc)));
+  auto slice = [&](int t, uint64_t n) { return std::make_pair(n * t / nth, n * (t + 1) / nth); };
+  parallel_run(nth, [&](int t) {
+    const auto r = slice(t, ncodes);
+    for (uint64_t c = r.first; c < r.second; ++c) lab[c].store(kUnset, std::memory_order_relaxed);
+  });
+  parallel_run(nth, [&](int t) {
+    const auto r = slice(t, ncodes);
+    std::vector<uint32_t> orbit(nperm);
+    for (uint64_t cc = r.first; cc < r.second; ++cc) {
+      const uint32_t c = static_cast<uint32_t>(cc);
+      if (lab[c].load(std::memory_order_relaxed) != kUnset) continue;
+      if (!bitmap_connected(k, c)) {
+        lab[c].store(kDisconnected, std::memory_order_relaxed);
+        continue;
+      }
+      uint32_t best = c;
+      for (size_t j = 0; j < nperm; ++j) {
+        const uint8_t* m = &pm[j * P];
+        uint32_t d = 0;
+        for (uint32_t x = c; x; x &= x - 1) d |= 1u << m[__builtin_ctz(x)];
+        orbit[j] = d;
+        best = std::min(best, d);
+      }
+      for (size_t j = 0; j < nperm; ++j) lab[orbit[j]].store(best, std::memory_order_relaxed);
     }
-    for (uint32_t d : orbit) canon_of[d] = best;
-    reps.push_back(best);
-  }
+  });
+  std::vector<uint32_t> reps;
+  for (uint32_t c = 0; c < ncodes; ++c)
+    if (lab[c].load(std::memory_order_relaxed) == c) reps.push_back(c);
   std::sort(reps.begin(), reps.end(), [](uint32_t a, uint32_t b) {
     const int pa = __builtin_popcount(a), pb = __builtin_popcount(b);
     return pa != pb ? pa < pb : a < b;
   });
   T.ncls = static_cast<int>(reps.size());
   T.canon = reps;
-  std::map<uint32_t, int> id;
-  for (int q = 0; q < T.ncls; ++q) id[reps[q]] = q;
+  std::vector<std::pair<uint32_t, uint16_t>> id(reps.size());
+  for (int q = 0; q < T.ncls; ++q) id[q] = {reps[q], static_cast<uint16_t>(q)};
+  std::sort(id.begin(), id.end());
   // traversal code t: full bitmap (t << 1) | 1 (edge v0-v1 implied)
   const uint32_t ntrav = 1u << (P - 1);
   T.table.assign(ntrav, kUnreachable);
-  for (uint32_t t = 0; t < ntrav; ++t) {
-    bool reach = true;
-    for (int i = 2; i < k; ++i) {
-      const uint32_t field = (t >> (i * (i - 1) / 2 - 1)) & ((1u << i) - 1u);
-      if (!field) reach = false;
+  parallel_run(nth, [&](int th) {
+    const auto r = slice(th, ntrav);
+    for (uint64_t tt = r.first; tt < r.second; ++tt) {
+      const uint32_t t = static_cast<uint32_t>(tt);
+      bool reach = true;
+      for (int i = 2; i < k; ++i) {
+        const uint32_t field = (t >> (i * (i - 1) / 2 - 1)) & ((1u << i) - 1u);
+        if (!field) reach = false;
+      }
+      if (!reach) continue;
+      const uint32_t canon = lab[(t << 1) | 1u].load(std::memory_order_relaxed);
+      const auto it = std::lower_bound(id.begin(), id.end(), std::make_pair(canon, static_cast<uint16_t>(0)));
+      T.table[t] = it->second;
     }
-    if (!reach) continue;
-    const uint32_t full = (t << 1) | 1u;
-    T.table[t] = static_cast<uint16_t>(id.at(canon_of[full]));
-  }
+  });
   return T;
 }
 
 std::mutex g_tables_lock;
-ClassTables* g_tables[8] = {nullptr};
+ClassTables* g_tables[kMotifMaxK + 1] = {nullptr};
 
 const ClassTables* tables(int k) {
   if (k < 3 || k > kMotifMaxK) return nullptr;
@@ -217,7 +258,7 @@ extern "C" int dm_motif_num_classes(int k) {
 
 extern "C" dm_status dm_motif_class_mask(int k, int cls, uint32_t* mask) {
   const ClassTables* T = tables(k);
-  if (!T) return fail(DM_E_K, "motif k must be in 3..7");
+  if (!T) return fail(DM_E_K, "motif k must be in 3..8");
   if (!mask || cls < 0 || cls >= T->ncls) return fail(DM_E_ARG, "class id out of range or null output");
   *mask = T->canon[cls];
   return DM_OK;
@@ -235,7 +276,7 @@ extern "C" dm_status dm_motif_class_table(int k, uint8_t* out, size_t len) {
 
 extern "C" dm_status dm_motif_class_table16(int k, uint16_t* out, size_t len) {
   const ClassTables* T = tables(k);
-  if (!T) return fail(DM_E_K, "motif k must be in 3..7");
+  if (!T) return fail(DM_E_K, "motif k must be in 3..8");
   if (!out) return fail(DM_E_ARG, "null output");
   if (len < T->table.size()) return fail(DM_E_BUFSZ, "table needs 2^(k(k-1)/2-1) entries");
   std::memcpy(out, T->table.data(), T->table.size() * sizeof(uint16_t));
@@ -281,6 +322,8 @@ struct dm_graph {
   // workspace reused across calls
   Buf ctrl, out, rows, ext_vert, ext_mask, newbuf, qroot, qstat, qlo, qhi, rgraph;
   Buf dfs_stack, dfs_mask;  // per-lane stacks of the one-lane-per-traversal ablation
+  Buf spill, tq;            // host-driven balancing: spilled tasks, relaunch queue
+  Buf wave_cnt;             // motifs at k = 8: per-wave class counters
   // learned ordering: features (cached), predictions, LPT order, chunk starts
   // and the order in rank space; the queue is reused while the parameter
   // fingerprint, grid and chunks per wave stay the same
@@ -458,7 +501,9 @@ dm_status read_opt(const dm_options* o, Opt* r) {
   *r = Opt();
   if (!o) return DM_OK;
   if (o->size != sizeof(dm_options)) return fail(DM_E_ARG, "dm_options.size != sizeof(dm_options)");
-  if (o->sched & ~63u) return fail(DM_E_ARG, "unknown sched bits");
+  if (o->sched & ~127u) return fail(DM_E_ARG, "unknown sched bits");
+  if ((o->sched & DM_SCHED_HOST_BALANCE) && (o->sched & DM_NO_DONATION))
+    return fail(DM_E_ARG, "DM_SCHED_HOST_BALANCE already runs without in-kernel donation");
   if ((o->sched & DM_IMPL_DFS) && ((o->sched & ~static_cast<uint32_t>(DM_IMPL_DFS | DM_NO_DONATION)) || o->roots))
     return fail(DM_E_ARG, "DM_IMPL_DFS runs the plain root order over every root, with no other option");
   if ((o->sched & DM_SCHED_COST) && (o->sched & DM_SCHED_LEARNED))
@@ -514,7 +559,11 @@ constexpr size_t kCtrlSlots = 32;  // int slot_state[kSlots], then slot_data
 // queue heads (kQueueHeads u64 counters, 128 B apart) after the slot data
 constexpr size_t kCtrlHeads = (kCtrlSlots + sizeof(int) * kSlots + sizeof(int) * kSlots * kTaskInts + 127) & ~size_t(127);
 
-size_t ctrl_bytes() { return kCtrlHeads + sizeof(unsigned long long) * kHeadStride * kQueueHeads; }
+// host-driven balancing: the stop word and the spill counter, a line each
+constexpr size_t kCtrlStop = kCtrlHeads + sizeof(unsigned long long) * kHeadStride * kQueueHeads;
+constexpr size_t kCtrlSpillN = kCtrlStop + 128;
+
+size_t ctrl_bytes() { return kCtrlSpillN + 128; }
 
 // scheduler fields common to both kernels
 Sched make_sched_at(char* c, const Opt& o, int grid, int64_t nq, const int32_t* qroot, const int32_t* qstat) {
@@ -533,7 +582,14 @@ Sched make_sched_at(char* c, const Opt& o, int grid, int64_t nq, const int32_t* 
   S.nchunks = 0;
   S.chunk = o.chunk ? static_cast<int>(o.chunk) : 1;
   S.nslots = kSlots;
-  S.donate = (o.sched & DM_NO_DONATION) ? 0 : 1;
+  S.host_bal = (o.sched & DM_SCHED_HOST_BALANCE) ? 1 : 0;
+  S.donate = ((o.sched & DM_NO_DONATION) || S.host_bal) ? 0 : 1;
+  S.stop_trigger = grid + 1;  // set by the launch's preparation when host_bal
+  S.stop = reinterpret_cast<int*>(c + kCtrlStop);
+  S.spill_n = reinterpret_cast<int*>(c + kCtrlSpillN);
+  S.spill = nullptr;
+  S.spill_cap = 0;
+  S.tq = nullptr;
   const float r = o.rebalance > 0.f ? o.rebalance : 0.0f;
   int trig = static_cast<int>(r * grid);
   S.idle_trigger = trig < 1 ? 1 : trig;
@@ -609,6 +665,7 @@ hipError_t enqueue(const Prepared& P, hipStream_t s, uint64_t* host_out, int* ho
 }
 
 dm_status run_prepared(const Prepared& P, hipStream_t s, uint64_t* host_out) {
+  g_last_launches = 1;
   int flags[2] = {0, 0};
   hipError_t e = enqueue(P, s, host_out, flags);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -616,6 +673,75 @@ dm_status run_prepared(const Prepared& P, hipStream_t s, uint64_t* host_out) {
   const dm_status st = check_flags(flags);
   if (st == DM_OK && P.rc_done) *P.rc_done = true;
   return st;
+}
+
+// Host-driven balancing (Section IV-D: stop, copy the traversal state,
+// redistribute, relaunch).  After each stopped launch the spilled tasks are
+// copied to the host, every task's untried index range is cut into pieces so
+// that the next launch has about two tasks per wave, and the kernel is
+// relaunched with those tasks as its queue; counters and per-root records
+// accumulate across launches.  After kMaxRelaunch stopped launches the last
+// one runs to the end.
+constexpr int kMaxRelaunch = 64;
+
+dm_status run_host_balanced(dm_graph* g, Prepared& P, hipStream_t s, uint64_t* host_out) {
+  Sched& S = P.clique ? P.ca.S : P.ma.S;
+  int flags[2] = {0, 0}, acc_flags[2] = {0, 0};
+  hipError_t e = enqueue(P, s, host_out, flags);
+  g_last_launches = 1;
+  std::vector<int> tasks, next;
+  for (int launch = 1;; ++launch) {
+    int nspill = 0;
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(&nspill, reinterpret_cast<char*>(P.ctrl) + kCtrlSpillN, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "host-balanced launch");
+    acc_flags[0] |= flags[0];
+    acc_flags[1] |= flags[1];
+    if (acc_flags[1] || nspill == 0) break;
+    if (nspill > S.spill_cap) return fail(DM_E_HIP, "host-balanced launch: spill array overflow");
+    tasks.resize(static_cast<size_t>(nspill) * kTaskInts);
+    HIP_OR_RETURN(hipMemcpy(tasks.data(), S.spill, sizeof(int) * tasks.size(), hipMemcpyDeviceToHost), "spill copy");
+    // redistribute: cut [lo, hi) (ints 4, 5 of a task) into pieces
+    int64_t width = 0;
+    for (int i = 0; i < nspill; ++i) width += tasks[i * kTaskInts + 5] - tasks[i * kTaskInts + 4];
+    const double per = width > 0 ? 2.0 * S.waves / static_cast<double>(width) : 0.0;
+    next.clear();
+    for (int i = 0; i < nspill; ++i) {
+      const int* t = &tasks[static_cast<size_t>(i) * kTaskInts];
+      const int lo = t[4], hi = t[5];
+      int pieces = static_cast<int>(per * (hi - lo) + 0.5);
+      if (pieces < 1) pieces = 1;
+      if (pieces > hi - lo) pieces = hi - lo;
+      for (int p = 0; p < pieces; ++p) {
+        const int a = lo + static_cast<int>(static_cast<int64_t>(hi - lo) * p / pieces);
+        const int b = lo + static_cast<int>(static_cast<int64_t>(hi - lo) * (p + 1) / pieces);
+        if (a >= b) continue;
+        next.insert(next.end(), t, t + kTaskInts);
+        next[next.size() - kTaskInts + 4] = a;
+        next[next.size() - kTaskInts + 5] = b;
+      }
+    }
+    const int64_t ntask = static_cast<int64_t>(next.size() / kTaskInts);
+    HIP_OR_RETURN(g->tq.ensure(sizeof(int) * next.size()), "relaunch queue");
+    HIP_OR_RETURN(hipMemcpyAsync(g->tq.p, next.data(), sizeof(int) * next.size(), hipMemcpyHostToDevice, s),
+                  "relaunch queue");
+    S.tq = g->tq.as<int>();
+    S.nq = ntask;
+    S.qroot = S.qlo = S.qhi = S.qstat = nullptr;
+    S.qbounds = nullptr;
+    S.nchunks = 0;
+    S.chunk = 1;
+    if (launch >= kMaxRelaunch) S.stop_trigger = S.waves + 1;  // the last launch runs to the end
+    g_last_launches = launch + 1;
+    // relaunch: scheduler words cleared, counters and records kept
+    e = launch_fill_u64(P.ctrl, P.ctrl_words, 0ull, s);
+    if (e == hipSuccess) e = P.clique ? launch_clique(P.ca, P.grid, P.lds, s) : launch_motif(P.ma, P.grid, P.lds, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(host_out, P.out_dev, sizeof(uint64_t) * P.out_count, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(flags, P.flags_dev, 2 * sizeof(int), hipMemcpyDeviceToHost, s);
+  }
+  return check_flags(acc_flags);
 }
 
 // queue of explicit roots (original ids), optionally mapped into rank space
@@ -743,6 +869,23 @@ int size_grid(int per_cu, int64_t nnz) {
   return static_cast<int>(std::min<int64_t>(full, cap));
 }
 
+// Host-driven balancing (Section IV-D): the spill array for the tasks busy
+// waves leave behind when the launch is stopped, and the stop trigger: the
+// launch stops once fewer than a fraction `active` of its waves are still
+// busy and the queue is drained (the paper's thresholds: 40% of the warps for
+// cliques, 10% for motifs; dm_options.rebalance overrides).
+dm_status prepare_host_balance(dm_graph* g, const Opt& o, int k, int grid, bool clique, Sched* S) {
+  if (!S->host_bal) return DM_OK;
+  const float active = o.rebalance > 0.f ? o.rebalance : (clique ? 0.4f : 0.1f);
+  int trig = grid - static_cast<int>(active * grid);
+  S->stop_trigger = trig < 1 ? 1 : trig;
+  S->spill_cap = grid * 4 * (k + 1) + 1024;
+  HIP_OR_RETURN(g->spill.ensure(sizeof(int) * static_cast<size_t>(S->spill_cap) * kTaskInts), "workspace");
+  S->spill = g->spill.as<int>();
+  if (!S->qbounds) S->chunk = 1;
+  return DM_OK;
+}
+
 dm_status prepare_clique(dm_graph* g, int k, const Opt& o, hipStream_t s, const int32_t* root_graph, int ngraphs,
                          Prepared* P) {
   dm_status st = ensure_dag(g, s);
@@ -760,6 +903,8 @@ dm_status prepare_clique(dm_graph* g, int k, const Opt& o, hipStream_t s, const 
   HIP_OR_RETURN(g->out.ensure(sizeof(uint64_t) * ngraphs), "workspace");
   Sched S = make_sched(g, o, grid, g->n, nullptr, nullptr);
   st = build_queue(g, o, grid, s, &S);
+  if (st != DM_OK) return st;
+  st = prepare_host_balance(g, o, k, grid, true, &S);
   if (st != DM_OK) return st;
   std::memset(&P->ca, 0, sizeof(P->ca));
   CliqueArgs& A = P->ca;
@@ -841,8 +986,12 @@ dm_status prepare_motif(dm_graph* g, int k, const Opt& o, hipStream_t s, const i
   HIP_OR_RETURN(g->ext_vert.ensure(sizeof(int32_t) * static_cast<size_t>(grid) * cap_total), "workspace");
   HIP_OR_RETURN(g->ext_mask.ensure(static_cast<size_t>(grid) * cap_total), "workspace");
   HIP_OR_RETURN(g->newbuf.ensure(sizeof(int32_t) * static_cast<size_t>(grid) * dmax), "workspace");
+  if (k == 8)  // class counters do not fit LDS: one row per wave in global memory
+    HIP_OR_RETURN(g->wave_cnt.ensure(sizeof(uint64_t) * static_cast<size_t>(grid) * T->ncls), "workspace");
   Sched S = make_sched(g, o, grid, g->n, nullptr, nullptr);
   st = build_queue(g, o, grid, s, &S);
+  if (st != DM_OK) return st;
+  st = prepare_host_balance(g, o, k, grid, false, &S);
   if (st != DM_OK) return st;
   A.rp = g->urp.as<int64_t>();
   A.col = g->ucol.as<int32_t>();
@@ -862,6 +1011,7 @@ dm_status prepare_motif(dm_graph* g, int k, const Opt& o, hipStream_t s, const i
   A.new_buf = g->newbuf.as<int32_t>();
   A.wave_ext_cap = cap_total;
   A.leaf_lds = 1;
+  A.wave_cnt = k == 8 ? g->wave_cnt.as<unsigned long long>() : nullptr;
   A.S = S;
   P->clique = false;
   P->grid = grid;
@@ -1005,6 +1155,8 @@ dm_status run_dfs(dm_graph* g, int op, int k, const Opt& o, hipStream_t s, uint6
     dmax = g->ddmax > 0 ? g->ddmax : 1;
     A.lane_stride = static_cast<int64_t>(k > 3 ? k - 3 : 1) * dmax;
   } else {
+    // the lane kernel keeps one wave's class counters in LDS: 853 fit, 11,117 do not
+    if (k > 7) return fail(DM_E_K, "DM_IMPL_DFS counts motifs up to k = 7");
     uint16_t* dtab = nullptr;
     HIP_OR_RETURN(device_table(k, &dtab), "class table upload");
     dm_status st = ensure_ranked(g, s);
@@ -1072,7 +1224,7 @@ extern "C" dm_status dm_count_cliques(dm_graph* g, int k, uint64_t* out_count, c
   apply_tuning(DM_OP_CLIQUE, k, &o);
   Prepared P;
   st = prepare(g, DM_OP_CLIQUE, k, o, s, nullptr, 1, &P);
-  if (st == DM_OK) st = run_prepared(P, s, &c);
+  if (st == DM_OK) st = (o.sched & DM_SCHED_HOST_BALANCE) ? run_host_balanced(g, P, s, &c) : run_prepared(P, s, &c);
   if (st == DM_OK) *out_count = c;
   return st;
 }
@@ -1080,7 +1232,7 @@ extern "C" dm_status dm_count_cliques(dm_graph* g, int k, uint64_t* out_count, c
 extern "C" dm_status dm_count_motifs(dm_graph* g, int k, uint64_t* out_counts, size_t out_len, const dm_options* opt) {
   if (!g || !out_counts) return fail(DM_E_ARG, "null graph or output");
   const ClassTables* T = tables(k);
-  if (!T) return fail(DM_E_K, "motif k must be in 3..7");
+  if (!T) return fail(DM_E_K, "motif k must be in 3..8");
   if (out_len < static_cast<size_t>(T->ncls)) return fail(DM_E_BUFSZ, "out_len < number of classes");
   Opt o;
   dm_status st = read_opt(opt, &o);
@@ -1096,7 +1248,8 @@ extern "C" dm_status dm_count_motifs(dm_graph* g, int k, uint64_t* out_counts, s
   apply_tuning(DM_OP_MOTIF, k, &o);
   Prepared P;
   st = prepare(g, DM_OP_MOTIF, k, o, s, nullptr, 1, &P);
-  if (st == DM_OK) st = run_prepared(P, s, tmp.data());
+  if (st == DM_OK)
+    st = (o.sched & DM_SCHED_HOST_BALANCE) ? run_host_balanced(g, P, s, tmp.data()) : run_prepared(P, s, tmp.data());
   if (st == DM_OK) std::memcpy(out_counts, tmp.data(), sizeof(uint64_t) * T->ncls);
   return st;
 }
@@ -1131,15 +1284,16 @@ constexpr size_t kScratchCtrl = align256(sizeof(uint16_t) << 20);
 extern "C" dm_status dm_count_motifs_static(dm_graph* g, int k, uint64_t* out_counts, size_t out_len,
                                             const dm_options* opt) {
   if (!g || !out_counts) return fail(DM_E_ARG, "null graph or output");
-  const ClassTables* T = tables(k);
-  if (!T) return fail(DM_E_K, "motif k must be in 3..7");
+  // k = 8's dictionary (256 MiB) does not fit the static array
+  const ClassTables* T = k <= 7 ? tables(k) : nullptr;
+  if (!T) return fail(DM_E_K, "dm_count_motifs_static: motif k must be in 3..7");
   if (out_len < static_cast<size_t>(T->ncls)) return fail(DM_E_BUFSZ, "out_len < number of classes");
   Opt o;
   dm_status st = read_opt(opt, &o);
   if (st != DM_OK) return st;
-  if (o.sched & (DM_SCHED_LEARNED | DM_SCHED_COST | DM_IMPL_DFS) || o.roots)
+  if (o.sched & (DM_SCHED_LEARNED | DM_SCHED_COST | DM_IMPL_DFS | DM_SCHED_HOST_BALANCE) || o.roots)
     return fail(DM_E_ARG, "dm_count_motifs_static runs the plain root queue over every root (no learned or "
-                          "cost ordering, root list or DFS ablation)");
+                          "cost ordering, root list, host-driven balancing or DFS ablation)");
   if (!g->ranked)
     return fail(DM_E_ARG, "dm_count_motifs_static needs the rank-renamed graph: load it with DM_CSR_RANK "
                           "(or count its motifs once with dm_count_motifs)");
@@ -1269,7 +1423,7 @@ extern "C" dm_status dm_list(dm_graph* g, int op, int k, dm_sink_fn sink, void* 
     if (k < 1 || k > kMaxK) return fail(DM_E_K, "clique k must be in 1..32");
   } else {
     T = tables(k);
-    if (!T) return fail(DM_E_K, "motif k must be in 3..7");
+    if (!T) return fail(DM_E_K, "motif k must be in 3..8");
   }
   Opt o;
   dm_status st = read_opt(opt, &o);
@@ -1408,6 +1562,55 @@ extern "C" dm_status dm_list(dm_graph* g, int op, int k, dm_sink_fn sink, void* 
   st = check_flags(flags);
   if (st != DM_OK) return st;
   *out_total = tail;
+  return DM_OK;
+}
+
+// ====================================================================== property filters
+
+extern "C" dm_status dm_induced_subgraph(dm_graph* g, const uint8_t* keep, void* stream, dm_graph** out) {
+  if (!out) return fail(DM_E_ARG, "null output handle");
+  *out = nullptr;
+  if (!g || (!keep && g->n > 0)) return fail(DM_E_ARG, "null graph or keep array");
+  hipStream_t s = pick_stream(g, stream);
+  const size_t n1 = static_cast<size_t>(g->n) + 1;
+  Buf dkeep, newid, srp;
+  HIP_OR_RETURN(dkeep.ensure(n1), "dm_induced_subgraph: allocate");
+  HIP_OR_RETURN(newid.ensure(sizeof(int64_t) * n1), "dm_induced_subgraph: allocate");
+  HIP_OR_RETURN(srp.ensure(sizeof(int64_t) * n1), "dm_induced_subgraph: allocate");
+  if (g->n > 0)
+    HIP_OR_RETURN(hipMemcpyAsync(dkeep.p, keep, static_cast<size_t>(g->n), hipMemcpyHostToDevice, s),
+                  "dm_induced_subgraph: copy");
+  int32_t* scol = nullptr;
+  int32_t n2 = 0;
+  int64_t nnz2 = 0;
+  if (g->n > 0)
+    HIP_OR_RETURN(induced_subgraph(g->rp.as<int64_t>(), g->col.as<int32_t>(), g->n, dkeep.as<uint8_t>(),
+                                   newid.as<int64_t>(), srp.as<int64_t>(), &scol, &n2, &nnz2, s),
+                  "dm_induced_subgraph");
+  else
+    HIP_OR_RETURN(hipMemsetAsync(srp.p, 0, sizeof(int64_t), s), "dm_induced_subgraph");
+  // (with no edges no column is read; a placeholder pointer keeps the call valid)
+  int32_t none = 0;
+  const dm_status st = dm_load_csr(n2, srp.as<int64_t>(), scol ? scol : &none, DM_CSR_DEVICE | DM_CSR_TRUSTED,
+                                   stream, out);
+  if (scol) (void)hipFree(scol);
+  return st;
+}
+
+extern "C" dm_status dm_count_quasi_cliques(dm_graph* g, int k, int min_edges, uint64_t* out_count,
+                                            const dm_options* opt) {
+  if (!g || !out_count) return fail(DM_E_ARG, "null graph or output");
+  const ClassTables* T = tables(k);
+  if (!T) return fail(DM_E_K, "quasi-cliques: k must be in 3..8");
+  if (min_edges < 0 || min_edges > k * (k - 1) / 2) return fail(DM_E_ARG, "min_edges outside 0..k(k-1)/2");
+  std::vector<uint64_t> c(T->ncls);
+  const dm_status st = dm_count_motifs(g, k, c.data(), c.size(), opt);
+  if (st != DM_OK) return st;
+  uint64_t sum = 0;
+  for (int q = 0; q < T->ncls; ++q)
+    if (__builtin_popcount(T->canon[q]) >= min_edges && __builtin_add_overflow(sum, c[q], &sum))
+      return fail(DM_E_OVERFLOW, "quasi-clique sum wrapped");
+  *out_count = sum;
   return DM_OK;
 }
 
@@ -1610,7 +1813,7 @@ extern "C" dm_status dm_batch(dm_graph* const* gs, int32_t num_graphs, int op, i
     if (k < 1 || k > kMaxK) return fail(DM_E_K, "clique k must be in 1..32");
   } else {
     const ClassTables* T = tables(k);
-    if (!T) return fail(DM_E_K, "motif k must be in 3..7");
+    if (!T) return fail(DM_E_K, "motif k must be in 3..8");
     width = T->ncls;
   }
   if (out_len < static_cast<size_t>(num_graphs) * width) return fail(DM_E_BUFSZ, "out_len < num_graphs * width");
@@ -1622,6 +1825,7 @@ extern "C" dm_status dm_batch(dm_graph* const* gs, int32_t num_graphs, int op, i
   if (o.roots) return fail(DM_E_ARG, "root lists are not supported in batches");
   if (o.sched & DM_SCHED_COST) return fail(DM_E_ARG, "cost ordering takes one graph's costs; not for batches");
   if (o.sched & DM_IMPL_DFS) return fail(DM_E_ARG, "DM_IMPL_DFS runs single graphs");
+  if (o.sched & DM_SCHED_HOST_BALANCE) return fail(DM_E_ARG, "DM_SCHED_HOST_BALANCE runs single graphs");
   if ((o.sched & DM_SCHED_LEARNED) && !o.mlp) return fail(DM_E_MODEL, "DM_SCHED_LEARNED needs mlp parameters");
   return batch_run(gs, num_graphs, op, k, width, o, out_counts);
 }
@@ -1756,7 +1960,8 @@ extern "C" dm_status dm_autotune(dm_graph* const* gs, int32_t num_graphs, int op
   if (st != DM_OK) return st;
   if (o.roots) return fail(DM_E_ARG, "tuning runs over every root");
   if ((o.sched & DM_SCHED_COST) && num_graphs > 1) return fail(DM_E_ARG, "cost ordering takes one graph's costs");
-  if (o.sched & DM_IMPL_DFS) return fail(DM_E_ARG, "the tuner times the wave kernels");
+  if (o.sched & (DM_IMPL_DFS | DM_SCHED_HOST_BALANCE))
+    return fail(DM_E_ARG, "the tuner times single in-kernel-balanced launches");
   if ((o.sched & DM_SCHED_LEARNED) && !o.mlp) return fail(DM_E_MODEL, "DM_SCHED_LEARNED needs mlp parameters");
   Tuning t;
   if (num_graphs == 1) {

@@ -565,6 +565,7 @@ __device__ __forceinline__ void flush_graph(const CliqueArgs& A, WaveAcc& W) {
 }
 
 // rows_g: this wave's global region for the rows of roots too wide for LDS
+template <bool kHostBal>
 __device__ void run_task(const CliqueArgs& A, const CliqueLds& L, uint64_t* rows_g, const Task& t,
                          WaveAcc& WA, int wave_gid) {
   const int lane = lane_id();
@@ -853,8 +854,21 @@ __device__ void run_task(const CliqueArgs& A, const CliqueLds& L, uint64_t* rows
             if (!fast) wave_sync();
           }
         }
-        // ---- donation (Section IV-D redistribute, done by the busy wave)
-        if (A.S.donate && (++steps % A.S.period) == 0 && sched_want_donation(A.S)) {
+        // ---- host-driven balancing: once the launch is stopped, the untried
+        // extensions of every open level become tasks for the next launch
+        // (checked every `period` steps without a pending solver job)
+        if (kHostBal) {
+          if (!job && (++steps % A.S.period) == 0 && sched_stopped(A.S)) {
+            wave_sync();
+            for (int s = s0; s <= depth; ++s) {
+              const int from = L.cur[s] + 1, to = L.hiv[s];
+              if (count_bits(L.stk + s * W, from, to) > 0)
+                sched_spill(A.S, task_payload(v, t.stat, s, from, to, L.cur));
+            }
+            break;
+          }
+        } else if (A.S.donate && (++steps % A.S.period) == 0 && sched_want_donation(A.S)) {
+          // ---- donation (Section IV-D redistribute, done by the busy wave)
           wave_sync();
           for (int s = s0; s <= depth; ++s) {
             const int from = L.cur[s] + 1, to = L.hiv[s];
@@ -890,6 +904,9 @@ __device__ void run_task(const CliqueArgs& A, const CliqueLds& L, uint64_t* rows
 
 // 4 waves per SIMD: the register budget (128 VGPRs) this needs holds the
 // kernel without spills and is what keeps row-read latency covered
+// (instantiated with kHostBal for launches under host-driven balancing, so
+// the default kernel carries none of that code)
+template <bool kHostBal>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) clique_kernel(CliqueArgs A) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int lane = lane_id();
@@ -908,11 +925,11 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4)))
   SchedIter it;
   sched_begin(A.S, it);
   Task t;
-  while (sched_next(A.S, it, wave_gid, L.cur, &t)) {
-    run_task(A, L, rows_g, t, WA, wave_gid);
+  while (sched_next<kHostBal>(A.S, it, wave_gid, L.cur, &t)) {
+    run_task<kHostBal>(A, L, rows_g, t, WA, wave_gid);
     WA.tasks++;
   }
-  sched_end(A.S);
+  sched_end<kHostBal>(A.S);
   const uint64_t t_idle = it.t_idle;
   flush_graph(A, WA);
   if (lane == 0 && WA.ovf) atomicOr(A.flags, 1);
@@ -940,11 +957,14 @@ size_t clique_lds_bytes(int dmax, int W, int k) {
 }
 
 hipError_t clique_occupancy(size_t lds_bytes, int* blocks_per_cu) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, clique_kernel, 64, lds_bytes);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, clique_kernel<false>, 64, lds_bytes);
 }
 
 hipError_t launch_clique(const CliqueArgs& a, int grid, size_t lds_bytes, hipStream_t s) {
-  hipLaunchKernelGGL(clique_kernel, dim3(grid), dim3(64), lds_bytes, s, a);
+  if (a.S.host_bal)
+    hipLaunchKernelGGL(clique_kernel<true>, dim3(grid), dim3(64), lds_bytes, s, a);
+  else
+    hipLaunchKernelGGL(clique_kernel<false>, dim3(grid), dim3(64), lds_bytes, s, a);
   return hipGetLastError();
 }
 

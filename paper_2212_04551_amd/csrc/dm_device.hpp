@@ -163,6 +163,18 @@ struct Sched {
   int waves;                  // waves in the launch
   uint64_t wait_limit;        // wall-clock ticks an idle wave may wait for work before it gives up
   int* flags;                 // flags[1] |= kFlagWaitLimit when a wave gives up
+  // Host-driven balancing (Section IV-D's stop / copy / redistribute /
+  // relaunch cycle; donation is off): once `stop_trigger` waves have found
+  // the queue drained, the launch is stopped; busy waves write their untried
+  // work as tasks into `spill` and leave, and the host relaunches with those
+  // tasks (in `tq`) as the queue.
+  int host_bal;               // 1: this launch stops and spills
+  int stop_trigger;           // idle waves that stop the launch
+  int* stop;                  // stop word (device)
+  int* spill_n;               // tasks spilled so far (device)
+  int* spill;                 // spill_cap tasks of kTaskInts ints
+  int spill_cap;
+  const int* tq;              // queue of tasks (kTaskInts ints each) instead of roots; null = roots
 };
 
 // flags[1] bit set by a wave that gave up waiting (the launch's counts are
@@ -386,22 +398,56 @@ __device__ __forceinline__ void sched_begin(const Sched& S, SchedIter& it) {
   if (lane_id() == 0) add_u64(S.state, kActiveOne);
 }
 
+template <bool kHostBal = false>
 __device__ __forceinline__ void sched_go_idle(const Sched& S, SchedIter& it) {
   if (lane_id() == 0) {
-    add_i32(S.idle, 1);
+    const int before = add_i32(S.idle, 1);
     add_u64(S.state, 0ull - kActiveOne);
+    if (kHostBal && S.host_bal && before + 1 >= S.stop_trigger) st_relaxed(S.stop, 1);
   }
   it.mode = 1;
   it.t0 = wall_clock64();
 }
 
+// Host-driven balancing: has the launch been stopped?  (one relaxed load)
+__device__ __forceinline__ bool sched_stopped(const Sched& S) {
+  int v = 0;
+  if (lane_id() == 0) v = ld_relaxed(S.stop);
+  return uni(v) != 0;
+}
+
+// Host-driven balancing: write one task (payload in `data`, lane i holds int
+// i) to the spill array; a full array flags the launch (flags[1] bit 16).
+__device__ __forceinline__ void sched_spill(const Sched& S, int data_lane) {
+  const int lane = lane_id();
+  int slot = 0;
+  if (lane == 0) slot = add_i32(S.spill_n, 1);
+  slot = uni(slot);
+  if (slot >= S.spill_cap) {
+    if (lane == 0) atomicOr(S.flags + 1, 16);
+    return;
+  }
+  if (lane < kTaskInts) S.spill[static_cast<int64_t>(slot) * kTaskInts + lane] = data_lane;
+}
+
 // Next unit of work into *t; false when the whole launch has drained.
+// kHostBal: the instantiation of kernels launched with host-driven balancing
+// (queues of spilled tasks, the stop trigger); the others compile without it.
+template <bool kHostBal = false>
 __device__ __forceinline__ bool sched_next(const Sched& S, SchedIter& it, int wave_gid, int* prefix_lds, Task* t) {
   for (;;) {
     if (it.q < it.e) {
       if (S.donate && it.e - it.q >= 2 && sched_want_donation(S)) {
         const int64_t mid = it.q + (it.e - it.q + 1) / 2;
         if (sched_publish(S, task_range_payload(mid, it.e), wave_gid)) it.e = mid;
+      }
+      if (kHostBal && S.tq) {
+        // a task written by an earlier, stopped launch
+        const int lane = lane_id();
+        const int data = lane < kTaskInts ? S.tq[it.q * kTaskInts + lane] : 0;
+        ++it.q;
+        *t = task_unpack(data, prefix_lds);
+        return true;
       }
       *t = sched_entry(S, it.q, INT_MAX);
       ++it.q;
@@ -414,8 +460,8 @@ __device__ __forceinline__ bool sched_next(const Sched& S, SchedIter& it, int wa
         it.e = e;
         continue;
       }
-      sched_go_idle(S, it);
-      if (!S.donate) return false;
+      sched_go_idle<kHostBal>(S, it);
+      if (!S.donate) return false;  // also with host-driven balancing, where donation is off
       continue;
     }
     if (it.mode == 2) {
@@ -456,9 +502,13 @@ __device__ __forceinline__ bool sched_next(const Sched& S, SchedIter& it, int wa
   }
 }
 
-// Leave the loop: the wave counted itself idle when the work ran out.
+// Leave the loop: the wave counted itself idle when the work ran out.  Under
+// host-driven balancing the count is left as it is: waves leave as soon as
+// they run out of work, and the stop trigger counts the waves that have
+// finished.
+template <bool kHostBal = false>
 __device__ __forceinline__ void sched_end(const Sched& S) {
-  if (lane_id() == 0) add_i32(S.idle, -1);
+  if (!kHostBal && lane_id() == 0) add_i32(S.idle, -1);
 }
 
 }  // namespace dm

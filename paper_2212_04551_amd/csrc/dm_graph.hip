@@ -399,4 +399,84 @@ done:
   return err;
 }
 
+// ------------------------------------------------------------------ vertex property filter
+
+namespace {
+
+__global__ void keep_flag_kernel(const uint8_t* keep, int32_t n, int64_t* flag) {
+  const int64_t v = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (v < n) flag[v] = keep[v] ? 1 : 0;
+  if (v == n) flag[n] = 0;
+}
+
+// kept neighbours of each kept vertex, at its new id
+__global__ void sub_degree_kernel(const int64_t* rp, const int32_t* col, int32_t n, const uint8_t* keep,
+                                  const int64_t* newid, int64_t* deg) {
+  const int64_t v = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (v >= n || !keep[v]) return;
+  int64_t c = 0;
+  for (int64_t e = rp[v]; e < rp[v + 1]; ++e) c += keep[col[e]] ? 1 : 0;
+  deg[newid[v]] = c;
+}
+
+// new adjacency lists: kept neighbours renamed, still ascending (new ids keep the old order)
+__global__ void sub_fill_kernel(const int64_t* rp, const int32_t* col, int32_t n, const uint8_t* keep,
+                                const int64_t* newid, const int64_t* srp, int32_t* scol) {
+  const int64_t v = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (v >= n || !keep[v]) return;
+  int64_t o = srp[newid[v]];
+  for (int64_t e = rp[v]; e < rp[v + 1]; ++e)
+    if (keep[col[e]]) scol[o++] = static_cast<int32_t>(newid[col[e]]);
+}
+
+}  // namespace
+
+// Induced subgraph on the vertices with keep[v] != 0.  newid[n+1] (exclusive
+// prefix of keep) and srp[n+1] are caller buffers; *n_out / *nnz_out come back
+// to the host; scol is allocated here (caller frees, hipFree) when nnz_out > 0.
+hipError_t induced_subgraph(const int64_t* rp, const int32_t* col, int32_t n, const uint8_t* keep, int64_t* newid,
+                            int64_t* srp, int32_t** scol, int32_t* n_out, int64_t* nnz_out, hipStream_t s) {
+  hipError_t err = hipSuccess;
+  void* temp = nullptr;
+  int64_t* flag = nullptr;
+  size_t tb = 0, tb2 = 0;
+  *scol = nullptr;
+  int64_t n2 = 0, nnz2 = 0;
+  DM_TRY(hipMalloc(&flag, sizeof(int64_t) * (static_cast<size_t>(n) + 1)));
+  hipLaunchKernelGGL(keep_flag_kernel, dim3(blocks_for(n + 1, 256)), dim3(256), 0, s, keep, n, flag);
+  DM_TRY(hipGetLastError());
+  DM_TRY(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, flag, newid, n + 1, s));
+  DM_TRY(hipcub::DeviceScan::ExclusiveSum(nullptr, tb2, flag, srp, n + 1, s));
+  DM_TRY(hipMalloc(&temp, (tb > tb2 ? tb : tb2) + 16));
+  DM_TRY(hipcub::DeviceScan::ExclusiveSum(temp, tb, flag, newid, n + 1, s));
+  DM_TRY(hipMemcpyAsync(&n2, newid + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  DM_TRY(hipStreamSynchronize(s));
+  // degrees at new ids (flag reused), then their exclusive prefix
+  hipLaunchKernelGGL(fill_u64_kernel, dim3(blocks_for(n2 + 1, 256)), dim3(256), 0, s,
+                     reinterpret_cast<unsigned long long*>(flag), n2 + 1, 0ull);
+  DM_TRY(hipGetLastError());
+  hipLaunchKernelGGL(sub_degree_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, rp, col, n, keep, newid, flag);
+  DM_TRY(hipGetLastError());
+  DM_TRY(hipcub::DeviceScan::ExclusiveSum(temp, tb2, flag, srp, static_cast<int>(n2 + 1), s));
+  DM_TRY(hipMemcpyAsync(&nnz2, srp + n2, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  DM_TRY(hipStreamSynchronize(s));
+  if (nnz2 > 0) {
+    DM_TRY(hipMalloc(scol, sizeof(int32_t) * static_cast<size_t>(nnz2)));
+    hipLaunchKernelGGL(sub_fill_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, rp, col, n, keep, newid, srp,
+                       *scol);
+    DM_TRY(hipGetLastError());
+  }
+  DM_TRY(hipStreamSynchronize(s));
+  *n_out = static_cast<int32_t>(n2);
+  *nnz_out = nnz2;
+done:
+  if (temp) (void)hipFree(temp);
+  if (flag) (void)hipFree(flag);
+  if (err != hipSuccess && *scol) {
+    (void)hipFree(*scol);
+    *scol = nullptr;
+  }
+  return err;
+}
+
 }  // namespace dm

@@ -14,10 +14,10 @@ namespace dm {
 constexpr int kMlpNet = 4 * 64 + 64 + 64 * 64 + 64 + 64 + 1;  // 4545 weights
 constexpr int kMlpBlob = kMlpNet + 8;                          // + feature mean[4], std[4]
 
-// Largest motif size: the canonical-relabeling dictionary of k = 7 has
-// 2^20 entries of 16-bit class ids (853 classes); entries whose code some
+// Largest motif size: the canonical-relabeling dictionary of k = 8 has
+// 2^27 entries of 16-bit class ids (11,117 classes); entries whose code some
 // v_i reaches with no edge to its predecessors hold kUnreachable.
-constexpr int kMotifMaxK = 7;
+constexpr int kMotifMaxK = 8;
 constexpr uint16_t kUnreachable = 0xFFFF;
 
 // Roots with at most this many out-neighbours keep their bitmap rows in LDS;
@@ -68,6 +68,7 @@ struct MotifArgs {
   int64_t level_off[8];    // start of level s inside a wave's region
   int64_t level_cap[8];
   int leaf_lds;            // the (k-2)-level list may be built straight into LDS (counting)
+  unsigned long long* wave_cnt;  // k = 8: per-wave class counters in global memory (ncls per wave)
   Sched S;
 };
 
@@ -204,6 +205,9 @@ hipError_t relabel_by_rank(const int64_t* rp, const int32_t* col, int32_t n, int
 hipError_t launch_max_degree(const int64_t* rp, int32_t n, int* out, hipStream_t s);
 // map vertex ids through a table: out[i] = map[in[i]]
 hipError_t launch_gather_i32(const int32_t* map, const int32_t* in, int32_t* out, int64_t count, hipStream_t s);
+// induced subgraph on the vertices with keep[v] != 0 (device keep[n]); see dm_graph.hip
+hipError_t induced_subgraph(const int64_t* rp, const int32_t* col, int32_t n, const uint8_t* keep, int64_t* newid,
+                            int64_t* srp, int32_t** scol, int32_t* n_out, int64_t* nnz_out, hipStream_t s);
 hipError_t row_cache_layout(const int64_t* drp, int32_t n, int64_t* off, int64_t* total, hipStream_t s);
 // offset copy: out[i] = in[i] + off (int64 row offsets) / (int32 column ids)
 hipError_t launch_offset_i64(const int64_t* in, int64_t* out, int64_t count, int64_t off, hipStream_t s);

@@ -115,6 +115,8 @@ struct MotifLds {
 
 __device__ __forceinline__ int off_of(int i) { return i * (i - 1) / 2 - 1; }  // bitmap field of v_i, i >= 2
 
+// Class counters per wave: in LDS for k <= 7; k = 8's 11,117 counters live
+// in a per-wave row of global memory (kBins == 64).
 template <int kBins>
 __device__ MotifLds carve(unsigned char* smem, int ncls) {
   MotifLds L;
@@ -124,7 +126,7 @@ __device__ MotifLds carve(unsigned char* smem, int ncls) {
     off += (bytes + 15) & ~static_cast<size_t>(15);
     return p;
   };
-  L.cnt = reinterpret_cast<unsigned long long*>(take(static_cast<size_t>(ncls) * 8));
+  L.cnt = kBins == 64 ? nullptr : reinterpret_cast<unsigned long long*>(take(static_cast<size_t>(ncls) * 8));
   L.adj = reinterpret_cast<unsigned long long*>(take(kBins * kBins * 8));
   L.nw = reinterpret_cast<unsigned long long*>(take(kBins * 8));
   L.ccount = reinterpret_cast<unsigned*>(take(2 * kBins * 4));
@@ -162,15 +164,24 @@ struct MotifWave {
   int32_t* vert;  // this wave's extension region
   uint8_t* mask;
   int32_t* nbuf;
+  unsigned long long* gcnt;  // k = 8: this wave's class counters in global memory
 };
 
+template <int kBins>
+__device__ __forceinline__ unsigned long long* class_counters(const MotifLds& L, const MotifWave& MW) {
+  if constexpr (kBins == 64) return MW.gcnt;
+  else return L.cnt;
+}
+
+template <int kBins>
 __device__ __forceinline__ void flush_counts(const MotifArgs& A, const MotifLds& L, MotifWave& MW) {
   const int lane = lane_id();
+  unsigned long long* cnt = class_counters<kBins>(L, MW);
   wave_sync();
   for (int c = lane; c < A.ncls; c += kWave) {
-    const unsigned long long v = L.cnt[c];
+    const unsigned long long v = cnt[c];
     if (MW.cur_g >= 0) add_counter(A.out + static_cast<size_t>(MW.cur_g) * A.ncls + c, v, A.flags);
-    L.cnt[c] = 0;
+    cnt[c] = 0;
   }
   wave_sync();
 }
@@ -368,8 +379,8 @@ __device__ __forceinline__ int leaf_level(const MotifArgs& A, const MotifLds& L,
   const unsigned low = static_cast<unsigned>(nm - 1);
   const int v0 = L.tr[0];
   for (int i = lane; i < kBins * kBins; i += kWave) L.adj[i] = 0;
-  if (lane < kBins) L.nw[lane] = 0;
-  if (lane < 2 * kBins) L.ccount[lane] = 0;
+  for (int i = lane; i < kBins; i += kWave) L.nw[i] = 0;
+  for (int i = lane; i < 2 * kBins; i += kWave) L.ccount[i] = 0;
   wave_sync();
   for (int c = lo; c < hi; c += kWave) {
     // ---- slice: canonical entries and a prefix sum of their degrees
@@ -490,12 +501,13 @@ __device__ __forceinline__ int leaf_level(const MotifArgs& A, const MotifLds& L,
   const int code_tr = L.code[s];
   const int fx = s >= 2 ? off_of(s) : 0;  // v_1's field is implied
   const int fy = off_of(s + 1);
+  unsigned long long* cnt = class_counters<kBins>(L, MW);
   auto add_class = [&](int code, uint64_t h) {
     const int cls = A.table[code];
     if (cls == kUnreachable) {
       atomicOr(A.flags + 1, 2);
     } else {
-      const unsigned long long old = atomicAdd(&L.cnt[cls], static_cast<unsigned long long>(h));
+      const unsigned long long old = atomicAdd(&cnt[cls], static_cast<unsigned long long>(h));
       if (old + h < old) MW.ovf = 1;
     }
     leaves_l += h;
@@ -536,14 +548,14 @@ __device__ __forceinline__ int next_canonical(const MotifArgs& A, const MotifLds
   return -1;
 }
 
-template <int kBins>
+template <int kBins, bool kHostBal>
 __device__ __forceinline__ void run_task(const MotifArgs& A, const MotifLds& L, MotifWave& MW, const Task& t, int wave_gid) {
   const int lane = lane_id();
   const int k = A.k;
   const int v0 = t.root;
   const int g = A.root_graph ? A.root_graph[v0] : 0;
   if (g != MW.cur_g) {
-    flush_counts(A, L, MW);
+    flush_counts<kBins>(A, L, MW);
     MW.cur_g = g;
   }
   uint64_t nodes_l = 0, leaves_l = 0, reads_l = 0;
@@ -612,8 +624,18 @@ __device__ __forceinline__ void run_task(const MotifArgs& A, const MotifLds& L, 
         if (lane == 0) { L.cursor[s] = 0; L.endv[s] = L.esize[s]; }
         wave_sync();
       }
-      // ---- donation of untried extensions at the shallowest level
-      if (A.S.donate && (++steps % A.S.period) == 0 && sched_want_donation(A.S)) {
+      // ---- host-driven balancing: once the launch is stopped, the untried
+      // extensions of every open level become tasks for the next launch
+      if (kHostBal) {
+        if ((++steps % A.S.period) == 0 && sched_stopped(A.S)) {
+          for (int q = s0; q <= s; ++q) {
+            const int from = L.cursor[q], to = L.endv[q];
+            if (to > from) sched_spill(A.S, task_payload(v0, t.stat, q, from, to, L.tr));
+          }
+          break;
+        }
+      } else if (A.S.donate && (++steps % A.S.period) == 0 && sched_want_donation(A.S)) {
+        // ---- donation of untried extensions at the shallowest level
         for (int q = s0; q <= s; ++q) {
           const int from = L.cursor[q], to = L.endv[q];
           if (to - from >= 2) {
@@ -645,8 +667,9 @@ __device__ __forceinline__ void run_task(const MotifArgs& A, const MotifLds& L, 
   }
 }
 
-// 4 waves per SIMD (128 VGPRs): enough waves to cover the lookups' latency
-template <int kBins>
+// 4 waves per SIMD (128 VGPRs): enough waves to cover the lookups' latency.
+// kHostBal: the instantiation for launches under host-driven balancing.
+template <int kBins, bool kHostBal>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) motif_kernel(MotifArgs A) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int lane = lane_id();
@@ -660,20 +683,24 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4)))
   MW.vert = A.ext_vert + static_cast<size_t>(wave_gid) * A.wave_ext_cap;
   MW.mask = A.ext_mask + static_cast<size_t>(wave_gid) * A.wave_ext_cap;
   MW.nbuf = A.new_buf + static_cast<size_t>(wave_gid) * A.dmax;
-  for (int c = lane; c < A.ncls; c += kWave) L.cnt[c] = 0;
+  MW.gcnt = A.wave_cnt ? A.wave_cnt + static_cast<size_t>(wave_gid) * A.ncls : nullptr;
+  {
+    unsigned long long* cnt = class_counters<kBins>(L, MW);
+    for (int c = lane; c < A.ncls; c += kWave) cnt[c] = 0;
+  }
   for (int c = lane; c < kFilterWords; c += kWave) L.filt[c] = 0u;
   wave_sync();
   const uint64_t t_begin = wall_clock64();
   SchedIter it;
   sched_begin(A.S, it);
   Task t;
-  while (sched_next(A.S, it, wave_gid, L.tr, &t)) {
-    run_task<kBins>(A, L, MW, t, wave_gid);
+  while (sched_next<kHostBal>(A.S, it, wave_gid, L.tr, &t)) {
+    run_task<kBins, kHostBal>(A, L, MW, t, wave_gid);
     MW.tasks++;
   }
-  sched_end(A.S);
+  sched_end<kHostBal>(A.S);
   const uint64_t t_idle = it.t_idle;
-  flush_counts(A, L, MW);
+  flush_counts<kBins>(A, L, MW);
   if (lane == 0 && MW.ovf) atomicOr(A.flags, 1);
   if (A.wave_stats && wave_gid < A.wave_stats_len && lane == 0) {
     const uint64_t total = wall_clock64() - t_begin;
@@ -782,6 +809,7 @@ __global__ void __launch_bounds__(64) list_motifs_kernel(MotifArgs A, Ring R) {
   MW.vert = A.ext_vert + static_cast<size_t>(wave_gid) * A.wave_ext_cap;
   MW.mask = A.ext_mask + static_cast<size_t>(wave_gid) * A.wave_ext_cap;
   MW.nbuf = A.new_buf + static_cast<size_t>(wave_gid) * A.dmax;
+  MW.gcnt = nullptr;
   SchedIter it;
   sched_begin(A.S, it);
   Task t;
@@ -792,12 +820,12 @@ __global__ void __launch_bounds__(64) list_motifs_kernel(MotifArgs A, Ring R) {
 
 }  // namespace
 
-int motif_bins(int k) { return k <= 6 ? 16 : 32; }
+int motif_bins(int k) { return k <= 6 ? 16 : (k == 7 ? 32 : 64); }
 
 size_t motif_lds_bytes(int k, int ncls) {
   const size_t nb = static_cast<size_t>(motif_bins(k));
   auto a16 = [](size_t x) { return (x + 15) & ~static_cast<size_t>(15); };
-  size_t off = a16(static_cast<size_t>(ncls) * 8) + a16(nb * nb * 8) + a16(nb * 8) + a16(2 * nb * 4);
+  size_t off = (nb == 64 ? 0 : a16(static_cast<size_t>(ncls) * 8)) + a16(nb * nb * 8) + a16(nb * 8) + a16(2 * nb * 4);
   off += a16((kWave + 1) * 8) + a16(kWave * 8) + a16(kWave * 4);
   off += 2 * a16(kSuf * 4) + a16(kSuf * kSuf * 4) + 3 * a16(kSuf * 4);
   off += a16(kLeafLds * 4) + a16(kLeafLds) + a16(kFilterWords * 4) + 16 + a16(kWave * 4);
@@ -806,9 +834,11 @@ size_t motif_lds_bytes(int k, int ncls) {
 }
 
 hipError_t motif_occupancy(int k, size_t lds_bytes, int* blocks_per_cu) {
-  return motif_bins(k) == 16
-             ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, motif_kernel<16>, 64, lds_bytes)
-             : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, motif_kernel<32>, 64, lds_bytes);
+  switch (motif_bins(k)) {
+    case 16: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, motif_kernel<16, false>, 64, lds_bytes);
+    case 32: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, motif_kernel<32, false>, 64, lds_bytes);
+    default: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, motif_kernel<64, false>, 64, lds_bytes);
+  }
 }
 
 size_t motif_list_lds_bytes() { return motif_lds_bytes(3, 1); }
@@ -819,10 +849,20 @@ hipError_t launch_list_motifs(const MotifArgs& a, const Ring& R, int grid, size_
 }
 
 hipError_t launch_motif(const MotifArgs& a, int grid, size_t lds_bytes, hipStream_t s) {
-  if (motif_bins(a.k) == 16)
-    hipLaunchKernelGGL(motif_kernel<16>, dim3(grid), dim3(64), lds_bytes, s, a);
-  else
-    hipLaunchKernelGGL(motif_kernel<32>, dim3(grid), dim3(64), lds_bytes, s, a);
+  const bool hb = a.S.host_bal != 0;
+  switch (motif_bins(a.k)) {
+    case 16:
+      if (hb) hipLaunchKernelGGL((motif_kernel<16, true>), dim3(grid), dim3(64), lds_bytes, s, a);
+      else hipLaunchKernelGGL((motif_kernel<16, false>), dim3(grid), dim3(64), lds_bytes, s, a);
+      break;
+    case 32:
+      if (hb) hipLaunchKernelGGL((motif_kernel<32, true>), dim3(grid), dim3(64), lds_bytes, s, a);
+      else hipLaunchKernelGGL((motif_kernel<32, false>), dim3(grid), dim3(64), lds_bytes, s, a);
+      break;
+    default:
+      if (hb) hipLaunchKernelGGL((motif_kernel<64, true>), dim3(grid), dim3(64), lds_bytes, s, a);
+      else hipLaunchKernelGGL((motif_kernel<64, false>), dim3(grid), dim3(64), lds_bytes, s, a);
+  }
   return hipGetLastError();
 }
 

@@ -25,17 +25,17 @@ DM_CSR_HOST, DM_CSR_DEVICE, DM_CSR_TRUSTED, DM_CSR_ORIENT, DM_CSR_RANK = 0, 1, 2
 DM_SCHED_PLAIN, DM_SCHED_LEARNED, DM_SCHED_AUTOTUNE, DM_RECORD_ROOTS, DM_NO_DONATION = 0, 1, 2, 4, 8
 DM_SCHED_COST = 16
 DM_IMPL_DFS = 32
+DM_SCHED_HOST_BALANCE = 64
 DM_OP_CLIQUE, DM_OP_MOTIF = 0, 1
 DM_MLP_NET = 4 * 64 + 64 + 64 * 64 + 64 + 64 + 1  # 4 -> 64 -> 64 -> 1 weights
 DM_MLP_NPARAMS = DM_MLP_NET + 8                     # + feature mean[4], std[4]
 
 EXPORTS = [
-    "dm_load_csr", "dm_free", "dm_graph_info", "dm_count_cliques",
-    "dm_motif_num_classes",
+    "dm_load_csr", "dm_free", "dm_graph_info", "dm_count_cliques", "dm_motif_num_classes",
     "dm_motif_class_mask", "dm_motif_class_table", "dm_motif_class_table16", "dm_count_motifs",
-    "dm_count_motifs_static", "dm_batch", "dm_list", "dm_strerror",
-    "dm_last_error", "dm_features", "dm_mlp_init", "dm_mlp_fit_normalizer", "dm_mlp_forward", "dm_mlp_targets",
-    "dm_mlp_loss_grad", "dm_mlp_adam_step", "dm_mlp_train", "dm_autotune",
+    "dm_count_motifs_static", "dm_batch", "dm_list", "dm_induced_subgraph", "dm_count_quasi_cliques",
+    "dm_strerror", "dm_last_error", "dm_last_launch_count", "dm_features", "dm_mlp_init", "dm_mlp_fit_normalizer",
+    "dm_mlp_forward", "dm_mlp_targets", "dm_mlp_loss_grad", "dm_mlp_adam_step", "dm_mlp_train", "dm_autotune",
 ]
 
 
@@ -109,9 +109,16 @@ def lib():
     L.dm_list.restype = ctypes.c_int
     L.dm_list.argtypes = [vp, ctypes.c_int, ctypes.c_int, SINK_FN, vp, ctypes.POINTER(ctypes.c_uint64),
                           ctypes.POINTER(dm_options)]
+    L.dm_induced_subgraph.restype = ctypes.c_int
+    L.dm_induced_subgraph.argtypes = [vp, vp, vp, ctypes.POINTER(vp)]
+    L.dm_count_quasi_cliques.restype = ctypes.c_int
+    L.dm_count_quasi_cliques.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64),
+                                         ctypes.POINTER(dm_options)]
     L.dm_batch.restype = ctypes.c_int
     L.dm_batch.argtypes = [ctypes.POINTER(vp), i32, ctypes.c_int, ctypes.c_int, vp, ctypes.c_size_t,
                            ctypes.POINTER(dm_options)]
+    L.dm_last_launch_count.restype = ctypes.c_int
+    L.dm_last_launch_count.argtypes = []
     L.dm_strerror.restype = ctypes.c_char_p
     L.dm_strerror.argtypes = [ctypes.c_int]
     L.dm_last_error.restype = ctypes.c_char_p
@@ -236,6 +243,14 @@ def load_csr(n: int, row_ptr, col, device: bool = False, trusted: bool = False, 
     return DMGraph(h.value)
 
 
+def graph_info(g: DMGraph):
+    """(n, nnz) of a loaded graph."""
+    n = ctypes.c_int32(0)
+    nnz = ctypes.c_int64(0)
+    _check(lib().dm_graph_info(g.handle, ctypes.byref(n), ctypes.byref(nnz)))
+    return int(n.value), int(nnz.value)
+
+
 def load_graph(g, **kw) -> DMGraph:
     """Load a graphgen.Graph (host arrays)."""
     return load_csr(g.n, g.row_ptr, g.col, **kw)
@@ -260,6 +275,11 @@ def count_cliques(g: DMGraph, k: int, **opt) -> int:
     return int(out.value)
 
 
+def last_launch_count() -> int:
+    """Kernel launches of this thread's last counting call (host-driven balancing relaunches)."""
+    return int(lib().dm_last_launch_count())
+
+
 def motif_num_classes(k: int) -> int:
     return int(lib().dm_motif_num_classes(k))
 
@@ -271,6 +291,8 @@ def motif_class_mask(k: int, cls: int) -> int:
 
 
 def motif_class_table(k: int) -> np.ndarray:
+    if not 3 <= k <= 6:
+        _check(lib().dm_motif_class_table(k, None, 0))  # raises DM_E_K
     n = 1 << (k * (k - 1) // 2 - 1)
     out = np.zeros(n, dtype=np.uint8)
     _check(lib().dm_motif_class_table(k, out.ctypes.data, n))
@@ -278,6 +300,8 @@ def motif_class_table(k: int) -> np.ndarray:
 
 
 def motif_class_table16(k: int) -> np.ndarray:
+    if motif_num_classes(k) < 0:
+        _check(lib().dm_motif_class_table16(k, None, 0))  # raises DM_E_K
     n = 1 << (k * (k - 1) // 2 - 1)
     out = np.zeros(n, dtype=np.uint16)
     _check(lib().dm_motif_class_table16(k, out.ctypes.data, n))
@@ -335,6 +359,23 @@ def list_subgraphs(g: DMGraph, op: int, k: int, sink=None, **opt):
     out = np.concatenate(parts) if parts else np.zeros((0, width), dtype=np.int32)
     assert out.shape[0] == total.value
     return out
+
+
+def induced_subgraph(g: DMGraph, keep, stream=None) -> DMGraph:
+    """dm_induced_subgraph: the subgraph on the vertices with keep[v] (host bool / uint8 array)."""
+    k = np.ascontiguousarray(np.asarray(keep, dtype=np.uint8))
+    h = ctypes.c_void_p(None)
+    _check(lib().dm_induced_subgraph(g.handle, k.ctypes.data if k.size else None, _stream(stream), ctypes.byref(h)))
+    return DMGraph(h.value)
+
+
+def count_quasi_cliques(g: DMGraph, k: int, min_edges: int, **opt) -> int:
+    """dm_count_quasi_cliques: connected induced k-subgraphs with >= min_edges edges."""
+    o, keep = make_options(**opt)
+    out = ctypes.c_uint64(0)
+    _check(lib().dm_count_quasi_cliques(g.handle, k, min_edges, ctypes.byref(out), ctypes.byref(o)))
+    del keep
+    return int(out.value)
 
 
 def batch(graphs: Sequence[DMGraph], op: int, k: int, **opt) -> np.ndarray:

@@ -95,14 +95,34 @@ def test_16bit_dictionary_matches_oracle_on_every_code(k):
         assert np.array_equal(np.where(T8 == 0xFF, 0xFFFF, T8.astype(np.uint16)), T)
 
 
+def test_16bit_dictionary_k8_against_oracle():
+    """k = 8 (2^27 codes, 11,117 classes): every class's canonical code, and
+    the class of 2^20 seeded random reachable traversal codes, against the
+    oracle's orbit labelling (an independent implementation)."""
+    k = 8
+    assert dm.motif_num_classes(k) == O.num_classes(k) == 11117
+    canon = O.class_canon(k)
+    for c in range(len(canon)):
+        assert dm.motif_class_mask(k, c) == int(canon[c])
+    T = dm.motif_class_table16(k)
+    assert T.size == 1 << 27
+    rng = np.random.default_rng(8)
+    t = rng.integers(0, 1 << 27, size=1 << 20, dtype=np.int64)
+    reach = np.ones(t.size, dtype=bool)
+    for i in range(2, k):
+        reach &= ((t >> (i * (i - 1) // 2 - 1)) & ((1 << i) - 1)) != 0
+    assert (T[t[~reach]] == 0xFFFF).all()
+    assert np.array_equal(T[t[reach]].astype(np.int64), O.class_of_codes(k, (t[reach] << 1) | 1))
+
+
 def test_unsupported_k():
-    assert dm.motif_num_classes(2) == -1 and dm.motif_num_classes(8) == -1
+    assert dm.motif_num_classes(2) == -1 and dm.motif_num_classes(9) == -1
     assert dm.motif_num_classes(7) == 853
     with pytest.raises(dm.DMError) as e:
         dm.motif_class_table(7)
     assert e.value.status == dm.DM_E_K
     with pytest.raises(dm.DMError) as e:
-        dm.motif_class_table16(8)
+        dm.motif_class_table16(9)
     assert e.value.status == dm.DM_E_K
     with pytest.raises(dm.DMError) as e:
         dm.motif_class_mask(4, 6)

@@ -88,7 +88,7 @@ def test_motif_listing_large_against_counts(k, n, m):
 def test_listing_argument_errors():
     h = dm.load_graph(gg.complete(5))
     with pytest.raises(dm.DMError) as e:
-        dm.list_subgraphs(h, dm.DM_OP_MOTIF, 8)
+        dm.list_subgraphs(h, dm.DM_OP_MOTIF, 9)
     assert e.value.status == dm.DM_E_K
     with pytest.raises(dm.DMError) as e:
         dm.list_subgraphs(h, dm.DM_OP_CLIQUE, 3, sched=dm.DM_SCHED_LEARNED)

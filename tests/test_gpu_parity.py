@@ -408,7 +408,7 @@ def test_error_paths():
         with pytest.raises(dm.DMError) as e:
             dm.count_cliques(h, bad_k)
         assert e.value.status == dm.DM_E_K
-    for bad_k in (2, 8):
+    for bad_k in (2, 9):
         with pytest.raises(dm.DMError) as e:
             dm.count_motifs(h, bad_k)
         assert e.value.status == dm.DM_E_K
@@ -525,3 +525,52 @@ def test_dfs_ablation_closed_forms_and_options():
         with pytest.raises(dm.DMError) as e:
             dm.count_cliques(h, 4, **dict(dict(sched=dm.DM_IMPL_DFS), **kw))
         assert e.value.status == dm.DM_E_ARG
+
+
+# ------------------------------------------------------------------ host-driven balancing (Section IV-D)
+
+def _k300_plus_background():
+    bg = gg.erdos_renyi(6000, 30000, 9)
+    g, _ = gg.disjoint_union([bg, gg.complete(300)])
+    return g, bg
+
+
+def test_host_balanced_relaunch_is_exact():
+    """DM_SCHED_HOST_BALANCE: the launch stops once the queue is drained and
+    most waves are idle, busy waves spill their untried extensions, the host
+    splits them and relaunches.  K_300 sits last in the rank order (degree
+    299), so its heavy roots are still running when the stop comes: the call
+    relaunches, and the counts stay exact (closed form for K_300 plus the
+    oracle on the background), with per-root records equal to the plain
+    launch's."""
+    import torch
+    g, bg = _k300_plus_background()
+    h = dm.load_graph(g)
+    for k in (4, 5):
+        exp = math.comb(300, k) + O.clique_count(bg, k, threads=8)
+        assert dm.count_cliques(h, k) == exp
+        assert dm.count_cliques(h, k, sched=dm.DM_SCHED_HOST_BALANCE) == exp, k
+        assert dm.last_launch_count() > 1, k
+        assert dm.count_cliques(h, k, sched=dm.DM_SCHED_HOST_BALANCE, rebalance=0.9) == exp, k
+    s1 = torch.zeros((g.n, 3), dtype=torch.int64, device="cuda")
+    s2 = torch.zeros((g.n, 3), dtype=torch.int64, device="cuda")
+    assert dm.count_cliques(h, 5, root_stats=s1) == dm.count_cliques(h, 5, root_stats=s2,
+                                                                      sched=dm.DM_SCHED_HOST_BALANCE)
+    assert torch.equal(s1, s2)
+    for k in (4, 5):
+        ck = O.motif_count(bg, k, threads=8)
+        kcls = int(np.nonzero(O.motif_brute(gg.complete(k), k))[0][0])
+        ck[kcls] += math.comb(300, k)
+        assert np.array_equal(dm.count_motifs(h, k, sched=dm.DM_SCHED_HOST_BALANCE), ck), k
+        # the motif default stops only below 10% busy waves (more than the
+        # 300 K_300 roots' waves); at 50% the K_300 roots are still running
+        # when the background's waves have finished
+        assert np.array_equal(dm.count_motifs(h, k, sched=dm.DM_SCHED_HOST_BALANCE, rebalance=0.5), ck), k
+        assert dm.last_launch_count() > 1, k
+    for bad in (dict(sched=dm.DM_SCHED_HOST_BALANCE | dm.DM_NO_DONATION),):
+        with pytest.raises(dm.DMError) as e:
+            dm.count_cliques(h, 4, **bad)
+        assert e.value.status == dm.DM_E_ARG
+    with pytest.raises(dm.DMError) as e:
+        dm.batch([h, h], dm.DM_OP_CLIQUE, 3, sched=dm.DM_SCHED_HOST_BALANCE)
+    assert e.value.status == dm.DM_E_ARG

@@ -696,3 +696,33 @@ def test_motif_list_closed_forms():
     rows = O.motif_list(gg.complete(7), 3)
     assert [tuple(r[:3]) for r in rows.tolist()] == list(itertools.combinations(range(7), 3))
     assert len(set(rows[:, 3].tolist())) == 1
+
+
+# ------------------------------------------------------------------ property filters
+
+@pytest.mark.parametrize("k", [3, 4, 5])
+def test_quasi_cliques_brute_vs_classes_and_closed_forms(k):
+    """Quasi-cliques (connected k-subsets with at least m induced edges): the
+    definition over every subset equals the sum over classes with enough
+    edges; m = C(k,2) gives networkx's k-cliques; m <= k-1 gives every
+    connected k-subset; K_n gives C(n,k) for every m."""
+    g = gg.erdos_renyi(16, 48, 30 + k)
+    G = to_nx(g)
+    full = k * (k - 1) // 2
+    for m in range(0, full + 1):
+        assert O.quasi_clique_brute(g, k, m) == O.quasi_clique_count(g, k, m), m
+    ncl = sum(1 for c in nx.enumerate_all_cliques(G) if len(c) == k)
+    assert O.quasi_clique_count(g, k, full) == ncl
+    assert O.quasi_clique_count(g, k, k - 1) == int(O.motif_brute(g, k).sum())
+    for m in (0, full // 2, full):
+        assert O.quasi_clique_count(gg.complete(9), k, m) == math.comb(9, k)
+
+
+def test_induced_subgraph_against_networkx():
+    g = gg.erdos_renyi(60, 240, 41)
+    keep = np.random.default_rng(4).random(g.n) < 0.6
+    h = O.induced(g, keep)
+    H = nx.convert_node_labels_to_integers(to_nx(g).subgraph(np.nonzero(keep)[0].tolist()), ordering="sorted")
+    assert h.n == H.number_of_nodes() and h.nnz == 2 * H.number_of_edges()
+    for v in range(h.n):
+        assert sorted(h.col[h.row_ptr[v]:h.row_ptr[v + 1]].tolist()) == sorted(H.neighbors(v))
