@@ -254,10 +254,11 @@ def quasi_clique_brute(g, k: int, min_edges: int) -> int:
     return cnt
 
 
-def quasi_clique_count(g, k: int, min_edges: int, threads: int = 1) -> int:
+def quasi_clique_count(g, k: int, min_edges: int, threads: int = 1, class_counts=None) -> int:
     """The same from the ESU class counts: the classes whose canonical
-    pattern has at least min_edges edges."""
-    c = motif_count(g, k, threads=threads)
+    pattern has at least min_edges edges.  class_counts: motif_count(g, k)
+    when the caller already has it (several thresholds on one graph)."""
+    c = motif_count(g, k, threads=threads) if class_counts is None else np.asarray(class_counts)
     edges = np.array([bin(int(x)).count("1") for x in class_canon(k)])
     return int(c[edges >= min_edges].sum())
 
