@@ -162,6 +162,25 @@ __device__ __forceinline__ uint64_t count_in(const uint64_t (&C)[NW], LdsU64* lr
   }
 }
 
+// Edges inside the set C (rows upper-triangular), one member per iteration: a
+// lane's loop over its own set, so the per-iteration work is one row read, an
+// AND and a popcount.
+template <int NW>
+__device__ __forceinline__ uint32_t edge_count(const uint64_t (&C)[NW], LdsU64* lr, int stride) {
+  uint32_t s = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    uint64_t x = pick<NW>(C, w);
+    while (x) {
+      const int i = w * 64 + __builtin_ctzll(x);
+      x &= x - 1;
+#pragma unroll
+      for (int q = 0; q < NW; ++q) s += static_cast<uint32_t>(__popcll(C[q] & lr[q * stride + i]));
+    }
+  }
+  return s;
+}
+
 __device__ __forceinline__ uint64_t range_mask64(int lo, int hi) {
   if (lo < 0) lo = 0;
   if (hi > 64) hi = 64;
@@ -324,70 +343,44 @@ __device__ __forceinline__ uint64_t lane_solve(const uint64_t (&C)[NW], const ui
     }
     if (ballot(!done) == 0) break;
     if (d >= 0) {
-      int wsel = -1;
+      const int r = r0 - d;  // members still to choose at this depth
+      if (r == 2) {
+        // the pairs (i, j) of cur with j in row(i) (rows hold only larger
+        // members), counted in one pass; cur is then empty and popped below
+        acc += edge_count<NW>(cur, lr, stride);
 #pragma unroll
-      for (int w = NW - 1; w >= 0; --w)
-        if (cur[w]) wsel = w;
-      if (wsel >= 0) {
-        const uint64_t cw = pick<NW>(cur, wsel);
-        const int i = wsel * 64 + __builtin_ctzll(cw);
+        for (int w = 0; w < NW; ++w) cur[w] = 0;
+      } else {
+        int wsel = -1;  // -1: a set restored by a pop can be empty
 #pragma unroll
-        for (int w = 0; w < NW; ++w) cur[w] = (w == wsel) ? (cw & (cw - 1)) : cur[w];
-        const int r = r0 - d;  // members still to choose at this depth, i included
-        // at the last level's parent up to two more members are taken in the
-        // same pass (all row reads in flight before any is used)
-        constexpr int kExtra = 2;
-        uint64_t rest[kExtra][NW];
-        int ix[kExtra];
-        bool has[kExtra];
-        uint64_t scan[NW];
+        for (int w = NW - 1; w >= 0; --w)
+          if (cur[w]) wsel = w;
+        if (wsel >= 0) {
+          const uint64_t cw = pick<NW>(cur, wsel);
+          const int i = wsel * 64 + __builtin_ctzll(cw);
 #pragma unroll
-        for (int w = 0; w < NW; ++w) scan[w] = cur[w];
+          for (int w = 0; w < NW; ++w) cur[w] = (w == wsel) ? (cw & (cw - 1)) : cur[w];
+          uint64_t ch[NW];
+          int cnt = 0;
 #pragma unroll
-        for (int e = 0; e < kExtra; ++e) {
-          int we = -1;
-          if (r == 2) {
-#pragma unroll
-            for (int w = NW - 1; w >= 0; --w)
-              if (scan[w]) we = w;
+          for (int q2 = 0; q2 < NW; ++q2) {
+            ch[q2] = cur[q2] & lr[q2 * stride + i];
+            cnt += __popcll(ch[q2]);
           }
-          has[e] = we >= 0;
-          ix[e] = i;
-          if (has[e]) {
-            const uint64_t ce = pick<NW>(scan, we);
-            ix[e] = we * 64 + __builtin_ctzll(ce);
+          if (r == 3) {
+            // the last two members inside ch: its edges, counted in place
+            // instead of pushing ch (no stack traffic at the deepest level)
+            if (cnt >= 2) acc += edge_count<NW>(ch, lr, stride);
+          } else if (cnt >= r - 1) {
+            const uint64_t c0 = cur[0], c1 = NW == 2 ? pick<NW>(cur, 1) : 0;
+            if (d == 0) { sa0 = c0; sa1 = c1; }
+            else if (d == 1) { sb0 = c0; sb1 = c1; }
+            else if (d == 2) { sc0 = c0; sc1 = c1; }
+            else { sd0 = c0; sd1 = c1; }
 #pragma unroll
-            for (int w = 0; w < NW; ++w) scan[w] = (w == we) ? (ce & (ce - 1)) : scan[w];
+            for (int w = 0; w < NW; ++w) cur[w] = ch[w];
+            ++d;
           }
-#pragma unroll
-          for (int w = 0; w < NW; ++w) rest[e][w] = has[e] ? scan[w] : 0;
-        }
-        uint64_t ch[NW];
-        int cnt = 0, cnt2 = 0;
-#pragma unroll
-        for (int q2 = 0; q2 < NW; ++q2) {
-          const uint64_t ra = lr[q2 * stride + i];
-          uint64_t rx[kExtra];
-#pragma unroll
-          for (int e = 0; e < kExtra; ++e) rx[e] = lr[q2 * stride + ix[e]];
-          ch[q2] = cur[q2] & ra;
-          cnt += __popcll(ch[q2]);
-#pragma unroll
-          for (int e = 0; e < kExtra; ++e) cnt2 += __popcll(rest[e][q2] & rx[e]);
-        }
-        if (r == 2) {
-          acc += static_cast<uint64_t>(cnt + cnt2);
-#pragma unroll
-          for (int w = 0; w < NW; ++w) cur[w] = scan[w];
-        } else if (cnt >= r - 1) {
-          const uint64_t c0 = cur[0], c1 = NW == 2 ? pick<NW>(cur, 1) : 0;
-          if (d == 0) { sa0 = c0; sa1 = c1; }
-          else if (d == 1) { sb0 = c0; sb1 = c1; }
-          else if (d == 2) { sc0 = c0; sc1 = c1; }
-          else { sd0 = c0; sd1 = c1; }
-#pragma unroll
-          for (int w = 0; w < NW; ++w) cur[w] = ch[w];
-          ++d;
         }
       }
       // a set used up in this pass is popped in the same pass
