@@ -574,7 +574,7 @@ def wl_ablation(args):
     Chung-Lu graph, motifs k = 3, 4 on the 10^5-vertex Chung-Lu graph (weight
     cap 1414) and k = 5 at weight cap 200.  Counts must agree across the
     three.  A DFS run longer than --ablation-limit seconds stops the DFS
-    column for the larger k of that series (marked null)."""
+    column for the larger k of that operation (marked null)."""
     import torch
     from paper_2212_04551_amd import dm
     from paper_2212_04551_amd import graphgen as gg
@@ -598,17 +598,19 @@ def wl_ablation(args):
     series = [("clique", "cl1m", lambda: gg.chung_lu(1_000_000, 20_000_000, 2.1, 1.0e4, args.seed)[0], (3, 4, 5, 6)),
               ("motif", "cl100k_cap1414", lambda: gg.chung_lu(100_000, 1_000_000, 2.3, 1414.0, args.seed)[0], (3, 4)),
               ("motif", "cl100k_cap200", lambda: gg.chung_lu(100_000, 1_000_000, 2.3, 200.0, args.seed)[0], (5,))]
+    dfs_ok = {"clique": True, "motif": True}  # per operation, across its graphs (larger k follow)
     for op, gname, make, ks in series:
+        if only and not any(x.startswith(f"{op}{k}") for x in only for k in ks):
+            continue
         g = make()
         h = dm.load_graph(g, orient=(op == "clique"), rank=(op == "motif"))
-        dfs_ok = True
         for k in ks:
             row = {"op": op, "graph": gname, "k": k}
             ref = None
             for name, flag in impls:
                 if only and f"{op}{k}{name}" not in only:
                     continue
-                if name == "DFS" and not dfs_ok:
+                if name == "DFS" and not dfs_ok[op]:
                     row[name + "_ms"] = None
                     continue
                 fn = (lambda f=flag: dm.count_cliques(h, k, sched=f, stream=stream)) if op == "clique" else \
@@ -620,12 +622,14 @@ def wl_ablation(args):
                     ref = c
                 assert np.array_equal(np.asarray(c), np.asarray(ref)), (op, k, name)
                 row[name + "_ms"] = ms
+                extra = ""
                 if name == "HOST":
                     row["HOST_launches"] = dm.last_launch_count()
+                    extra = f", {row['HOST_launches']} launches"
                 row["subgraphs"] = tot
-                log(f"ablation {op} {gname} k={k} {name}: {ms:.1f} ms ({tot} subgraphs)")
+                log(f"ablation {op} {gname} k={k} {name}: {ms:.1f} ms ({tot} subgraphs{extra})")
                 if name == "DFS" and ms > 1e3 * args.ablation_limit:
-                    dfs_ok = False
+                    dfs_ok[op] = False
             for a, b in (("DFS", "WC"), ("WC", "OPT"), ("DFS", "OPT"), ("WC", "HOST"), ("HOST", "OPT")):
                 if row.get(a + "_ms") and row.get(b + "_ms"):
                     row[f"{a}/{b}"] = row[a + "_ms"] / row[b + "_ms"]

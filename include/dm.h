@@ -254,6 +254,62 @@ dm_status dm_induced_subgraph(dm_graph* g, const uint8_t* keep, void* stream, dm
 dm_status dm_count_quasi_cliques(dm_graph* g, int k, int min_edges, uint64_t* out_count, const dm_options* opt);
 
 /*
+ * Directed graphs (Section II: the method is stated for undirected graphs and
+ * carries over to directed ones; Section IV-C: a subgraph's pattern is the
+ * bitmap of its pairs, here two bits per pair).
+ *
+ * dm_load_digraph: like dm_load_csr, but row_ptr / col are the arcs as sorted
+ * out-lists (arc v -> col[i] for i in [row_ptr[v], row_ptr[v+1])): strictly
+ * ascending per vertex, no self-arc; an opposite pair u -> w, w -> u is two
+ * arcs.  row_ptr[n] is the number of arcs (any value >= 0).  Flags as
+ * dm_load_csr (DM_CSR_DEVICE: device pointers; DM_CSR_TRUSTED skips the
+ * checks; DM_CSR_ORIENT / DM_CSR_RANK prepare the underlying graph).  The
+ * handle holds the underlying undirected graph (edge {u, w} for every arc),
+ * which every other call sees: cliques, undirected motifs, listings and
+ * filters count subgraphs of the underlying graph.  It also holds two arc bits
+ * per adjacency entry for dm_count_motifs_directed.  The caller's arrays are
+ * copied.  Errors: DM_E_ARG (null pointers, n < 0, unknown flag), DM_E_CSR
+ * (conventions violated), DM_E_NOMEM / DM_E_HIP.
+ */
+dm_status dm_load_digraph(int32_t n, const int64_t* row_ptr, const int32_t* col, uint32_t flags, void* stream,
+                          dm_graph** out);
+
+/* *is_directed = 1 for a dm_load_digraph handle (and *arcs its arc count), else 0 (arcs 0). */
+dm_status dm_digraph_info(const dm_graph* g, int32_t* is_directed, int64_t* arcs);
+
+/*
+ * Directed classes on k vertices (k in 1..5).  A k-vertex digraph in a vertex
+ * order has the code with, for each pair t < i (p = i(i-1)/2 + t), bit 2p set
+ * for the arc t -> i and bit 2p+1 for the arc i -> t.  Its class is the
+ * smallest code over all k! vertex orders; the classes of the weakly connected
+ * digraphs are numbered 0, 1, ... by increasing smallest code (13, 199 and
+ * 9,364 classes at k = 3, 4, 5).
+ *   dm_motif_directed_num_classes: the number of classes, or -1 for k outside 1..5.
+ *   dm_motif_directed_class_code: the smallest code of class cls.
+ *   dm_motif_directed_class_table: the class of every code, out[code] for all
+ *     2^(k(k-1)) codes (0xFFFF: not weakly connected); len >= 2^(k(k-1)).
+ * Host-only; no GPU needed.  Errors: DM_E_K, DM_E_ARG, DM_E_BUFSZ.
+ */
+int32_t dm_motif_directed_num_classes(int k);
+dm_status dm_motif_directed_class_code(int k, int32_t cls, uint32_t* code);
+dm_status dm_motif_directed_class_table(int k, uint16_t* out, size_t len);
+
+/*
+ * dm_count_motifs_directed: for k in 3..5, out_counts[c] (host, out_len >=
+ * dm_motif_directed_num_classes(k)) = the number of vertex sets S, |S| = k,
+ * whose induced subdigraph is weakly connected and in class c.  Enumeration
+ * over the underlying undirected graph (every connected k-subset once, from
+ * its smallest vertex id, by Section IV-E's canonical-candidate rule), one
+ * wave per root, no donation; classification by the dictionary above.
+ * Options: stream, chunk, waves_per_cu, wait_limit_us and DM_NO_DONATION
+ * (no effect); anything else gives DM_E_ARG.  Errors: DM_E_ARG (null pointers,
+ * a handle not made by dm_load_digraph), DM_E_K, DM_E_BUFSZ, DM_E_OVERFLOW,
+ * DM_E_NOMEM / DM_E_HIP.
+ */
+dm_status dm_count_motifs_directed(dm_graph* g, int k, uint64_t* out_counts, size_t out_len,
+                                   const dm_options* opt);
+
+/*
  * Count many graphs in one persistent launch.  op is DM_OP_CLIQUE (one count
  * per graph) or DM_OP_MOTIF (ncls(k) counts per graph).  out_counts is
  * row-major [num_graphs][per-graph width].  The graphs are concatenated as a

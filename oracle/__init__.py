@@ -72,6 +72,22 @@ def _load():
     L.or_triangles.argtypes = [i32, vp, vp, vp]
     L.or_core.restype = None
     L.or_core.argtypes = [i32, vp, vp, vp]
+    L.or_dcanon.restype = u32
+    L.or_dcanon.argtypes = [ctypes.c_int, u32]
+    L.or_dnum_classes.restype = ctypes.c_int
+    L.or_dnum_classes.argtypes = [ctypes.c_int]
+    L.or_dclass_canon.restype = ctypes.c_int
+    L.or_dclass_canon.argtypes = [ctypes.c_int, vp, ctypes.c_int]
+    L.or_dclass_of_code.restype = ctypes.c_int
+    L.or_dclass_of_code.argtypes = [ctypes.c_int, u32]
+    L.or_dnum_connected_labelled.restype = i64
+    L.or_dnum_connected_labelled.argtypes = [ctypes.c_int]
+    L.or_dclass_table.restype = ctypes.c_int
+    L.or_dclass_table.argtypes = [ctypes.c_int, vp, i64]
+    L.or_dmotif_brute.restype = ctypes.c_int
+    L.or_dmotif_brute.argtypes = [i32, vp, vp, ctypes.c_int, vp]
+    L.or_dmotif_esu.restype = ctypes.c_int
+    L.or_dmotif_esu.argtypes = [i32, vp, vp, vp, vp, ctypes.c_int, ctypes.c_int, vp]
     _lib = L
     return L
 
@@ -421,3 +437,81 @@ def features(g) -> np.ndarray:
     L.or_core(g.n, rp.ctypes.data, col.ctypes.data, core.ctypes.data)
     deg = np.diff(rp)
     return np.stack([deg, two[:g.n], core[:g.n], tri[:g.n]], axis=1).astype(np.float64)
+
+
+# ------------------------------------------------------------------ directed graphs
+
+def dcanon(k: int, code: int) -> int:
+    """Minimum directed code over all k! vertex orders (two bits per pair
+    t < i: bit 2p = arc t->i, bit 2p+1 = arc i->t, p = i(i-1)/2 + t)."""
+    return int(_load().or_dcanon(k, code))
+
+
+def dnum_classes(k: int) -> int:
+    """Weakly connected digraphs on k vertices up to isomorphism."""
+    return int(_load().or_dnum_classes(k))
+
+
+def dclass_canon(k: int) -> np.ndarray:
+    """Minimum codes of the weakly connected classes, in class-id order."""
+    L = _load()
+    ncls = L.or_dnum_classes(k)
+    out = np.zeros(max(ncls, 1), dtype=np.uint32)
+    L.or_dclass_canon(k, out.ctypes.data, ncls)
+    return out[:ncls]
+
+
+def dclass_of_code(k: int, code: int) -> int:
+    """Class id of a directed code, or -1 if the digraph is not weakly connected."""
+    return int(_load().or_dclass_of_code(k, code))
+
+
+def dclass_table(k: int) -> np.ndarray:
+    """dclass_of_code for every code on k vertices (int32, -1 if not weakly connected)."""
+    out = np.zeros(1 << (k * (k - 1)), dtype=np.int32)
+    if _load().or_dclass_table(k, out.ctypes.data, out.size) != 0:
+        raise ValueError("k out of range")
+    return out
+
+
+def dnum_connected_labelled(k: int) -> int:
+    return int(_load().or_dnum_connected_labelled(k))
+
+
+def undirected_of(dg):
+    """The underlying undirected graph of a digraph (arcs in sorted out-lists
+    row_ptr / col): every arc u->w gives the edge {u, w}; sorted, no repeats."""
+    n = int(dg.n)
+    rp = np.asarray(dg.row_ptr, dtype=np.int64)
+    dst = np.asarray(dg.col, dtype=np.int64)
+    src = np.repeat(np.arange(n, dtype=np.int64), np.diff(rp))
+    key = np.unique(np.concatenate([src * n + dst, dst * n + src])) if dst.size else np.zeros(0, np.int64)
+    a = key // max(n, 1)
+    b = (key % max(n, 1)).astype(np.int32)
+    urp = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(a, minlength=n), out=urp[1:])
+    return urp, b
+
+
+def dmotif_brute(dg, k: int) -> np.ndarray:
+    """Per-class counts of the weakly connected induced k-vertex subdigraphs,
+    by the definition: every k-subset of the vertices."""
+    rp, col = _csr(dg)
+    out = np.zeros(max(dnum_classes(k), 1), dtype=np.uint64)
+    if _load().or_dmotif_brute(dg.n, rp.ctypes.data, col.ctypes.data, k, out.ctypes.data) != 0:
+        raise ValueError("bad arguments")
+    return out[:dnum_classes(k)]
+
+
+def dmotif_count(dg, k: int, threads: int = 1) -> np.ndarray:
+    """The same by ESU enumeration of connected k-subsets of the underlying
+    undirected graph, each classified by its arcs."""
+    rp, col = _csr(dg)
+    urp, ucol = undirected_of(dg)
+    ucol = np.ascontiguousarray(ucol if ucol.size else np.zeros(1, np.int32))
+    out = np.zeros(max(dnum_classes(k), 1), dtype=np.uint64)
+    rc = _load().or_dmotif_esu(dg.n, rp.ctypes.data, col.ctypes.data, urp.ctypes.data, ucol.ctypes.data, k,
+                               threads, out.ctypes.data)
+    if rc != 0:
+        raise ValueError("bad arguments")
+    return out[:dnum_classes(k)]

@@ -950,3 +950,288 @@ uint64_t or_motif_timed(int32_t n, const int64_t* rp, const int32_t* col, int k,
     free(J);
     return tot;
 }
+
+/* ====================================================================== */
+/* Directed graphs (Section II: the method is stated for undirected graphs */
+/* and said to extend to directed ones).  A k-vertex digraph in a vertex    */
+/* order is coded with two bits per pair t < i: bit 2 p(t,i) = arc t -> i,  */
+/* bit 2 p(t,i) + 1 = arc i -> t, p(t,i) = i(i-1)/2 + t.  Its class is the  */
+/* minimum code over all k! vertex orders; classes are the weakly connected */
+/* ones, numbered by increasing minimum code.  k <= 5 (20-bit codes).       */
+/* ====================================================================== */
+
+#define OR_MAX_DMOTIF_K 5
+
+static uint32_t dcode_from_arcs(int k, const unsigned char arc[OR_MAXK][OR_MAXK]) {
+    uint32_t c = 0;
+    for (int i = 1; i < k; ++i)
+        for (int t = 0; t < i; ++t) {
+            if (arc[t][i]) c |= 1u << (2 * pair_bit(t, i));
+            if (arc[i][t]) c |= 1u << (2 * pair_bit(t, i) + 1);
+        }
+    return c;
+}
+
+static void arcs_from_dcode(int k, uint32_t c, unsigned char arc[OR_MAXK][OR_MAXK]) {
+    memset(arc, 0, sizeof(unsigned char) * OR_MAXK * OR_MAXK);
+    for (int i = 1; i < k; ++i)
+        for (int t = 0; t < i; ++t) {
+            if (c >> (2 * pair_bit(t, i)) & 1u) arc[t][i] = 1;
+            if (c >> (2 * pair_bit(t, i) + 1) & 1u) arc[i][t] = 1;
+        }
+}
+
+/* weakly connected: connected after forgetting directions */
+static int weakly_connected_dcode(int k, uint32_t c) {
+    unsigned char arc[OR_MAXK][OR_MAXK];
+    arcs_from_dcode(k, c, arc);
+    int seen[OR_MAXK] = {0}, stack[OR_MAXK], sp = 0, cnt = 1;
+    seen[0] = 1;
+    stack[sp++] = 0;
+    while (sp) {
+        int x = stack[--sp];
+        for (int y = 0; y < k; ++y)
+            if ((arc[x][y] || arc[y][x]) && !seen[y]) { seen[y] = 1; cnt++; stack[sp++] = y; }
+    }
+    return cnt == k;
+}
+
+/* minimum code over all k! vertex orders (new position p[x] for old vertex x) */
+uint32_t or_dcanon(int k, uint32_t c) {
+    unsigned char arc[OR_MAXK][OR_MAXK];
+    arcs_from_dcode(k, c, arc);
+    int ax[OR_MAXK * OR_MAXK], ay[OR_MAXK * OR_MAXK], na = 0;
+    for (int x = 0; x < k; ++x)
+        for (int y = 0; y < k; ++y)
+            if (arc[x][y]) { ax[na] = x; ay[na] = y; ++na; }
+    int p[OR_MAXK];
+    for (int i = 0; i < k; ++i) p[i] = i;
+    uint32_t best = 0xffffffffu;
+    do {
+        /* the arc x -> y becomes p[x] -> p[y] */
+        uint32_t d = 0;
+        for (int e = 0; e < na; ++e) {
+            const int a = p[ax[e]], b = p[ay[e]];
+            d |= a < b ? 1u << (2 * pair_bit(a, b)) : 1u << (2 * pair_bit(b, a) + 1);
+        }
+        if (d < best) best = d;
+    } while (next_perm(p, k));
+    return best;
+}
+
+typedef struct {
+    int ready;
+    int ncls;
+    uint32_t* canon;       /* [ncls] minimum codes, ascending */
+    int32_t* class_of;     /* [4^C(k,2)] class id of every code, -1 if not weakly connected */
+} dclass_info;
+
+static dclass_info g_dcls[OR_MAX_DMOTIF_K + 1];
+
+/* Every code's minimum by brute force over the k! orders (memoised per
+ * code), then the connected minima sorted. */
+static const dclass_info* dclasses(int k) {
+    if (k < 1 || k > OR_MAX_DMOTIF_K) return NULL;
+    pthread_mutex_lock(&g_cls_lock);
+    dclass_info* D = &g_dcls[k];
+    if (!D->ready) {
+        const int bits = k * (k - 1);
+        const int64_t ncodes = (int64_t)1 << bits;
+        uint32_t* mins = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)ncodes);
+        D->class_of = (int32_t*)malloc(sizeof(int32_t) * (size_t)ncodes);
+        uint32_t* reps = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)ncodes);
+        int64_t nrep = 0;
+        for (int64_t c = 0; c < ncodes; ++c) {
+            mins[c] = or_dcanon(k, (uint32_t)c);
+            if (mins[c] == (uint32_t)c && weakly_connected_dcode(k, (uint32_t)c)) reps[nrep++] = (uint32_t)c;
+        }
+        /* reps are already ascending (c runs upwards) */
+        D->ncls = (int)nrep;
+        D->canon = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(nrep > 0 ? nrep : 1));
+        memcpy(D->canon, reps, sizeof(uint32_t) * (size_t)nrep);
+        for (int64_t c = 0; c < ncodes; ++c) {
+            D->class_of[c] = -1;
+            if (!weakly_connected_dcode(k, (uint32_t)c)) continue;
+            int64_t lo = 0, hi = nrep;
+            while (lo < hi) {
+                int64_t mid = (lo + hi) / 2;
+                if (reps[mid] < mins[c]) lo = mid + 1; else hi = mid;
+            }
+            D->class_of[c] = (int32_t)lo;
+        }
+        free(mins);
+        free(reps);
+        D->ready = 1;
+    }
+    pthread_mutex_unlock(&g_cls_lock);
+    return D;
+}
+
+int or_dnum_classes(int k) {
+    const dclass_info* D = dclasses(k);
+    return D ? D->ncls : -1;
+}
+
+int or_dclass_canon(int k, uint32_t* out, int cap) {
+    const dclass_info* D = dclasses(k);
+    if (!D || cap < D->ncls) return -1;
+    memcpy(out, D->canon, sizeof(uint32_t) * (size_t)D->ncls);
+    return D->ncls;
+}
+
+int or_dclass_of_code(int k, uint32_t code) {
+    const dclass_info* D = dclasses(k);
+    if (!D || (uint64_t)code >> (k * (k - 1))) return -2;
+    return D->class_of[code];
+}
+
+/* number of labelled weakly connected digraphs on k vertices */
+int64_t or_dnum_connected_labelled(int k) {
+    const dclass_info* D = dclasses(k);
+    if (!D) return -1;
+    int64_t cnt = 0;
+    for (int64_t c = 0; c < ((int64_t)1 << (k * (k - 1))); ++c) cnt += D->class_of[c] >= 0;
+    return cnt;
+}
+
+/* L1: every k-subset of a digraph given by sorted out-lists; out_counts[ncls] */
+int or_dmotif_brute(int32_t n, const int64_t* rp, const int32_t* col, int k, uint64_t* out_counts) {
+    graph_t g = { n, rp, col };
+    const dclass_info* D = dclasses(k);
+    if (!D || k < 2) return -1;
+    memset(out_counts, 0, sizeof(uint64_t) * (size_t)D->ncls);
+    if (k > n) return 0;
+    int idx[OR_MAXK];
+    for (int i = 0; i < k; ++i) idx[i] = i;
+    unsigned char arc[OR_MAXK][OR_MAXK];
+    for (;;) {
+        memset(arc, 0, sizeof arc);
+        for (int a = 0; a < k; ++a)
+            for (int b = 0; b < k; ++b)
+                if (a != b && has_edge(&g, idx[a], idx[b])) arc[a][b] = 1;
+        int q = D->class_of[dcode_from_arcs(k, arc)];
+        if (q >= 0) out_counts[q]++;
+        int i = k - 1;
+        while (i >= 0 && idx[i] == n - k + i) --i;
+        if (i < 0) break;
+        idx[i]++;
+        for (int j = i + 1; j < k; ++j) idx[j] = idx[j - 1] + 1;
+    }
+    return 0;
+}
+
+/* L2: ESU (Wernicke's enumeration of connected k-subsets: a subset grows by
+ * a vertex of its extension set; a new vertex w adds to the extension set its
+ * neighbours above the root that are neither in the subset nor adjacent to
+ * it), over the underlying undirected graph, each subset classified by its
+ * arcs.  Threads take roots from a shared counter. */
+typedef struct {
+    graph_t out;           /* arcs */
+    const int64_t* urp;    /* underlying undirected graph, sorted */
+    const int32_t* ucol;
+    int k;
+    const dclass_info* D;
+    int64_t next;
+    int32_t n;
+    pthread_mutex_t lock;
+    uint64_t* total;       /* [ncls] */
+} desu_job;
+
+static int u_adjacent(const desu_job* J, int32_t a, int32_t b) {
+    int64_t lo = J->urp[a], hi = J->urp[a + 1];
+    while (lo < hi) {
+        int64_t mid = (lo + hi) / 2;
+        if (J->ucol[mid] == b) return 1;
+        if (J->ucol[mid] < b) lo = mid + 1; else hi = mid;
+    }
+    return 0;
+}
+
+static void desu_extend(const desu_job* J, int32_t* sub, int s, int32_t* ext, int64_t ne, uint64_t* cnt) {
+    if (s == J->k) {
+        unsigned char arc[OR_MAXK][OR_MAXK];
+        memset(arc, 0, sizeof arc);
+        for (int a = 0; a < s; ++a)
+            for (int b = 0; b < s; ++b)
+                if (a != b && has_edge(&J->out, sub[a], sub[b])) arc[a][b] = 1;
+        int q = J->D->class_of[dcode_from_arcs(s, arc)];
+        if (q >= 0) cnt[q]++;
+        return;
+    }
+    const int32_t v = sub[0];
+    while (ne > 0) {
+        const int32_t w = ext[--ne];
+        /* new extension set: what is left of ext plus w's exclusive neighbours */
+        int64_t cap = ne + (J->urp[w + 1] - J->urp[w]);
+        int32_t* nx = (int32_t*)malloc(sizeof(int32_t) * (size_t)(cap > 0 ? cap : 1));
+        int64_t nn = 0;
+        for (int64_t i = 0; i < ne; ++i) nx[nn++] = ext[i];
+        for (int64_t e = J->urp[w]; e < J->urp[w + 1]; ++e) {
+            const int32_t u = J->ucol[e];
+            if (u <= v) continue;
+            int excl = 1;
+            for (int a = 0; a < s && excl; ++a)
+                if (sub[a] == u || u_adjacent(J, sub[a], u)) excl = 0;
+            for (int64_t i = 0; i < nn && excl; ++i)
+                if (nx[i] == u) excl = 0;
+            if (excl) nx[nn++] = u;
+        }
+        sub[s] = w;
+        desu_extend(J, sub, s + 1, nx, nn, cnt);
+        free(nx);
+    }
+}
+
+static void* desu_worker(void* arg) {
+    desu_job* J = (desu_job*)arg;
+    uint64_t* cnt = (uint64_t*)calloc((size_t)J->D->ncls, sizeof(uint64_t));
+    int32_t sub[OR_MAXK];
+    for (;;) {
+        pthread_mutex_lock(&J->lock);
+        int64_t v = J->next++;
+        pthread_mutex_unlock(&J->lock);
+        if (v >= J->n) break;
+        int64_t d = J->urp[v + 1] - J->urp[v];
+        int32_t* ext = (int32_t*)malloc(sizeof(int32_t) * (size_t)(d > 0 ? d : 1));
+        int64_t ne = 0;
+        for (int64_t e = J->urp[v]; e < J->urp[v + 1]; ++e)
+            if (J->ucol[e] > v) ext[ne++] = J->ucol[e];
+        sub[0] = (int32_t)v;
+        if (J->k == 1) cnt[J->D->class_of[0]]++;
+        else desu_extend(J, sub, 1, ext, ne, cnt);
+        free(ext);
+    }
+    pthread_mutex_lock(&J->lock);
+    for (int c = 0; c < J->D->ncls; ++c) J->total[c] += cnt[c];
+    pthread_mutex_unlock(&J->lock);
+    free(cnt);
+    return NULL;
+}
+
+/* rp/col: the arcs (sorted out-lists); urp/ucol: the underlying undirected
+ * graph (sorted, symmetric), built by the caller */
+int or_dmotif_esu(int32_t n, const int64_t* rp, const int32_t* col, const int64_t* urp, const int32_t* ucol, int k,
+                  int nthreads, uint64_t* out_counts) {
+    const dclass_info* D = dclasses(k);
+    if (!D || k < 2) return -1;
+    memset(out_counts, 0, sizeof(uint64_t) * (size_t)D->ncls);
+    desu_job J;
+    J.out.n = n; J.out.rp = rp; J.out.col = col;
+    J.urp = urp; J.ucol = ucol; J.k = k; J.D = D; J.next = 0; J.n = n; J.total = out_counts;
+    pthread_mutex_init(&J.lock, NULL);
+    if (nthreads < 1) nthreads = 1;
+    pthread_t th[64];
+    if (nthreads > 64) nthreads = 64;
+    for (int t = 0; t < nthreads; ++t) pthread_create(&th[t], NULL, desu_worker, &J);
+    for (int t = 0; t < nthreads; ++t) pthread_join(th[t], NULL);
+    pthread_mutex_destroy(&J.lock);
+    return 0;
+}
+
+/* the class of every directed code on k vertices (-1: not weakly connected) */
+int or_dclass_table(int k, int32_t* out, int64_t len) {
+    const dclass_info* D = dclasses(k);
+    if (!D || len < ((int64_t)1 << (k * (k - 1)))) return -1;
+    memcpy(out, D->class_of, sizeof(int32_t) * (size_t)((int64_t)1 << (k * (k - 1))));
+    return 0;
+}

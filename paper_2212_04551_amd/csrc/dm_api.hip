@@ -219,6 +219,75 @@ const ClassTables* tables(int k) {
   return g_tables[k];
 }
 
+// Directed classes (k <= 5): codes take two bits per vertex pair t < i,
+// bit 2p for the arc t -> i and bit 2p+1 for i -> t (p = i(i-1)/2 + t); a
+// class is the smallest code over all vertex orders, and the weakly connected
+// classes are numbered by increasing smallest code.  Orbit labelling: codes
+// are visited in increasing order, and the first one not yet labelled is the
+// smallest of its orbit, whose k! images are labelled with it.
+struct DClassTables {
+  int ncls = 0;
+  std::vector<uint32_t> canon;  // class -> smallest code
+  std::vector<uint16_t> table;  // code -> class (kUnreachable: not weakly connected)
+};
+
+DClassTables build_dtables(int k) {
+  DClassTables T;
+  const int npairs = k * (k - 1) / 2;
+  const uint32_t ncodes = 1u << (2 * npairs);
+  std::vector<int32_t> orbit(ncodes, -1);
+  std::vector<uint32_t> reps;
+  std::vector<std::vector<int>> perms;
+  std::vector<int> p(k);
+  for (int i = 0; i < k; ++i) p[i] = i;
+  do perms.push_back(p);
+  while (std::next_permutation(p.begin(), p.end()));
+  int ax[kDMotifMaxK * kDMotifMaxK], ay[kDMotifMaxK * kDMotifMaxK];
+  for (uint32_t c = 0; c < ncodes; ++c) {
+    if (orbit[c] >= 0) continue;
+    const int id = static_cast<int>(reps.size());
+    reps.push_back(c);
+    int na = 0;
+    for (int i = 1; i < k; ++i)
+      for (int t = 0; t < i; ++t) {
+        const int b = 2 * pair_index(t, i);
+        if ((c >> b) & 1u) { ax[na] = t; ay[na] = i; ++na; }
+        if ((c >> (b + 1)) & 1u) { ax[na] = i; ay[na] = t; ++na; }
+      }
+    for (const auto& q : perms) {
+      uint32_t img = 0;
+      for (int e = 0; e < na; ++e) {
+        const int a = q[ax[e]], b = q[ay[e]];
+        img |= a < b ? 1u << (2 * pair_index(a, b)) : 1u << (2 * pair_index(b, a) + 1);
+      }
+      orbit[img] = id;
+    }
+  }
+  std::vector<int> cls_of_orbit(reps.size(), -1);
+  for (size_t r = 0; r < reps.size(); ++r) {
+    uint32_t und = 0;  // the underlying undirected graph
+    for (int pi = 0; pi < npairs; ++pi)
+      if ((reps[r] >> (2 * pi)) & 3u) und |= 1u << pi;
+    if (bitmap_connected(k, und)) {
+      cls_of_orbit[r] = T.ncls++;
+      T.canon.push_back(reps[r]);
+    }
+  }
+  T.table.assign(ncodes, kUnreachable);
+  for (uint32_t c = 0; c < ncodes; ++c)
+    if (cls_of_orbit[orbit[c]] >= 0) T.table[c] = static_cast<uint16_t>(cls_of_orbit[orbit[c]]);
+  return T;
+}
+
+DClassTables* g_dtables[kDMotifMaxK + 1] = {nullptr};
+
+const DClassTables* dtables(int k) {
+  if (k < 1 || k > kDMotifMaxK) return nullptr;
+  std::lock_guard<std::mutex> lk(g_tables_lock);
+  if (!g_dtables[k]) g_dtables[k] = new DClassTables(build_dtables(k));
+  return g_dtables[k];
+}
+
 // device copies of the dictionary, per (device, k)
 std::mutex g_dev_tables_lock;
 std::map<std::pair<int, int>, uint16_t*> g_dev_tables;
@@ -234,12 +303,13 @@ hipError_t device_table(int k, uint16_t** out) {
     *out = it->second;
     return hipSuccess;
   }
-  const ClassTables* T = tables(k);
+  // keys above 100 hold the directed dictionaries (k + 100)
+  const std::vector<uint16_t>& tab = k > 100 ? dtables(k - 100)->table : tables(k)->table;
   uint16_t* p = nullptr;
-  const size_t bytes = T->table.size() * sizeof(uint16_t);
+  const size_t bytes = tab.size() * sizeof(uint16_t);
   e = hipMalloc(&p, bytes);
   if (e != hipSuccess) return e;
-  e = hipMemcpy(p, T->table.data(), bytes, hipMemcpyHostToDevice);
+  e = hipMemcpy(p, tab.data(), bytes, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     (void)hipFree(p);
     return e;
@@ -324,6 +394,10 @@ struct dm_graph {
   Buf dfs_stack, dfs_mask;  // per-lane stacks of the one-lane-per-traversal ablation
   Buf spill, tq;            // host-driven balancing: spilled tasks, relaunch queue
   Buf wave_cnt;             // motifs at k = 8: per-wave class counters
+  // digraphs (dm_load_digraph): arc bits per adjacency entry, directed-motif workspace
+  bool directed = false;
+  int64_t arcs = 0;
+  Buf dir, ext_arcs, dhit, dndir;
   // learned ordering: features (cached), predictions, LPT order, chunk starts
   // and the order in rank space; the queue is reused while the parameter
   // fingerprint, grid and chunks per wave stay the same
@@ -1976,4 +2050,220 @@ extern "C" dm_status dm_autotune(dm_graph* const* gs, int32_t num_graphs, int op
   out->waves_per_cu = t.waves_per_cu;
   out->ms = t.ms;
   return DM_OK;
+}
+
+// ====================================================================== directed graphs
+
+namespace {
+
+// Host check of the arc conventions: sorted out-lists, no self-arc, no repeated arc.
+bool host_validate_arcs(int32_t n, const int64_t* rp, const int32_t* col, std::string* why) {
+  if (rp[0] != 0) { *why = "row_ptr[0] != 0"; return false; }
+  for (int32_t v = 0; v < n; ++v)
+    if (rp[v + 1] < rp[v]) { *why = "row_ptr decreases"; return false; }
+  for (int32_t v = 0; v < n; ++v)
+    for (int64_t i = rp[v]; i < rp[v + 1]; ++i) {
+      const int32_t u = col[i];
+      if (u < 0 || u >= n) { *why = "column id out of range"; return false; }
+      if (u == v) { *why = "self-arc"; return false; }
+      if (i > rp[v] && col[i - 1] >= u) { *why = "out-list not strictly ascending (or repeated arc)"; return false; }
+    }
+  return true;
+}
+
+}  // namespace
+
+extern "C" dm_status dm_load_digraph(int32_t n, const int64_t* row_ptr, const int32_t* col, uint32_t flags,
+                                     void* stream, dm_graph** out) {
+  if (!out) return fail(DM_E_ARG, "null output handle");
+  *out = nullptr;
+  if (n < 0 || !row_ptr || (!col && n > 0)) return fail(DM_E_ARG, "n < 0 or null CSR array");
+  if (flags & ~15u) return fail(DM_E_ARG, "unknown flag");
+  const bool on_device = flags & DM_CSR_DEVICE;
+  const bool trusted = flags & DM_CSR_TRUSTED;
+  int64_t arcs = 0;
+  if (!on_device) {
+    arcs = row_ptr[n];
+    if (arcs < 0) return fail(DM_E_CSR, "negative arc count");
+    std::string why;
+    if (!trusted && !host_validate_arcs(n, row_ptr, col, &why)) return fail(DM_E_CSR, why);
+  }
+  hipStream_t own = nullptr;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (!s) HIP_OR_RETURN(hipStreamCreateWithFlags(&own, hipStreamNonBlocking), "dm_load_digraph: stream");
+  if (!s) s = own;
+  struct StreamGuard {
+    hipStream_t st;
+    ~StreamGuard() {
+      if (st) (void)hipStreamDestroy(st);
+    }
+  } guard{own};
+  if (on_device) {
+    HIP_OR_RETURN(hipMemcpyAsync(&arcs, row_ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, s), "dm_load_digraph: read arcs");
+    HIP_OR_RETURN(hipStreamSynchronize(s), "dm_load_digraph: read arcs");
+    if (arcs < 0) return fail(DM_E_CSR, "negative arc count");
+  }
+  Buf arp, acol, flag;
+  const int64_t* drp = row_ptr;
+  const int32_t* dcol = col;
+  if (!on_device) {
+    HIP_OR_RETURN(arp.ensure(sizeof(int64_t) * (static_cast<size_t>(n) + 1)), "dm_load_digraph: allocate");
+    HIP_OR_RETURN(acol.ensure(sizeof(int32_t) * static_cast<size_t>(arcs > 0 ? arcs : 1)), "dm_load_digraph: allocate");
+    HIP_OR_RETURN(hipMemcpyAsync(arp.p, row_ptr, sizeof(int64_t) * (static_cast<size_t>(n) + 1), hipMemcpyHostToDevice, s),
+                  "dm_load_digraph: copy");
+    if (arcs > 0)
+      HIP_OR_RETURN(hipMemcpyAsync(acol.p, col, sizeof(int32_t) * arcs, hipMemcpyHostToDevice, s), "dm_load_digraph: copy");
+    drp = arp.as<int64_t>();
+    dcol = acol.as<int32_t>();
+  } else if (!trusted && n > 0) {
+    int bad = 0;
+    HIP_OR_RETURN(flag.ensure(sizeof(int)), "dm_load_digraph: allocate");
+    HIP_OR_RETURN(launch_fill_i32(flag.as<int>(), 1, 0, s), "dm_load_digraph: validate");
+    HIP_OR_RETURN(launch_arc_validate(drp, dcol, n, arcs, flag.as<int>(), s), "dm_load_digraph: validate");
+    HIP_OR_RETURN(hipMemcpyAsync(&bad, flag.p, sizeof(int), hipMemcpyDeviceToHost, s), "dm_load_digraph: validate");
+    HIP_OR_RETURN(hipStreamSynchronize(s), "dm_load_digraph: validate");
+    if (bad) {
+      char buf[96];
+      std::snprintf(buf, sizeof buf, "device arc validation failed (flags 0x%x)", bad);
+      return fail(DM_E_CSR, buf);
+    }
+  }
+  int64_t* urp = nullptr;
+  int32_t* ucol = nullptr;
+  uint8_t* udir = nullptr;
+  int64_t unnz = 0;
+  hipError_t e = hipSuccess;
+  if (n > 0) {
+    e = digraph_underlying(drp, dcol, n, arcs, &urp, &ucol, &udir, &unnz, s);
+  } else {
+    e = hipMalloc(&urp, sizeof(int64_t));
+    if (e == hipSuccess) e = hipMemsetAsync(urp, 0, sizeof(int64_t), s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+  }
+  if (e != hipSuccess) {
+    (void)hipFree(urp);
+    (void)hipFree(ucol);
+    (void)hipFree(udir);
+    return hip_fail(e, "dm_load_digraph: underlying graph");
+  }
+  int32_t none = 0;
+  const dm_status st = dm_load_csr(n, urp, ucol ? ucol : &none, DM_CSR_DEVICE | DM_CSR_TRUSTED |
+                                   (flags & (DM_CSR_ORIENT | DM_CSR_RANK)), stream, out);
+  (void)hipFree(urp);
+  (void)hipFree(ucol);
+  if (st != DM_OK) {
+    (void)hipFree(udir);
+    return st;
+  }
+  dm_graph* g = *out;
+  g->directed = true;
+  g->arcs = arcs;
+  g->dir.p = udir;  // adopted: freed with the handle
+  g->dir.bytes = udir ? static_cast<size_t>(unnz > 0 ? unnz : 1) : 0;
+  return DM_OK;
+}
+
+extern "C" dm_status dm_digraph_info(const dm_graph* g, int32_t* is_directed, int64_t* arcs) {
+  if (!g) return fail(DM_E_ARG, "null graph");
+  if (is_directed) *is_directed = g->directed ? 1 : 0;
+  if (arcs) *arcs = g->directed ? g->arcs : 0;
+  return DM_OK;
+}
+
+extern "C" int32_t dm_motif_directed_num_classes(int k) {
+  const DClassTables* T = dtables(k);
+  return T ? T->ncls : -1;
+}
+
+extern "C" dm_status dm_motif_directed_class_code(int k, int32_t cls, uint32_t* code) {
+  const DClassTables* T = dtables(k);
+  if (!T) return fail(DM_E_K, "directed motif k must be in 1..5");
+  if (!code || cls < 0 || cls >= T->ncls) return fail(DM_E_ARG, "class id out of range or null output");
+  *code = T->canon[cls];
+  return DM_OK;
+}
+
+extern "C" dm_status dm_motif_directed_class_table(int k, uint16_t* out, size_t len) {
+  const DClassTables* T = dtables(k);
+  if (!T) return fail(DM_E_K, "directed motif k must be in 1..5");
+  if (!out) return fail(DM_E_ARG, "null output");
+  if (len < T->table.size()) return fail(DM_E_BUFSZ, "len < 2^(k(k-1))");
+  std::memcpy(out, T->table.data(), sizeof(uint16_t) * T->table.size());
+  return DM_OK;
+}
+
+extern "C" dm_status dm_count_motifs_directed(dm_graph* g, int k, uint64_t* out_counts, size_t out_len,
+                                              const dm_options* opt) {
+  if (!g || !out_counts) return fail(DM_E_ARG, "null graph or output");
+  if (!g->directed) return fail(DM_E_ARG, "not a directed graph (load it with dm_load_digraph)");
+  if (k < 3 || k > kDMotifMaxK) return fail(DM_E_K, "directed motif k must be in 3..5");
+  const DClassTables* T = dtables(k);
+  if (out_len < static_cast<size_t>(T->ncls)) return fail(DM_E_BUFSZ, "out_len < number of directed classes");
+  Opt o;
+  dm_status st = read_opt(opt, &o);
+  if (st != DM_OK) return st;
+  if ((o.sched & ~static_cast<uint32_t>(DM_NO_DONATION)) || o.roots || o.root_stats)
+    return fail(DM_E_ARG, "directed motifs take only stream, chunk, waves_per_cu and wait_limit_us");
+  hipStream_t s = pick_stream(g, o.stream);
+  uint16_t* dtab = nullptr;
+  HIP_OR_RETURN(device_table(k + 100, &dtab), "directed class table upload");
+  const int dmax = g->dmax > 0 ? g->dmax : 1;
+  const size_t lds = dmotif_lds_bytes(T->ncls);
+  int per_cu = 0;
+  HIP_OR_RETURN(dmotif_occupancy(lds, &per_cu), "occupancy");
+  if (per_cu < 1) per_cu = 1;
+  if (per_cu > 16) per_cu = 16;
+  if (o.waves_per_cu && static_cast<int>(o.waves_per_cu) < per_cu) per_cu = static_cast<int>(o.waves_per_cu);
+  const int grid = size_grid(per_cu, g->nnz);
+  DMotifArgs A;
+  std::memset(&A, 0, sizeof(A));
+  int64_t cap_total = 0;
+  for (int lv = 1; lv <= k - 1; ++lv) {
+    A.level_off[lv] = cap_total;
+    A.level_cap[lv] = static_cast<int64_t>(lv) * dmax;
+    cap_total += A.level_cap[lv];
+  }
+  A.hit_cap = static_cast<int64_t>(k - 1) * dmax;
+  A.wave_cap = cap_total;
+  const size_t gw = static_cast<size_t>(grid);
+  HIP_OR_RETURN(g->ctrl.ensure(ctrl_bytes()), "workspace");
+  HIP_OR_RETURN(g->out.ensure(sizeof(uint64_t) * T->ncls), "workspace");
+  HIP_OR_RETURN(g->ext_vert.ensure(sizeof(int32_t) * gw * cap_total), "workspace");
+  HIP_OR_RETURN(g->ext_mask.ensure(gw * cap_total), "workspace");
+  HIP_OR_RETURN(g->ext_arcs.ensure(sizeof(uint16_t) * gw * cap_total), "workspace");
+  HIP_OR_RETURN(g->dhit.ensure(gw * A.hit_cap), "workspace");
+  HIP_OR_RETURN(g->newbuf.ensure(sizeof(int32_t) * gw * dmax), "workspace");
+  HIP_OR_RETURN(g->dndir.ensure(gw * dmax), "workspace");
+  Sched S = make_sched(g, o, grid, g->n, nullptr, nullptr);
+  S.donate = 0;  // roots only: no donated task states for this kernel
+  A.rp = g->rp.as<int64_t>();
+  A.col = g->col.as<int32_t>();
+  A.dir = g->dir.as<uint8_t>();
+  A.n = g->n;
+  A.k = k;
+  A.dmax = dmax;
+  A.ncls = T->ncls;
+  A.table = dtab;
+  A.out = g->out.as<unsigned long long>();
+  A.flags = ctrl_flags(g);
+  A.vert = g->ext_vert.as<int32_t>();
+  A.mask = g->ext_mask.as<uint8_t>();
+  A.arcs = g->ext_arcs.as<uint16_t>();
+  A.hit = g->dhit.as<uint8_t>();
+  A.nbuf = g->newbuf.as<int32_t>();
+  A.ndir = g->dndir.as<uint8_t>();
+  A.S = S;
+  g_last_launches = 1;
+  int flags[2] = {0, 0};
+  hipError_t e = launch_fill_u64(g->ctrl.as<unsigned long long>(), static_cast<int64_t>(ctrl_bytes() / 8), 0ull, s);
+  if (e == hipSuccess) e = launch_fill_u64(A.out, T->ncls, 0ull, s);
+  if (e == hipSuccess && g->n > 0) e = launch_dmotif(A, grid, lds, s);
+  std::vector<uint64_t> tmp(T->ncls);
+  if (e == hipSuccess) e = hipMemcpyAsync(tmp.data(), A.out, sizeof(uint64_t) * T->ncls, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(flags, A.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "directed motif kernel / copy-back");
+  st = check_flags(flags);
+  if (st == DM_OK) std::memcpy(out_counts, tmp.data(), sizeof(uint64_t) * T->ncls);
+  return st;
 }

@@ -165,6 +165,41 @@ __device__ __forceinline__ bool ring_emit(const Ring& R, const int* prefix, int 
   return true;
 }
 
+// Directed graphs (dm_digraph.hip): the underlying undirected graph drives
+// the enumeration, two arc bits per adjacency entry drive the classification.
+constexpr int kDMotifMaxK = 5;
+struct DMotifArgs {
+  const int64_t* rp;       // underlying undirected graph (original ids), sorted lists
+  const int32_t* col;
+  const uint8_t* dir;      // per entry (u, w): bit 0 arc u -> w, bit 1 arc w -> u
+  int32_t n;
+  int k;
+  int dmax;                // largest undirected degree
+  int ncls;
+  const uint16_t* table;   // directed code (2 bits per vertex pair) -> class, 2^(k(k-1)) entries
+  unsigned long long* out; // [ncls]
+  int* flags;              // [0] overflow, [1] capacity / dictionary errors
+  int32_t* vert;           // per-wave level lists (levels 1..k-1)
+  uint8_t* mask;
+  uint16_t* arcs;
+  uint8_t* hit;            // per-wave marks of the entries an extension touches
+  int32_t* nbuf;           // per-wave new entries (dmax each)
+  uint8_t* ndir;
+  int64_t wave_cap;        // entries per wave in vert / mask / arcs
+  int64_t hit_cap;         // entries per wave in hit
+  int64_t level_off[kDMotifMaxK + 1];
+  int64_t level_cap[kDMotifMaxK + 1];
+  Sched S;
+};
+hipError_t launch_arc_validate(const int64_t* rp, const int32_t* col, int32_t n, int64_t arcs, int* flag,
+                               hipStream_t s);
+// the underlying undirected graph of the arcs (sorted out-lists): urp[n+1],
+// ucol[unnz], udir[unnz], allocated here (hipMalloc) and owned by the caller
+hipError_t digraph_underlying(const int64_t* rp, const int32_t* col, int32_t n, int64_t arcs, int64_t** urp,
+                              int32_t** ucol, uint8_t** udir, int64_t* unnz, hipStream_t s);
+size_t dmotif_lds_bytes(int ncls);
+hipError_t dmotif_occupancy(size_t lds_bytes, int* blocks_per_cu);
+hipError_t launch_dmotif(const DMotifArgs& a, int grid, size_t lds_bytes, hipStream_t s);
 // kernel launchers (return hipSuccess or the launch error)
 hipError_t launch_dfs_clique(const DfsArgs& a, int grid, hipStream_t s);
 hipError_t launch_dfs_motif(const DfsArgs& a, int grid, hipStream_t s);

@@ -34,6 +34,8 @@ EXPORTS = [
     "dm_load_csr", "dm_free", "dm_graph_info", "dm_count_cliques", "dm_motif_num_classes",
     "dm_motif_class_mask", "dm_motif_class_table", "dm_motif_class_table16", "dm_count_motifs",
     "dm_count_motifs_static", "dm_batch", "dm_list", "dm_induced_subgraph", "dm_count_quasi_cliques",
+    "dm_load_digraph", "dm_digraph_info", "dm_motif_directed_num_classes", "dm_motif_directed_class_code",
+    "dm_motif_directed_class_table", "dm_count_motifs_directed",
     "dm_strerror", "dm_last_error", "dm_last_launch_count", "dm_features", "dm_mlp_init", "dm_mlp_fit_normalizer",
     "dm_mlp_forward", "dm_mlp_targets", "dm_mlp_loss_grad", "dm_mlp_adam_step", "dm_mlp_train", "dm_autotune",
 ]
@@ -111,6 +113,18 @@ def lib():
                           ctypes.POINTER(dm_options)]
     L.dm_induced_subgraph.restype = ctypes.c_int
     L.dm_induced_subgraph.argtypes = [vp, vp, vp, ctypes.POINTER(vp)]
+    L.dm_load_digraph.restype = ctypes.c_int
+    L.dm_load_digraph.argtypes = [i32, vp, vp, u32, vp, ctypes.POINTER(vp)]
+    L.dm_digraph_info.restype = ctypes.c_int
+    L.dm_digraph_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i64)]
+    L.dm_motif_directed_num_classes.restype = i32
+    L.dm_motif_directed_num_classes.argtypes = [ctypes.c_int]
+    L.dm_motif_directed_class_code.restype = ctypes.c_int
+    L.dm_motif_directed_class_code.argtypes = [ctypes.c_int, i32, ctypes.POINTER(u32)]
+    L.dm_motif_directed_class_table.restype = ctypes.c_int
+    L.dm_motif_directed_class_table.argtypes = [ctypes.c_int, vp, ctypes.c_size_t]
+    L.dm_count_motifs_directed.restype = ctypes.c_int
+    L.dm_count_motifs_directed.argtypes = [vp, ctypes.c_int, vp, ctypes.c_size_t, ctypes.POINTER(dm_options)]
     L.dm_count_quasi_cliques.restype = ctypes.c_int
     L.dm_count_quasi_cliques.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64),
                                          ctypes.POINTER(dm_options)]
@@ -473,3 +487,67 @@ def __getattr__(name):
     if name in EXPORTS:
         return getattr(lib(), name)
     raise AttributeError(name)
+
+
+# ------------------------------------------------------------------ directed graphs
+
+def load_digraph_csr(n: int, row_ptr, col, device: bool = False, trusted: bool = False, stream=None,
+                     orient: bool = False, rank: bool = False) -> DMGraph:
+    """dm_load_digraph: arcs as sorted out-lists (numpy, or torch CUDA tensors with device=True)."""
+    if not device:
+        row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        col = np.ascontiguousarray(col, dtype=np.int32)
+        if col.size == 0:
+            col = np.zeros(1, dtype=np.int32)
+    flags = (DM_CSR_DEVICE if device else DM_CSR_HOST) | (DM_CSR_TRUSTED if trusted else 0)
+    flags |= DM_CSR_ORIENT if orient else 0
+    flags |= DM_CSR_RANK if rank else 0
+    h = ctypes.c_void_p(None)
+    _check(lib().dm_load_digraph(n, _ptr(row_ptr), _ptr(col), flags, _stream(stream), ctypes.byref(h)))
+    return DMGraph(h.value)
+
+
+def load_digraph(d, **kw) -> DMGraph:
+    """Load a graphgen.Digraph (host arrays)."""
+    return load_digraph_csr(d.n, d.row_ptr, d.col, **kw)
+
+
+def load_digraph_device(n: int, row_ptr, col, **kw) -> DMGraph:
+    return load_digraph_csr(n, row_ptr, col, device=True, **kw)
+
+
+def digraph_info(g: DMGraph):
+    """(1, arcs) for a digraph handle, (0, 0) otherwise."""
+    d = ctypes.c_int32(0)
+    a = ctypes.c_int64(0)
+    _check(lib().dm_digraph_info(g.handle, ctypes.byref(d), ctypes.byref(a)))
+    return int(d.value), int(a.value)
+
+
+def motif_directed_num_classes(k: int) -> int:
+    return int(lib().dm_motif_directed_num_classes(k))
+
+
+def motif_directed_class_code(k: int, cls: int) -> int:
+    c = ctypes.c_uint32(0)
+    _check(lib().dm_motif_directed_class_code(k, cls, ctypes.byref(c)))
+    return int(c.value)
+
+
+def motif_directed_class_table(k: int) -> np.ndarray:
+    """Class of every directed code on k vertices (0xFFFF: not weakly connected)."""
+    if motif_directed_num_classes(k) < 0:
+        _check(lib().dm_motif_directed_class_table(k, None, 0))
+    out = np.zeros(1 << (k * (k - 1)), dtype=np.uint16)
+    _check(lib().dm_motif_directed_class_table(k, out.ctypes.data, out.size))
+    return out
+
+
+def count_motifs_directed(g: DMGraph, k: int, **opt) -> np.ndarray:
+    """dm_count_motifs_directed: per-class counts of weakly connected induced k-subdigraphs."""
+    nc = motif_directed_num_classes(k)
+    out = np.zeros(max(nc, 1), dtype=np.uint64)
+    o, keep = make_options(**opt)
+    _check(lib().dm_count_motifs_directed(g.handle, k, out.ctypes.data, out.size if nc > 0 else 0, ctypes.byref(o)))
+    del keep
+    return out[:nc]

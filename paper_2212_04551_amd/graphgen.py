@@ -312,3 +312,65 @@ def workload_graph(name: str, seed: int = 0, **kw) -> Graph:
     if name == "sbm200x60":
         return sbm(200, 60, 0.45, 0.0005, seed)
     raise KeyError(name)
+
+
+# ---------------------------------------------------------------- directed graphs
+
+@dataclass
+class Digraph:
+    """Arcs as sorted out-lists: row_ptr[n+1] (int64), col[arcs] (int32)."""
+    n: int
+    row_ptr: np.ndarray
+    col: np.ndarray
+
+    @property
+    def arcs(self) -> int:
+        return int(self.row_ptr[-1])
+
+
+def digraph_from_arcs(n: int, arcs: Iterable[Tuple[int, int]]) -> Digraph:
+    a = np.asarray(list(arcs), dtype=np.int64).reshape(-1, 2)
+    a = a[a[:, 0] != a[:, 1]]
+    key = np.unique(a[:, 0] * max(n, 1) + a[:, 1]) if a.size else np.zeros(0, np.int64)
+    src = key // max(n, 1)
+    rp = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(src, minlength=n), out=rp[1:])
+    return Digraph(n, rp, (key % max(n, 1)).astype(np.int32))
+
+
+def orient(g: Graph, seed: int, both: float = 0.2) -> Digraph:
+    """Each edge {u, v} of g becomes an arc u->v or v->u (fair coin), or both
+    arcs with probability `both` (seeded)."""
+    rng = np.random.default_rng(seed)
+    src = np.repeat(np.arange(g.n, dtype=np.int64), np.diff(g.row_ptr))
+    dst = g.col.astype(np.int64)
+    keep = src < dst
+    u, v = src[keep], dst[keep]
+    r = rng.random(u.size)
+    fwd = (r < both) | (r >= both + (1.0 - both) / 2)
+    bwd = r < both + (1.0 - both) / 2
+    arcs = np.concatenate([np.stack([u[fwd], v[fwd]], 1), np.stack([v[bwd], u[bwd]], 1)])
+    return digraph_from_arcs(g.n, arcs)
+
+
+def random_digraph(n: int, m: int, seed: int, both: float = 0.2) -> Digraph:
+    """An orientation of the Erdos-Renyi G(n, m) graph."""
+    return orient(erdos_renyi(n, m, seed), seed + 1, both)
+
+
+def symmetric(g: Graph) -> Digraph:
+    """Every edge as two opposite arcs."""
+    return Digraph(g.n, g.row_ptr.copy(), g.col.copy())
+
+
+def transitive_tournament(n: int) -> Digraph:
+    return digraph_from_arcs(n, [(a, b) for a in range(n) for b in range(a + 1, n)])
+
+
+def directed_cycle(n: int) -> Digraph:
+    return digraph_from_arcs(n, [(a, (a + 1) % n) for a in range(n)])
+
+
+def reverse(d: Digraph) -> Digraph:
+    src = np.repeat(np.arange(d.n, dtype=np.int64), np.diff(d.row_ptr))
+    return digraph_from_arcs(d.n, np.stack([d.col.astype(np.int64), src], 1))

@@ -175,3 +175,33 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.returncode == 2
     assert "one GPU only" in r.stderr
     assert r.stdout == ""
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5])
+def test_directed_dictionary_matches_oracle_on_every_code(k):
+    """The directed dictionary the kernel reads: the class of every one of the
+    2^(k(k-1)) codes equals the oracle's (brute force over all k! orders), and
+    each class's smallest code is the oracle's."""
+    T = dm.motif_directed_class_table(k)
+    assert T.dtype == np.uint16 and T.size == 1 << (k * (k - 1))
+    assert dm.motif_directed_num_classes(k) == O.dnum_classes(k)
+    exp = O.dclass_table(k)
+    assert np.array_equal(np.where(T == 0xFFFF, -1, T.astype(np.int64)), exp.astype(np.int64))
+    canon = O.dclass_canon(k)
+    for c in range(0, len(canon), max(1, len(canon) // 97)):
+        assert dm.motif_directed_class_code(k, c) == int(canon[c])
+
+
+def test_directed_host_errors():
+    assert dm.motif_directed_num_classes(6) == -1 and dm.motif_directed_num_classes(0) == -1
+    with pytest.raises(dm.DMError) as e:
+        dm.motif_directed_class_code(3, 13)
+    assert e.value.status == dm.DM_E_ARG
+    with pytest.raises(dm.DMError) as e:
+        dm.motif_directed_class_table(6)
+    assert e.value.status == dm.DM_E_K
+    # arc conventions are checked on the host before any GPU work
+    for rp, col in (([0, 1, 1, 1], [0]), ([0, 2, 2, 2], [2, 1]), ([0, 1, 1, 1], [7]), ([1, 1, 1, 1], [])):
+        with pytest.raises(dm.DMError) as e:
+            dm.load_digraph_csr(3, np.array(rp, np.int64), np.array(col, np.int32))
+        assert e.value.status == dm.DM_E_CSR
