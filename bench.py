@@ -30,9 +30,9 @@ KS = (3, 4, 5, 6, 7, 8)
 # (SQ_INSTS_VALU) and HBM bytes per launch (FETCH_SIZE and WRITE_SIZE, each
 # scaled by what the counter reads for a device copy of known size).  Valid
 # only for the kernel source they were taken on.
-CLIQUE_K8 = {"source_sha": "2211e7bdb24cac1d", "valu_insts": 804065161215.0,
-             "active_lane_fraction": 33392213038493.0 / (64 * 804065161215.0),
-             "hbm_bytes": 2.0 * 837202.5625 * 1024 + 418480.125 * 1024,
+CLIQUE_K8 = {"source_sha": "ca957bc266cf21a8", "valu_insts": 802762808272.0,
+             "active_lane_fraction": 23713261325381.0 / (64 * 802762808272.0),
+             "hbm_bytes": 2.0 * 777285.875 * 1024 + 228454.75 * 1024,
              "profile": "profiles/clique_kernel_cl1m_k8_counters.md"}
 
 
@@ -44,9 +44,12 @@ def kernel_source_sha(kernel: str = "dm_clique.hip") -> str:
     return h.hexdigest()[:16]
 
 
-# HBM bytes per launch of the motif kernel on the sampled 5-motif workload
-# (same scaling), valid only for the kernel source they were taken on.
-TRAFFIC_MOTIF = {"source_sha": "98e6d219ceea12ac", "bytes_per_launch": 2.0 * 233289032.6 * 1024 + 54953631.5 * 1024}
+# Counters of the motif kernel's timed launch on the sampled 5-motif workload
+# (same passes and scaling), valid only for the kernel source they were taken on.
+MOTIF_K5 = {"source_sha": "338cab95d4520563", "valu_insts": 899032450819.0,
+            "active_lane_fraction": 29455662262708.0 / (64 * 899032450819.0),
+            "hbm_bytes": 2.0 * 235390024.6875 * 1024 + 54998852.59375 * 1024,
+            "profile": "profiles/motif_kernel_cl100k_k5_sample_counters.md"}
 # MI355X VALU issue peak: 256 CUs x 4 SIMDs, a wave64 VALU instruction takes
 # 4 cycles on a 16-lane SIMD, at 2.4 GHz: 6.14e11 wave instructions/s, i.e.
 # 39.3e12 lane operations/s.
@@ -453,17 +456,25 @@ def wl_cl100k_motif_sample(args):
                       {"subgraphs": n_sub, "roots": int(len(roots)), "tree_nodes": int(nodes),
                        "adjacency_reads": int(reads), "kernel_ms": kms})
     achieved = alg_bytes / (kms / 1e3) / 1e9
-    sha = kernel_source_sha("dm_motif.hip")
-    out["roofline"] = {
-        "bound": "hbm",
-        "kernel": "motif_kernel",
-        "achieved": achieved,
-        "peak": HBM_PEAK_GBS,
-        "unit": "GB/s",
-        "frac": achieved / HBM_PEAK_GBS,
-        "traffic": TRAFFIC_MOTIF["bytes_per_launch"] if sha == TRAFFIC_MOTIF["source_sha"] else None,
-        "work": f"16 B x {int(nodes)} tree nodes + 4 B x {int(reads)} adjacency entries",
-    }
+    byte_model = {"bytes": alg_bytes, "achieved_GBs": achieved, "frac_of_hbm_peak": achieved / HBM_PEAK_GBS,
+                  "work": f"16 B x {int(nodes)} tree nodes + 4 B x {int(reads)} adjacency entries"}
+    if kernel_source_sha("dm_motif.hip") == MOTIF_K5["source_sha"]:
+        # the nearer ceiling is VALU issue (about half of it is used); HBM
+        # traffic counted per launch is a few percent of its peak
+        ops = 64.0 * MOTIF_K5["valu_insts"] / (kms / 1e3) / 1e12
+        out["roofline"] = {
+            "bound": "alu", "kernel": "motif_kernel", "achieved": ops, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
+            "frac": ops / ALU_PEAK_TOPS, "traffic": MOTIF_K5["hbm_bytes"],
+            "basis": f"SQ_INSTS_VALU = {MOTIF_K5['valu_insts']:.4g} per launch x 64 lanes ({MOTIF_K5['profile']}) "
+                     f"/ this run's HIP-event launch time {kms:.1f} ms",
+            "active_lane_fraction": MOTIF_K5["active_lane_fraction"],
+            "hbm_counted_GBs": MOTIF_K5["hbm_bytes"] / (kms / 1e3) / 1e9,
+            "byte_model": byte_model,
+        }
+    else:
+        out["roofline"] = {"bound": "hbm", "kernel": "motif_kernel", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                           "basis": "byte model (counters stale for this kernel source)", "byte_model": byte_model}
     return out
 
 

@@ -310,6 +310,27 @@ dm_status dm_count_motifs_directed(dm_graph* g, int k, uint64_t* out_counts, siz
                                    const dm_options* opt);
 
 /*
+ * Subgraph matching (Section IV-E: Filter admits subgraph-matching
+ * properties; Section IV-C: patterns as pair bitmaps).  *out_count = the
+ * number of copies of the connected pattern P in g:
+ *   DM_PATTERN_INDUCED: vertex sets S, |S| = k, whose induced subgraph is
+ *     isomorphic to P (the count of P's class);
+ *   otherwise: subgraphs of g (vertex set and edge subset) isomorphic to P,
+ *     i.e. monomorphisms of P into g divided by |Aut(P)|, computed as
+ *     sum over classes H of count(H) x (copies of P spanning H).
+ * pattern: P's code on k vertices in any vertex order: one bit per pair
+ * (bit i(i-1)/2 + t = edge t-i, k in 3..8), or with DM_PATTERN_DIRECTED two
+ * bits per pair as in the directed dictionary (k in 3..5; g from
+ * dm_load_digraph).  Runs dm_count_motifs / dm_count_motifs_directed with opt.
+ * Errors: DM_E_ARG (null pointers, unknown flag, bits beyond k vertices, a
+ * pattern that is not (weakly) connected), DM_E_K, DM_E_OVERFLOW, and those of
+ * the counting call.
+ */
+enum { DM_PATTERN_INDUCED = 1, DM_PATTERN_DIRECTED = 2 };
+dm_status dm_count_pattern(dm_graph* g, int k, uint32_t pattern, uint32_t flags, uint64_t* out_count,
+                           const dm_options* opt);
+
+/*
  * Count many graphs in one persistent launch.  op is DM_OP_CLIQUE (one count
  * per graph) or DM_OP_MOTIF (ncls(k) counts per graph).  out_counts is
  * row-major [num_graphs][per-graph width].  The graphs are concatenated as a

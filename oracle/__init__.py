@@ -515,3 +515,78 @@ def dmotif_count(dg, k: int, threads: int = 1) -> np.ndarray:
     if rc != 0:
         raise ValueError("bad arguments")
     return out[:dnum_classes(k)]
+
+
+# ------------------------------------------------------------------ subgraph matching
+
+def _pattern_arcs(k: int, code: int, directed: bool):
+    """Adjacency (k x k booleans) of a pattern code: undirected, bit
+    i(i-1)/2 + t = edge t-i; directed, bit 2p = arc t->i and bit 2p+1 =
+    arc i->t (p = i(i-1)/2 + t)."""
+    A = np.zeros((k, k), dtype=bool)
+    for i in range(1, k):
+        for t in range(i):
+            p = i * (i - 1) // 2 + t
+            if directed:
+                A[t, i] = bool(code >> (2 * p) & 1)
+                A[i, t] = bool(code >> (2 * p + 1) & 1)
+            else:
+                A[t, i] = A[i, t] = bool(code >> p & 1)
+    return A
+
+
+def _embeddings(A, n, has, induced):
+    """Injective maps phi of the pattern's vertices into 0..n-1 with
+    has(phi(a), phi(b)) whenever A[a, b] (and only then, if induced)."""
+    k = A.shape[0]
+    und = A | A.T
+    order = [0]  # a connected order: each next vertex adjacent to an earlier one
+    while len(order) < k:
+        order.append(next(v for v in range(k) if v not in order and any(und[v, u] for u in order)))
+    phi = [-1] * k
+    used = set()
+    count = 0
+
+    def ok(a, x):
+        for b in range(k):
+            if phi[b] < 0:
+                continue
+            y = phi[b]
+            if A[a, b] and not has(x, y):
+                return False
+            if A[b, a] and not has(y, x):
+                return False
+            if induced and (not A[a, b] and has(x, y) or not A[b, a] and has(y, x)):
+                return False
+        return True
+
+    def rec(j):
+        nonlocal count
+        if j == k:
+            count += 1
+            return
+        a = order[j]
+        for x in range(n):
+            if x not in used and ok(a, x):
+                phi[a] = x
+                used.add(x)
+                rec(j + 1)
+                used.discard(x)
+                phi[a] = -1
+
+    rec(0)
+    return count
+
+
+def pattern_count_brute(g, k: int, code: int, induced: bool = False, directed: bool = False) -> int:
+    """Copies of the connected pattern P (a code on k vertices) in g, by the
+    definition: edge-preserving injective maps of P into g (also non-edge
+    preserving when induced), divided by the maps of P onto itself.  g: an
+    undirected Graph, or a Digraph with directed=True.  Pure Python: small
+    graphs only."""
+    A = _pattern_arcs(k, code, directed)
+    adj = [set(int(x) for x in g.col[g.row_ptr[v]:g.row_ptr[v + 1]]) for v in range(g.n)]
+    emb = _embeddings(A, g.n, lambda x, y: y in adj[x], induced)
+    aut = _embeddings(A, k, lambda x, y: bool(A[x, y]), True)
+    assert emb % aut == 0
+    return emb // aut

@@ -2267,3 +2267,92 @@ extern "C" dm_status dm_count_motifs_directed(dm_graph* g, int k, uint64_t* out_
   if (st == DM_OK) std::memcpy(out_counts, tmp.data(), sizeof(uint64_t) * T->ncls);
   return st;
 }
+
+// ====================================================================== pattern matching
+
+namespace {
+
+// Images of a pattern code under vertex orders.  Copies of a connected
+// pattern P spanning a k-vertex graph H = the distinct images of P that are
+// subgraphs of H (= |{orders s : s(P) in H}| / |Aut(P)|).  Undirected codes
+// have one bit per pair, directed codes two (the layouts of the two
+// dictionaries).
+struct PatternCopies {
+  std::vector<std::vector<int>> perms;
+  int k = 0;
+  bool directed = false;
+  uint32_t image(uint32_t code, const std::vector<int>& p) const {
+    uint32_t img = 0;
+    for (int i = 1; i < k; ++i)
+      for (int t = 0; t < i; ++t) {
+        const int a = p[t], b = p[i];
+        if (!directed) {
+          if ((code >> pair_index(t, i)) & 1u) img |= 1u << (a < b ? pair_index(a, b) : pair_index(b, a));
+        } else {
+          const int bit = 2 * pair_index(t, i);
+          // arc t -> i becomes a -> b, arc i -> t becomes b -> a
+          if ((code >> bit) & 1u) img |= a < b ? 1u << (2 * pair_index(a, b)) : 1u << (2 * pair_index(b, a) + 1);
+          if ((code >> (bit + 1)) & 1u) img |= a < b ? 1u << (2 * pair_index(a, b) + 1) : 1u << (2 * pair_index(b, a));
+        }
+      }
+    return img;
+  }
+};
+
+}  // namespace
+
+extern "C" dm_status dm_count_pattern(dm_graph* g, int k, uint32_t pattern, uint32_t flags, uint64_t* out_count,
+                                      const dm_options* opt) {
+  if (!g || !out_count) return fail(DM_E_ARG, "null graph or output");
+  if (flags & ~3u) return fail(DM_E_ARG, "unknown pattern flag");
+  const bool directed = flags & DM_PATTERN_DIRECTED;
+  const bool induced = flags & DM_PATTERN_INDUCED;
+  if (directed ? (k < 3 || k > kDMotifMaxK) : (k < 3 || k > kMotifMaxK))
+    return fail(DM_E_K, directed ? "directed pattern k must be in 3..5" : "pattern k must be in 3..8");
+  const int bits = directed ? k * (k - 1) : k * (k - 1) / 2;
+  if (bits < 32 && (pattern >> bits)) return fail(DM_E_ARG, "pattern code has bits beyond its k vertices");
+  // the pattern's class: its smallest code over all vertex orders
+  PatternCopies pc;
+  pc.k = k;
+  pc.directed = directed;
+  std::vector<int> p(k);
+  for (int i = 0; i < k; ++i) p[i] = i;
+  do pc.perms.push_back(p);
+  while (std::next_permutation(p.begin(), p.end()));
+  // the distinct images of P under all vertex orders: its copies on k labelled
+  // vertices (k! / |Aut(P)| of them); the smallest is P's class
+  std::vector<uint32_t> imgs;
+  imgs.reserve(pc.perms.size());
+  for (const auto& q : pc.perms) imgs.push_back(pc.image(pattern, q));
+  std::sort(imgs.begin(), imgs.end());
+  imgs.erase(std::unique(imgs.begin(), imgs.end()), imgs.end());
+  const uint32_t canon = imgs.front();
+  uint32_t und = pattern;
+  if (directed) {
+    und = 0;
+    for (int pi = 0; pi < k * (k - 1) / 2; ++pi)
+      if ((pattern >> (2 * pi)) & 3u) und |= 1u << pi;
+  }
+  if (!bitmap_connected(k, und)) return fail(DM_E_ARG, "the pattern must be (weakly) connected");
+  const int ncls = directed ? dtables(k)->ncls : tables(k)->ncls;
+  const std::vector<uint32_t>& reps = directed ? dtables(k)->canon : tables(k)->canon;
+  std::vector<uint64_t> c(ncls);
+  dm_status st = directed ? dm_count_motifs_directed(g, k, c.data(), c.size(), opt)
+                          : dm_count_motifs(g, k, c.data(), c.size(), opt);
+  if (st != DM_OK) return st;
+  uint64_t sum = 0;
+  for (int q = 0; q < ncls; ++q) {
+    if (c[q] == 0) continue;
+    uint64_t copies = 0;
+    if (induced) {
+      copies = reps[q] == canon ? 1 : 0;
+    } else {
+      for (const uint32_t u : imgs) copies += (u & ~reps[q]) == 0;  // copies of P spanning the class's graph
+    }
+    uint64_t add = 0;
+    if (__builtin_mul_overflow(c[q], copies, &add) || __builtin_add_overflow(sum, add, &sum))
+      return fail(DM_E_OVERFLOW, "pattern count wrapped");
+  }
+  *out_count = sum;
+  return DM_OK;
+}
