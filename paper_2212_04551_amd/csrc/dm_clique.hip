@@ -162,11 +162,34 @@ __device__ __forceinline__ uint64_t count_in(const uint64_t (&C)[NW], LdsU64* lr
   }
 }
 
+typedef __attribute__((address_space(3))) const uint32_t LdsU32;
+
 // Edges inside the set C (rows upper-triangular), one member per iteration: a
 // lane's loop over its own set, so the per-iteration work is one row read, an
-// AND and a popcount.
+// AND and a popcount.  One-word sets are walked as two 32-bit halves: a member
+// of the low half needs both halves of its row, one of the high half only the
+// high half (its row has no lower members), and finding and clearing the next
+// member are 32-bit operations (about a third fewer instructions per member).
 template <int NW>
 __device__ __forceinline__ uint32_t edge_count(const uint64_t (&C)[NW], LdsU64* lr, int stride) {
+  if constexpr (NW == 1) {
+    const uint32_t clo = static_cast<uint32_t>(C[0]), chi = static_cast<uint32_t>(C[0] >> 32);
+    LdsU32* lr32 = (LdsU32*)(lr);
+    uint32_t s = 0;
+    uint32_t x = clo;
+    while (x) {
+      const int i = __builtin_ctz(x);
+      x &= x - 1;
+      s += static_cast<uint32_t>(__popc(clo & lr32[2 * i]) + __popc(chi & lr32[2 * i + 1]));
+    }
+    x = chi;
+    while (x) {
+      const int i = 32 + __builtin_ctz(x);
+      x &= x - 1;
+      s += static_cast<uint32_t>(__popc(chi & lr32[2 * i + 1]));
+    }
+    return s;
+  }
   uint32_t s = 0;
 #pragma unroll
   for (int w = 0; w < NW; ++w) {

@@ -13,8 +13,10 @@
 //     undirected lists, keeping for every list entry its undirected adjacency
 //     mask over the traversal and two arc bits per traversal vertex.  The
 //     directed pattern code of Section IV-C's bitmap takes two bits per vertex
-//     pair; at |tr| = k-1 every canonical entry completes one subgraph whose
-//     class comes from a dictionary over all 2^(k(k-1)) codes.
+//     pair.  Once |tr| = k-2, each canonical x and every canonical y of the
+//     extension set that x's step would build complete one subgraph, counted
+//     without building that set; its class comes from a dictionary over all
+//     2^(k(k-1)) codes.
 #include <hipcub/hipcub.hpp>
 
 #include "dm_internal.hpp"
@@ -363,6 +365,70 @@ __device__ int next_dcanonical(const DMotifArgs& A, const DLds& L, const DWave& 
   return -1;
 }
 
+// The last two levels at once: x = v_{k-2} is appended to tr (|tr| = k-2)
+// and every canonical y of the extension set that follows is counted at
+// once, without writing that set: x's neighbours new to the set are
+// canonical (their only traversal neighbour is x, and they lie above the
+// root), and an old entry's mask and arc bits gain x's bit from the marks its
+// neighbour scan leaves.
+__device__ void dleaf(const DMotifArgs& A, const DLds& L, const DWave& W, int s, int px, int x, uint64_t& pending) {
+  const int lane = lane_id();
+  const int32_t* Ev = W.vert + A.level_off[s];
+  const uint8_t* Em = W.mask + A.level_off[s];
+  const uint16_t* Ea = W.arcs + A.level_off[s];
+  const int ns = L.esize[s];
+  if (lane == 0) {
+    L.tr[s] = x;
+    L.dcode[s + 1] = L.dcode[s] | static_cast<int>((Ea[px] & ((1u << (2 * s)) - 1u)) << (s * (s - 1)));
+    for (int f = 0; f < s; ++f) {
+      const int a = L.sufmax[s * kDSlots + f];
+      L.sufmax[(s + 1) * kDSlots + f] = a > x ? a : x;
+    }
+    L.sufmax[(s + 1) * kDSlots + s] = -1;
+  }
+  wave_sync();
+  const int base = L.dcode[s + 1];
+  const int shift = (s + 1) * s;  // v_{s+1}'s pairs with tr[0..s]
+  const int v0 = L.tr[0];
+  const int64_t xb = A.rp[x];
+  const int dx = static_cast<int>(A.rp[x + 1] - xb);
+  for (int c = 0; c < dx; c += kWave) {
+    const int i = c + lane;
+    const bool ok = i < dx && A.col[xb + i] > v0;
+    const int w = ok ? A.col[xb + i] : 0;
+    const unsigned d = ok ? A.dir[xb + i] : 0u;
+    const int j = ok ? lower_bound_i32(Ev, ns, w) : ns;
+    const bool found = ok && j < ns && Ev[j] == w;
+    if (found && j != px) W.hit[j] = static_cast<uint8_t>(0x80u | d);
+    bool intr = false;
+    for (int t = 0; t < s; ++t) intr |= (L.tr[t] == w);
+    const bool isnew = ok && !found && !intr;
+    if (isnew) {
+      const int cls = A.table[base | static_cast<int>(((d & 3u) << (2 * s)) << shift)];
+      if (cls == kUnreachable) atomicOr(A.flags + 1, 2);
+      else atomicAdd(L.cnt + cls, 1u);
+    }
+    pending += static_cast<uint64_t>(__popcll(ballot(isnew)));
+  }
+  wave_sync();
+  for (int c = 0; c < ns; c += kWave) {
+    const int j = c + lane;
+    const bool valid = j < ns && j != px;
+    const unsigned h = valid ? W.hit[j] : 0u;
+    const unsigned m = valid ? (Em[j] | ((h & 0x80u) ? (1u << s) : 0u)) : 0u;
+    const bool ok = valid && dcanonical(L, s + 1, Ev[j], m);
+    if (ok) {
+      const unsigned arcs = Ea[j] | ((h & 3u) << (2 * s));
+      const int cls = A.table[base | static_cast<int>(arcs << shift)];
+      if (cls == kUnreachable) atomicOr(A.flags + 1, 2);
+      else atomicAdd(L.cnt + cls, 1u);
+    }
+    if (h) W.hit[j] = 0;
+    pending += static_cast<uint64_t>(__popcll(ballot(ok)));
+  }
+  wave_sync();
+}
+
 // Every weakly connected induced k-subgraph rooted at v0 (its smallest id)
 // is counted once in its class.  `pending` counts increments since the last
 // flush of the 32-bit LDS counters.
@@ -393,33 +459,6 @@ __device__ void dmotif_root(const DMotifArgs& A, const DLds& L, const DWave& W, 
   wave_sync();
   int s = 1;
   for (;;) {
-    if (s == k - 1) {
-      const int32_t* E = W.vert + A.level_off[s];
-      const uint8_t* Em = W.mask + A.level_off[s];
-      const uint16_t* Ea = W.arcs + A.level_off[s];
-      const int ns = L.esize[s];
-      const int shift = s * (s - 1);
-      const unsigned low2 = (1u << (2 * s)) - 1u;
-      const int base = L.dcode[s];
-      for (int c = 0; c < ns; c += kWave) {
-        const int j = c + lane;
-        const bool ok = j < ns && dcanonical(L, s, E[j], Em[j]);
-        if (ok) {
-          const int code = base | static_cast<int>((Ea[j] & low2) << shift);
-          const int cls = A.table[code];
-          if (cls == kUnreachable) atomicOr(A.flags + 1, 2);
-          else atomicAdd(L.cnt + cls, 1u);
-        }
-        pending += static_cast<uint64_t>(__popcll(ballot(ok)));
-      }
-      if (pending >= (1ull << 31)) {
-        dflush(A, L);
-        pending = 0;
-      }
-      if (s == 1) break;
-      --s;
-      continue;
-    }
     const int idx = next_dcanonical(A, L, W, s, L.cursor[s], L.endv[s]);
     if (idx < 0) {
       if (s == 1) break;
@@ -428,6 +467,14 @@ __device__ void dmotif_root(const DMotifArgs& A, const DLds& L, const DWave& W, 
     }
     const int x = W.vert[A.level_off[s] + idx];
     if (lane == 0) L.cursor[s] = idx + 1;
+    if (s == k - 2) {
+      dleaf(A, L, W, s, idx, x, pending);
+      if (pending >= (1ull << 31)) {
+        dflush(A, L);
+        pending = 0;
+      }
+      continue;
+    }
     dextend(A, L, W, s, idx, x);
     ++s;
     if (lane == 0) {

@@ -27,6 +27,7 @@ DM_SCHED_COST = 16
 DM_IMPL_DFS = 32
 DM_SCHED_HOST_BALANCE = 64
 DM_OP_CLIQUE, DM_OP_MOTIF = 0, 1
+DM_PATTERN_INDUCED, DM_PATTERN_DIRECTED = 1, 2
 DM_MLP_NET = 4 * 64 + 64 + 64 * 64 + 64 + 64 + 1  # 4 -> 64 -> 64 -> 1 weights
 DM_MLP_NPARAMS = DM_MLP_NET + 8                     # + feature mean[4], std[4]
 
@@ -35,7 +36,7 @@ EXPORTS = [
     "dm_motif_class_mask", "dm_motif_class_table", "dm_motif_class_table16", "dm_count_motifs",
     "dm_count_motifs_static", "dm_batch", "dm_list", "dm_induced_subgraph", "dm_count_quasi_cliques",
     "dm_load_digraph", "dm_digraph_info", "dm_motif_directed_num_classes", "dm_motif_directed_class_code",
-    "dm_motif_directed_class_table", "dm_count_motifs_directed",
+    "dm_motif_directed_class_table", "dm_count_motifs_directed", "dm_count_pattern",
     "dm_strerror", "dm_last_error", "dm_last_launch_count", "dm_features", "dm_mlp_init", "dm_mlp_fit_normalizer",
     "dm_mlp_forward", "dm_mlp_targets", "dm_mlp_loss_grad", "dm_mlp_adam_step", "dm_mlp_train", "dm_autotune",
 ]
@@ -125,6 +126,9 @@ def lib():
     L.dm_motif_directed_class_table.argtypes = [ctypes.c_int, vp, ctypes.c_size_t]
     L.dm_count_motifs_directed.restype = ctypes.c_int
     L.dm_count_motifs_directed.argtypes = [vp, ctypes.c_int, vp, ctypes.c_size_t, ctypes.POINTER(dm_options)]
+    L.dm_count_pattern.restype = ctypes.c_int
+    L.dm_count_pattern.argtypes = [vp, ctypes.c_int, u32, u32, ctypes.POINTER(ctypes.c_uint64),
+                                   ctypes.POINTER(dm_options)]
     L.dm_count_quasi_cliques.restype = ctypes.c_int
     L.dm_count_quasi_cliques.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64),
                                          ctypes.POINTER(dm_options)]
@@ -551,3 +555,13 @@ def count_motifs_directed(g: DMGraph, k: int, **opt) -> np.ndarray:
     _check(lib().dm_count_motifs_directed(g.handle, k, out.ctypes.data, out.size if nc > 0 else 0, ctypes.byref(o)))
     del keep
     return out[:nc]
+
+
+def count_pattern(g: DMGraph, k: int, code: int, induced: bool = False, directed: bool = False, **opt) -> int:
+    """dm_count_pattern: copies of a connected pattern (its pair-bitmap code on k vertices)."""
+    flags = (DM_PATTERN_INDUCED if induced else 0) | (DM_PATTERN_DIRECTED if directed else 0)
+    out = ctypes.c_uint64(0)
+    o, keep = make_options(**opt)
+    _check(lib().dm_count_pattern(g.handle, k, ctypes.c_uint32(code), flags, ctypes.byref(out), ctypes.byref(o)))
+    del keep
+    return int(out.value)
