@@ -30,9 +30,9 @@ KS = (3, 4, 5, 6, 7, 8)
 # (SQ_INSTS_VALU) and HBM bytes per launch (FETCH_SIZE and WRITE_SIZE, each
 # scaled by what the counter reads for a device copy of known size).  Valid
 # only for the kernel source they were taken on.
-CLIQUE_K8 = {"source_sha": "ca957bc266cf21a8", "valu_insts": 802762808272.0,
-             "active_lane_fraction": 23713261325381.0 / (64 * 802762808272.0),
-             "hbm_bytes": 2.0 * 777285.875 * 1024 + 228454.75 * 1024,
+CLIQUE_K8 = {"source_sha": "d6e1706eb4102345", "valu_insts": 618152677106.0,
+             "active_lane_fraction": 18407614113773.0 / (64 * 618152677106.0),
+             "hbm_bytes": 2.0 * 710069.25 * 1024 + 214022.6875 * 1024,
              "profile": "profiles/clique_kernel_cl1m_k8_counters.md"}
 
 

@@ -162,8 +162,6 @@ __device__ __forceinline__ uint64_t count_in(const uint64_t (&C)[NW], LdsU64* lr
   }
 }
 
-typedef __attribute__((address_space(3))) const uint32_t LdsU32;
-
 // Edges inside the set C (rows upper-triangular), one member per iteration: a
 // lane's loop over its own set, so the per-iteration work is one row read, an
 // AND and a popcount.  One-word sets are walked as two 32-bit halves: a member
@@ -173,20 +171,22 @@ typedef __attribute__((address_space(3))) const uint32_t LdsU32;
 template <int NW>
 __device__ __forceinline__ uint32_t edge_count(const uint64_t (&C)[NW], LdsU64* lr, int stride) {
   if constexpr (NW == 1) {
+    // (rows are read as whole 64-bit words: 32-bit reads of one half cost
+    // more in LDS bank conflicts than they save)
     const uint32_t clo = static_cast<uint32_t>(C[0]), chi = static_cast<uint32_t>(C[0] >> 32);
-    LdsU32* lr32 = (LdsU32*)(lr);
     uint32_t s = 0;
     uint32_t x = clo;
     while (x) {
       const int i = __builtin_ctz(x);
       x &= x - 1;
-      s += static_cast<uint32_t>(__popc(clo & lr32[2 * i]) + __popc(chi & lr32[2 * i + 1]));
+      const uint64_t r = lr[i];
+      s += static_cast<uint32_t>(__popc(clo & static_cast<uint32_t>(r)) + __popc(chi & static_cast<uint32_t>(r >> 32)));
     }
     x = chi;
     while (x) {
       const int i = 32 + __builtin_ctz(x);
       x &= x - 1;
-      s += static_cast<uint32_t>(__popc(chi & lr32[2 * i + 1]));
+      s += static_cast<uint32_t>(__popc(chi & static_cast<uint32_t>(lr[i] >> 32)));
     }
     return s;
   }
