@@ -140,6 +140,21 @@ def base_record(metric_value, ms_per_step, steps, warmup, workload, extra_config
     }
 
 
+def device_info():
+    """The GPU and software the line was measured on."""
+    import torch
+    p = torch.cuda.get_device_properties(0)
+    info = {"name": p.name, "arch": getattr(p, "gcnArchName", ""), "compute_units": p.multi_processor_count,
+            "memory_GiB": round(p.total_memory / 2**30, 1), "hip": getattr(torch.version, "hip", None),
+            "torch": torch.__version__}
+    try:
+        from paper_2212_04551_amd import dm
+        info["library"] = os.path.relpath(dm.LIB_PATH, ROOT)
+    except Exception:  # noqa: BLE001 - informational only
+        pass
+    return info
+
+
 def timed_steps(fn, steps, warmup, label):
     import torch
     for w in range(warmup):
@@ -857,6 +872,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     out = WORKLOADS[args.workload](args)
+    out["device"] = device_info()
     print(json.dumps(out), flush=True)
 
 
