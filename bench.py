@@ -865,8 +865,8 @@ def main():
                     help="also run one device copy of 1 GiB (counter calibration for profiles)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU design is described "
-              f"in DESIGN.md and is not implemented", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): sharding the roots over several "
+              f"GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
