@@ -685,6 +685,8 @@ def wl_directed(args):
     from paper_2212_04551_amd import graphgen as gg
 
     stream = torch.cuda.current_stream()
+    if args.copy_probe:
+        copy_probe()
     rows = []
     for gname, ks in (("cl100k_m5e5_cap100", (3, 4, 5)),):
         d = gg.orient(gg.chung_lu(100_000, 500_000, 2.3, 100.0, args.seed)[0], args.seed + 1, both=0.2)
