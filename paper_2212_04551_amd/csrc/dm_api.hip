@@ -398,6 +398,8 @@ struct dm_graph {
   bool directed = false;
   int64_t arcs = 0;
   Buf dir, ext_arcs, dhit, dndir;
+  Buf rdir;             // arc bits in the rank-renamed graph (urp / ucol)
+  bool dranked = false;
   // learned ordering: features (cached), predictions, LPT order, chunk starts
   // and the order in rank space; the queue is reused while the parameter
   // fingerprint, grid and chunks per wave stay the same
@@ -2192,6 +2194,31 @@ extern "C" dm_status dm_motif_directed_class_table(int k, uint16_t* out, size_t 
   return DM_OK;
 }
 
+namespace {
+
+// launch shapes by (classes, waves-per-CU cap): the search asks the runtime
+// for the residency of ~100 shapes
+std::mutex g_dplan_lock;
+std::vector<std::pair<std::pair<int, int>, DMotifPlan>> g_dplans;
+
+hipError_t dmotif_plan_cached(int ncls, int max_waves, DMotifPlan* plan) {
+  std::lock_guard<std::mutex> lk(g_dplan_lock);
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  const std::pair<int, int> key(ncls + (dev << 20), max_waves);
+  for (const auto& p : g_dplans)
+    if (p.first == key) {
+      *plan = p.second;
+      return hipSuccess;
+    }
+  e = dmotif_plan(ncls, max_waves, plan);
+  if (e == hipSuccess) g_dplans.emplace_back(key, *plan);
+  return e;
+}
+
+}  // namespace
+
 extern "C" dm_status dm_count_motifs_directed(dm_graph* g, int k, uint64_t* out_counts, size_t out_len,
                                               const dm_options* opt) {
   if (!g || !out_counts) return fail(DM_E_ARG, "null graph or output");
@@ -2208,13 +2235,31 @@ extern "C" dm_status dm_count_motifs_directed(dm_graph* g, int k, uint64_t* out_
   uint16_t* dtab = nullptr;
   HIP_OR_RETURN(device_table(k + 100, &dtab), "directed class table upload");
   const int dmax = g->dmax > 0 ? g->dmax : 1;
-  const size_t lds = dmotif_lds_bytes(T->ncls);
-  int per_cu = 0;
-  HIP_OR_RETURN(dmotif_occupancy(lds, &per_cu), "occupancy");
-  if (per_cu < 1) per_cu = 1;
-  if (per_cu > 16) per_cu = 16;
-  if (o.waves_per_cu && static_cast<int>(o.waves_per_cu) < per_cu) per_cu = static_cast<int>(o.waves_per_cu);
-  const int grid = size_grid(per_cu, g->nnz);
+  if (dmax >= (1 << 26)) return fail(DM_E_ARG, "directed motifs need every degree below 2^26");
+  // the traversal runs on the graph renamed by (degree, id) rank, like the
+  // undirected motifs: a subgraph's root is its lowest-rank vertex, so hubs
+  // root few subgraphs and no single root's tree dominates the launch
+  st = ensure_ranked(g, s);
+  if (st != DM_OK) return st;
+  if (!g->dranked) {
+    HIP_OR_RETURN(g->rdir.ensure(static_cast<size_t>(g->nnz > 0 ? g->nnz : 1)), "rank arc bits: allocate");
+    HIP_OR_RETURN(g->ctrl.ensure(ctrl_bytes()), "workspace");
+    int bad = 0;
+    hipError_t e = launch_fill_u64(g->ctrl.as<unsigned long long>(), static_cast<int64_t>(ctrl_bytes() / 8), 0ull, s);
+    if (e == hipSuccess)
+      e = digraph_rank_dir(g->rp.as<int64_t>(), g->col.as<int32_t>(), g->dir.as<uint8_t>(), g->n, g->rank.as<int32_t>(),
+                           g->urp.as<int64_t>(), g->ucol.as<int32_t>(), g->rdir.as<uint8_t>(), ctrl_flags(g), s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&bad, ctrl_flags(g), sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "rank arc bits");
+    if (bad) return fail(DM_E_CSR, "rank arc bits: the renamed graph is missing an entry");
+    g->dranked = true;
+  }
+  DMotifPlan plan;
+  HIP_OR_RETURN(dmotif_plan_cached(T->ncls, static_cast<int>(o.waves_per_cu), &plan), "directed motif launch shape");
+  const int nw = plan.waves_per_group;
+  // workgroups: the shape's residency over the CUs, fewer on a small graph
+  const int grid = std::max(1, size_grid(plan.groups_per_cu * nw, g->nnz) / nw);
   DMotifArgs A;
   std::memset(&A, 0, sizeof(A));
   int64_t cap_total = 0;
@@ -2225,7 +2270,8 @@ extern "C" dm_status dm_count_motifs_directed(dm_graph* g, int k, uint64_t* out_
   }
   A.hit_cap = static_cast<int64_t>(k - 1) * dmax;
   A.wave_cap = cap_total;
-  const size_t gw = static_cast<size_t>(grid);
+  A.leaf_cap = plan.leaf_cap;
+  const size_t gw = static_cast<size_t>(grid) * nw;
   HIP_OR_RETURN(g->ctrl.ensure(ctrl_bytes()), "workspace");
   HIP_OR_RETURN(g->out.ensure(sizeof(uint64_t) * T->ncls), "workspace");
   HIP_OR_RETURN(g->ext_vert.ensure(sizeof(int32_t) * gw * cap_total), "workspace");
@@ -2234,11 +2280,11 @@ extern "C" dm_status dm_count_motifs_directed(dm_graph* g, int k, uint64_t* out_
   HIP_OR_RETURN(g->dhit.ensure(gw * A.hit_cap), "workspace");
   HIP_OR_RETURN(g->newbuf.ensure(sizeof(int32_t) * gw * dmax), "workspace");
   HIP_OR_RETURN(g->dndir.ensure(gw * dmax), "workspace");
-  Sched S = make_sched(g, o, grid, g->n, nullptr, nullptr);
+  Sched S = make_sched(g, o, static_cast<int>(gw), g->n, nullptr, nullptr);
   S.donate = 0;  // roots only: no donated task states for this kernel
-  A.rp = g->rp.as<int64_t>();
-  A.col = g->col.as<int32_t>();
-  A.dir = g->dir.as<uint8_t>();
+  A.rp = g->urp.as<int64_t>();
+  A.col = g->ucol.as<int32_t>();
+  A.dir = g->rdir.as<uint8_t>();
   A.n = g->n;
   A.k = k;
   A.dmax = dmax;
@@ -2257,7 +2303,7 @@ extern "C" dm_status dm_count_motifs_directed(dm_graph* g, int k, uint64_t* out_
   int flags[2] = {0, 0};
   hipError_t e = launch_fill_u64(g->ctrl.as<unsigned long long>(), static_cast<int64_t>(ctrl_bytes() / 8), 0ull, s);
   if (e == hipSuccess) e = launch_fill_u64(A.out, T->ncls, 0ull, s);
-  if (e == hipSuccess && g->n > 0) e = launch_dmotif(A, grid, lds, s);
+  if (e == hipSuccess && g->n > 0) e = launch_dmotif(A, grid, nw, plan.lds, s);
   std::vector<uint64_t> tmp(T->ncls);
   if (e == hipSuccess) e = hipMemcpyAsync(tmp.data(), A.out, sizeof(uint64_t) * T->ncls, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipMemcpyAsync(flags, A.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, s);

@@ -111,7 +111,38 @@ __global__ void __launch_bounds__(256) union_kernel(const int64_t* rp, const int
   if (!kFill) udeg[v] = cnt;
 }
 
+// The arc bits of every entry at its place in the rank-renamed graph: row
+// rank[u], the entry of rank[w] (renaming keeps the pair's orientation, so
+// the bits are unchanged).
+__global__ void rank_dir_kernel(const int64_t* rp, const int32_t* col, const uint8_t* dir, int32_t n,
+                                const int32_t* rank, const int64_t* urp, const int32_t* ucol, uint8_t* udir,
+                                int* flag) {
+  const int64_t u = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (u >= n) return;
+  const int ru = rank[u];
+  const int64_t b = urp[ru];
+  const int len = static_cast<int>(urp[ru + 1] - b);
+  for (int64_t e = rp[u]; e < rp[u + 1]; ++e) {
+    const int rw = rank[col[e]];
+    int lo = 0, hi = len;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (ucol[b + mid] < rw) lo = mid + 1; else hi = mid;
+    }
+    if (lo < len && ucol[b + lo] == rw) udir[b + lo] = dir[e];
+    else atomicOr(flag, 1);  // the renamed graph lacks the entry
+  }
+}
+
 }  // namespace
+
+hipError_t digraph_rank_dir(const int64_t* rp, const int32_t* col, const uint8_t* dir, int32_t n, const int32_t* rank,
+                            const int64_t* urp, const int32_t* ucol, uint8_t* udir, int* flag, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(rank_dir_kernel, dim3(nblocks(n, 256)), dim3(256), 0, s, rp, col, dir, n, rank, urp, ucol, udir,
+                     flag);
+  return hipGetLastError();
+}
 
 #define DG_TRY(x)                          \
   do {                                     \
@@ -200,6 +231,21 @@ done:
 namespace {
 
 constexpr int kDSlots = kDMotifMaxK + 1;
+constexpr int kDMaxWaves = 8;  // waves per workgroup
+// the level k-2 list (the one every x step at the last levels searches) is
+// built in LDS when it has at most this many entries
+typedef __attribute__((address_space(3))) int32_t LdsI32d;
+typedef __attribute__((address_space(3))) uint16_t LdsU16d;
+typedef __attribute__((address_space(3))) uint8_t LdsU8d;
+
+// The workgroup's waves run independent traversals (they share only the class
+// counters), so lanes of one wave order their LDS and memory traffic with a
+// wave-scope fence pair, never with a workgroup barrier.
+__device__ __forceinline__ void dsync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 struct DLds {
   int* tr;        // [kDSlots] traversal
@@ -208,13 +254,26 @@ struct DLds {
   int* cursor;    // [kDSlots]
   int* endv;      // [kDSlots]
   int* esize;     // [kDSlots]
-  int* nnew;      // [1] new entries of the extension in progress
+  int* nnew;      // [4] [1]: the level k-2 list is in lv / lm / la
+  int32_t* lv;    // [leaf_cap] level k-2 list in LDS (when it fits): vertex
+  uint16_t* la;   // [leaf_cap] arc bits
+  uint8_t* lm;    // [leaf_cap] undirected mask
+  uint8_t* lhit;  // [leaf_cap] marks of the entries an x step touches
   unsigned* cnt;  // [ncls] class counters since the last flush
 };
 
-__device__ DLds dcarve(unsigned char* smem) {
+constexpr int kDLdsInts = 3 * kDSlots + kDSlots * kDSlots + 3 * kDSlots + 4;
+
+// per-wave bytes: the traversal state and the LDS level list
+__host__ __device__ constexpr size_t dwave_lds_bytes(int leaf_cap) {
+  return kDLdsInts * sizeof(int) + static_cast<size_t>(leaf_cap) * (4 + 2 + 1 + 1);
+}
+
+// Wave wid's part of the workgroup's LDS; the class counters after the
+// nw waves' parts are shared by the workgroup.
+__device__ DLds dcarve(unsigned char* smem, int leaf_cap, int wid, int nw) {
   DLds L;
-  int* p = reinterpret_cast<int*>(smem);
+  int* p = reinterpret_cast<int*>(smem + wid * dwave_lds_bytes(leaf_cap));
   L.tr = p;
   L.dcode = p + kDSlots;
   L.sufmax = p + 2 * kDSlots;
@@ -222,7 +281,11 @@ __device__ DLds dcarve(unsigned char* smem) {
   L.endv = L.cursor + kDSlots;
   L.esize = L.endv + kDSlots;
   L.nnew = L.esize + kDSlots;
-  L.cnt = reinterpret_cast<unsigned*>(L.nnew + 4);
+  L.lv = L.nnew + 4;
+  L.la = reinterpret_cast<uint16_t*>(L.lv + leaf_cap);
+  L.lm = reinterpret_cast<uint8_t*>(L.la + leaf_cap);
+  L.lhit = L.lm + leaf_cap;
+  L.cnt = reinterpret_cast<unsigned*>(smem + nw * dwave_lds_bytes(leaf_cap));
   return L;
 }
 
@@ -291,11 +354,12 @@ __device__ void dextend(const DMotifArgs& A, const DLds& L, const DWave& W, int 
     if (lane == 0) atomicOr(A.flags + 1, 1);
     nn = A.dmax;
   }
-  int32_t* Nv = W.vert + A.level_off[s + 1];
-  uint8_t* Nm = W.mask + A.level_off[s + 1];
-  uint16_t* Na = W.arcs + A.level_off[s + 1];
-  const int64_t cap = A.level_cap[s + 1];
-  wave_sync();
+  const bool to_lds = s + 1 == A.k - 2 && static_cast<int64_t>(ns) - 1 + nn <= A.leaf_cap;
+  int32_t* Nv = to_lds ? L.lv : W.vert + A.level_off[s + 1];
+  uint8_t* Nm = to_lds ? L.lm : W.mask + A.level_off[s + 1];
+  uint16_t* Na = to_lds ? L.la : W.arcs + A.level_off[s + 1];
+  const int64_t cap = to_lds ? A.leaf_cap : A.level_cap[s + 1];
+  dsync();
   // both parts are sorted by id: every entry's place is its rank in the other part
   for (int j = lane; j < ns; j += kWave) {
     if (j == px) continue;
@@ -328,6 +392,7 @@ __device__ void dextend(const DMotifArgs& A, const DLds& L, const DWave& W, int 
   }
   if (lane == 0) {
     L.esize[s + 1] = static_cast<int>(nsz);
+    if (s + 1 == A.k - 2) L.nnew[1] = to_lds ? 1 : 0;
     L.tr[s] = x;
     // v_s's pairs with tr[0..s-1] take bits s(s-1) .. s(s-1) + 2s - 1
     L.dcode[s + 1] = L.dcode[s] | static_cast<int>((Ea[px] & ((1u << (2 * s)) - 1u)) << (s * (s - 1)));
@@ -337,25 +402,29 @@ __device__ void dextend(const DMotifArgs& A, const DLds& L, const DWave& W, int 
     }
     L.sufmax[(s + 1) * kDSlots + s] = -1;
   }
-  wave_sync();
+  dsync();
 }
 
+// Move the workgroup's counters into the results.  Any wave may flush while
+// the others count: each counter is taken and cleared in one atomic step.
 __device__ void dflush(const DMotifArgs& A, const DLds& L) {
-  wave_sync();
+  dsync();
   for (int c = lane_id(); c < A.ncls; c += kWave) {
-    const unsigned v = L.cnt[c];
-    if (v) {
-      add_counter(A.out + c, v, A.flags);
-      L.cnt[c] = 0;
-    }
+    if (L.cnt[c]) add_counter(A.out + c, atomicExch(L.cnt + c, 0u), A.flags);
   }
-  wave_sync();
+  dsync();
+}
+
+// does level s live in LDS?  (only the level k-2 list, when it fits)
+__device__ __forceinline__ bool level_in_lds(const DMotifArgs& A, const DLds& L, int s) {
+  return s == A.k - 2 && L.nnew[1] != 0;
 }
 
 __device__ int next_dcanonical(const DMotifArgs& A, const DLds& L, const DWave& W, int s, int from, int to) {
   const int lane = lane_id();
-  const int32_t* Ev = W.vert + A.level_off[s];
-  const uint8_t* Em = W.mask + A.level_off[s];
+  const bool lds = level_in_lds(A, L, s);
+  const int32_t* Ev = lds ? L.lv : W.vert + A.level_off[s];
+  const uint8_t* Em = lds ? L.lm : W.mask + A.level_off[s];
   for (int c = from; c < to; c += kWave) {
     const int j = c + lane;
     const bool ok = j < to && dcanonical(L, s, Ev[j], Em[j]);
@@ -371,22 +440,32 @@ __device__ int next_dcanonical(const DMotifArgs& A, const DLds& L, const DWave& 
 // canonical (their only traversal neighbour is x, and they lie above the
 // root), and an old entry's mask and arc bits gain x's bit from the marks its
 // neighbour scan leaves.
+template <bool kLds>
 __device__ void dleaf(const DMotifArgs& A, const DLds& L, const DWave& W, int s, int px, int x, uint64_t& pending) {
   const int lane = lane_id();
-  const int32_t* Ev = W.vert + A.level_off[s];
-  const uint8_t* Em = W.mask + A.level_off[s];
-  const uint16_t* Ea = W.arcs + A.level_off[s];
+  // the level list and the marks: LDS-typed when the list is in LDS, so its
+  // reads are LDS instructions
+  const int32_t* Evg = W.vert + A.level_off[s];
+  const uint8_t* Emg = W.mask + A.level_off[s];
+  const uint16_t* Eag = W.arcs + A.level_off[s];
+  LdsI32d* Evl = (LdsI32d*)(L.lv);
+  LdsU8d* Eml = (LdsU8d*)(L.lm);
+  LdsU16d* Eal = (LdsU16d*)(L.la);
+  auto ev = [&](int j) -> int { return kLds ? Evl[j] : Evg[j]; };
+  auto em = [&](int j) -> unsigned { return kLds ? Eml[j] : Emg[j]; };
+  auto ea = [&](int j) -> unsigned { return kLds ? Eal[j] : Eag[j]; };
+  uint8_t* hit = kLds ? L.lhit : W.hit;
   const int ns = L.esize[s];
   if (lane == 0) {
     L.tr[s] = x;
-    L.dcode[s + 1] = L.dcode[s] | static_cast<int>((Ea[px] & ((1u << (2 * s)) - 1u)) << (s * (s - 1)));
+    L.dcode[s + 1] = L.dcode[s] | static_cast<int>((ea(px) & ((1u << (2 * s)) - 1u)) << (s * (s - 1)));
     for (int f = 0; f < s; ++f) {
       const int a = L.sufmax[s * kDSlots + f];
       L.sufmax[(s + 1) * kDSlots + f] = a > x ? a : x;
     }
     L.sufmax[(s + 1) * kDSlots + s] = -1;
   }
-  wave_sync();
+  dsync();
   const int base = L.dcode[s + 1];
   const int shift = (s + 1) * s;  // v_{s+1}'s pairs with tr[0..s]
   const int v0 = L.tr[0];
@@ -397,9 +476,13 @@ __device__ void dleaf(const DMotifArgs& A, const DLds& L, const DWave& W, int s,
     const bool ok = i < dx && A.col[xb + i] > v0;
     const int w = ok ? A.col[xb + i] : 0;
     const unsigned d = ok ? A.dir[xb + i] : 0u;
-    const int j = ok ? lower_bound_i32(Ev, ns, w) : ns;
-    const bool found = ok && j < ns && Ev[j] == w;
-    if (found && j != px) W.hit[j] = static_cast<uint8_t>(0x80u | d);
+    int lo = 0, hi = ok ? ns : 0;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (ev(mid) < w) lo = mid + 1; else hi = mid;
+    }
+    const bool found = ok && lo < ns && ev(lo) == w;
+    if (found && lo != px) hit[lo] = static_cast<uint8_t>(0x80u | d);
     bool intr = false;
     for (int t = 0; t < s; ++t) intr |= (L.tr[t] == w);
     const bool isnew = ok && !found && !intr;
@@ -410,28 +493,31 @@ __device__ void dleaf(const DMotifArgs& A, const DLds& L, const DWave& W, int s,
     }
     pending += static_cast<uint64_t>(__popcll(ballot(isnew)));
   }
-  wave_sync();
+  dsync();
   for (int c = 0; c < ns; c += kWave) {
     const int j = c + lane;
     const bool valid = j < ns && j != px;
-    const unsigned h = valid ? W.hit[j] : 0u;
-    const unsigned m = valid ? (Em[j] | ((h & 0x80u) ? (1u << s) : 0u)) : 0u;
-    const bool ok = valid && dcanonical(L, s + 1, Ev[j], m);
+    const unsigned h = valid ? hit[j] : 0u;
+    const unsigned m = valid ? (em(j) | ((h & 0x80u) ? (1u << s) : 0u)) : 0u;
+    const bool ok = valid && dcanonical(L, s + 1, ev(j), m);
     if (ok) {
-      const unsigned arcs = Ea[j] | ((h & 3u) << (2 * s));
+      const unsigned arcs = ea(j) | ((h & 3u) << (2 * s));
       const int cls = A.table[base | static_cast<int>(arcs << shift)];
       if (cls == kUnreachable) atomicOr(A.flags + 1, 2);
       else atomicAdd(L.cnt + cls, 1u);
     }
-    if (h) W.hit[j] = 0;
+    if (h) hit[j] = 0;
     pending += static_cast<uint64_t>(__popcll(ballot(ok)));
   }
-  wave_sync();
+  dsync();
 }
 
 // Every weakly connected induced k-subgraph rooted at v0 (its smallest id)
-// is counted once in its class.  `pending` counts increments since the last
-// flush of the 32-bit LDS counters.
+// is counted once in its class.  `pending` counts this wave's increments since
+// its last flush of the workgroup's 32-bit LDS counters.  A counter holds only
+// increments its waves made after their own last flush, and a wave flushes
+// once it passes 2^28; a leaf step adds at most dmax + (k-2) dmax, so with at
+// most kDMaxWaves waves and dmax < 2^26 no counter reaches 2^32.
 __device__ void dmotif_root(const DMotifArgs& A, const DLds& L, const DWave& W, int v0, uint64_t& pending) {
   const int lane = lane_id();
   const int k = A.k;
@@ -439,9 +525,11 @@ __device__ void dmotif_root(const DMotifArgs& A, const DLds& L, const DWave& W, 
   const int d0 = static_cast<int>(A.rp[v0 + 1] - b0);
   const int skip = uni(lower_bound_i32(A.col + b0, d0, v0 + 1));
   {
-    int32_t* E1 = W.vert + A.level_off[1];
-    uint8_t* M1 = W.mask + A.level_off[1];
-    uint16_t* A1 = W.arcs + A.level_off[1];
+    const bool lds1 = k == 3 && d0 - skip <= A.leaf_cap;  // level 1 is level k-2
+    int32_t* E1 = lds1 ? L.lv : W.vert + A.level_off[1];
+    uint8_t* M1 = lds1 ? L.lm : W.mask + A.level_off[1];
+    uint16_t* A1 = lds1 ? L.la : W.arcs + A.level_off[1];
+    if (lane == 0 && k == 3) L.nnew[1] = lds1 ? 1 : 0;
     for (int i = lane; i < d0 - skip; i += kWave) {
       E1[i] = A.col[b0 + skip + i];
       M1[i] = 1;
@@ -456,7 +544,7 @@ __device__ void dmotif_root(const DMotifArgs& A, const DLds& L, const DWave& W, 
       L.endv[1] = d0 - skip;
     }
   }
-  wave_sync();
+  dsync();
   int s = 1;
   for (;;) {
     const int idx = next_dcanonical(A, L, W, s, L.cursor[s], L.endv[s]);
@@ -465,11 +553,12 @@ __device__ void dmotif_root(const DMotifArgs& A, const DLds& L, const DWave& W, 
       --s;
       continue;
     }
-    const int x = W.vert[A.level_off[s] + idx];
+    const int x = level_in_lds(A, L, s) ? L.lv[idx] : W.vert[A.level_off[s] + idx];
     if (lane == 0) L.cursor[s] = idx + 1;
     if (s == k - 2) {
-      dleaf(A, L, W, s, idx, x, pending);
-      if (pending >= (1ull << 31)) {
+      if (level_in_lds(A, L, s)) dleaf<true>(A, L, W, s, idx, x, pending);
+      else dleaf<false>(A, L, W, s, idx, x, pending);
+      if (pending >= (1ull << 28)) {
         dflush(A, L);
         pending = 0;
       }
@@ -481,16 +570,18 @@ __device__ void dmotif_root(const DMotifArgs& A, const DLds& L, const DWave& W, 
       L.cursor[s] = 0;
       L.endv[s] = L.esize[s];
     }
-    wave_sync();
+    dsync();
   }
 }
 
-__global__ void __launch_bounds__(64) dmotif_kernel(DMotifArgs A) {
+__global__ void __launch_bounds__(64 * kDMaxWaves) dmotif_kernel(DMotifArgs A) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int lane = lane_id();
-  const int wave_gid = blockIdx.x;
-  DLds L = dcarve(smem);
-  for (int c = lane; c < A.ncls; c += kWave) L.cnt[c] = 0;
+  const int wid = static_cast<int>(threadIdx.x) / kWave;
+  const int nw = static_cast<int>(blockDim.x) / kWave;
+  const int wave_gid = static_cast<int>(blockIdx.x) * nw + wid;
+  DLds L = dcarve(smem, A.leaf_cap, wid, nw);
+  for (int c = static_cast<int>(threadIdx.x); c < A.ncls; c += static_cast<int>(blockDim.x)) L.cnt[c] = 0;
   DWave W;
   W.vert = A.vert + static_cast<size_t>(wave_gid) * A.wave_cap;
   W.mask = A.mask + static_cast<size_t>(wave_gid) * A.wave_cap;
@@ -499,29 +590,71 @@ __global__ void __launch_bounds__(64) dmotif_kernel(DMotifArgs A) {
   W.nbuf = A.nbuf + static_cast<size_t>(wave_gid) * A.dmax;
   W.ndir = A.ndir + static_cast<size_t>(wave_gid) * A.dmax;
   for (int64_t i = lane; i < A.hit_cap; i += kWave) W.hit[i] = 0;
-  wave_sync();
+  for (int i = lane; i < A.leaf_cap; i += kWave) L.lhit[i] = 0;
+  __syncthreads();  // the shared counters are zero before any wave counts (the only workgroup barrier)
   uint64_t pending = 0;
   SchedIter it;
   sched_begin(A.S, it);
   Task t;
   while (sched_next(A.S, it, wave_gid, L.tr, &t)) dmotif_root(A, L, W, t.root, pending);
   sched_end(A.S);
+  // every wave flushes on its way out; the last one to leave takes what the
+  // others counted after their own flush
   dflush(A, L);
 }
 
 }  // namespace
 
-size_t dmotif_lds_bytes(int ncls) {
-  const size_t ints = 3 * kDSlots + kDSlots * kDSlots + 3 * kDSlots + 4;
-  return ints * sizeof(int) + static_cast<size_t>(ncls) * sizeof(unsigned);
+size_t dmotif_lds_bytes(int ncls, int leaf_cap, int waves) {
+  return static_cast<size_t>(waves) * dwave_lds_bytes(leaf_cap) + static_cast<size_t>(ncls) * sizeof(unsigned);
 }
 
-hipError_t dmotif_occupancy(size_t lds_bytes, int* blocks_per_cu) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, dmotif_kernel, 64, lds_bytes);
+hipError_t dmotif_plan(int ncls, int max_waves_per_cu, DMotifPlan* best) {
+  // Every (waves per workgroup, workgroups per CU) shape, its LDS split between
+  // the shared counters and the waves' level lists.  Most resident waves wins
+  // (the kernel is bound by the latency of its dependent reads), among shapes
+  // whose level list holds at least kMinLeaf entries when any does; then the
+  // longest level list.
+  constexpr size_t kCuLds = 160 * 1024;
+  constexpr int kMinLeaf = 256;
+  DMotifPlan cand[64];
+  int nc = 0;
+  for (int nw = 1; nw <= kDMaxWaves; nw *= 2) {
+    for (int b = 1; b <= 32 && nc < 64; ++b) {
+      const long long per_wave = (static_cast<long long>(kCuLds / b) - 4ll * ncls) / nw -
+                                 static_cast<long long>(dwave_lds_bytes(0));
+      if (per_wave < 0) break;
+      int leaf = static_cast<int>(per_wave / (4 + 2 + 1 + 1));
+      if (leaf > 4096) leaf = 4096;
+      leaf &= ~63;
+      const size_t lds = dmotif_lds_bytes(ncls, leaf, nw);
+      int fit = 0;
+      hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&fit, dmotif_kernel, kWave * nw, lds);
+      if (e != hipSuccess) return e;
+      if (fit < 1) continue;
+      if (max_waves_per_cu > 0 && fit * nw > max_waves_per_cu) fit = max_waves_per_cu / nw;
+      if (fit < 1) continue;
+      cand[nc++] = DMotifPlan{nw, leaf, fit, lds};
+    }
+  }
+  bool any_long = false;
+  for (int i = 0; i < nc; ++i) any_long |= cand[i].leaf_cap >= kMinLeaf;
+  best->waves_per_group = 0;
+  for (int i = 0; i < nc; ++i) {
+    const DMotifPlan& c = cand[i];
+    if (any_long && c.leaf_cap < kMinLeaf) continue;
+    const int w = c.groups_per_cu * c.waves_per_group;
+    const int bw = best->groups_per_cu * best->waves_per_group;
+    if (best->waves_per_group == 0 || w > bw || (w == bw && c.leaf_cap > best->leaf_cap) ||
+        (w == bw && c.leaf_cap == best->leaf_cap && c.waves_per_group < best->waves_per_group))
+      *best = c;
+  }
+  return best->waves_per_group ? hipSuccess : hipErrorInvalidConfiguration;
 }
 
-hipError_t launch_dmotif(const DMotifArgs& a, int grid, size_t lds_bytes, hipStream_t s) {
-  hipLaunchKernelGGL(dmotif_kernel, dim3(grid), dim3(64), lds_bytes, s, a);
+hipError_t launch_dmotif(const DMotifArgs& a, int grid, int waves_per_group, size_t lds_bytes, hipStream_t s) {
+  if (waves_per_group < 1 || waves_per_group > kDMaxWaves) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(dmotif_kernel, dim3(grid), dim3(kWave * waves_per_group), lds_bytes, s, a);
   return hipGetLastError();
 }
 

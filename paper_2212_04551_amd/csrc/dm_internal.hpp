@@ -187,6 +187,7 @@ struct DMotifArgs {
   uint8_t* ndir;
   int64_t wave_cap;        // entries per wave in vert / mask / arcs
   int64_t hit_cap;         // entries per wave in hit
+  int leaf_cap;            // entries of the level k-2 list kept in LDS
   int64_t level_off[kDMotifMaxK + 1];
   int64_t level_cap[kDMotifMaxK + 1];
   Sched S;
@@ -197,9 +198,23 @@ hipError_t launch_arc_validate(const int64_t* rp, const int32_t* col, int32_t n,
 // ucol[unnz], udir[unnz], allocated here (hipMalloc) and owned by the caller
 hipError_t digraph_underlying(const int64_t* rp, const int32_t* col, int32_t n, int64_t arcs, int64_t** urp,
                               int32_t** ucol, uint8_t** udir, int64_t* unnz, hipStream_t s);
-size_t dmotif_lds_bytes(int ncls);
-hipError_t dmotif_occupancy(size_t lds_bytes, int* blocks_per_cu);
-hipError_t launch_dmotif(const DMotifArgs& a, int grid, size_t lds_bytes, hipStream_t s);
+// the arc bits in the rank-renamed graph: udir[urp[rank[u]] + j] for the
+// entry of rank[w] in row rank[u]; flag |= 1 for an entry the renamed graph
+// lacks
+hipError_t digraph_rank_dir(const int64_t* rp, const int32_t* col, const uint8_t* dir, int32_t n, const int32_t* rank,
+                            const int64_t* urp, const int32_t* ucol, uint8_t* udir, int* flag, hipStream_t s);
+// launch shape of the directed motif kernel: waves per workgroup (they share
+// one LDS copy of the class counters), workgroups per CU, the LDS level list
+// length and the dynamic LDS bytes
+struct DMotifPlan {
+  int waves_per_group;
+  int leaf_cap;
+  int groups_per_cu;
+  size_t lds;
+};
+size_t dmotif_lds_bytes(int ncls, int leaf_cap, int waves);
+hipError_t dmotif_plan(int ncls, int max_waves_per_cu, DMotifPlan* plan);
+hipError_t launch_dmotif(const DMotifArgs& a, int grid, int waves_per_group, size_t lds_bytes, hipStream_t s);
 // kernel launchers (return hipSuccess or the launch error)
 hipError_t launch_dfs_clique(const DfsArgs& a, int grid, hipStream_t s);
 hipError_t launch_dfs_motif(const DfsArgs& a, int grid, hipStream_t s);
