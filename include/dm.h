@@ -298,13 +298,15 @@ dm_status dm_motif_directed_class_table(int k, uint16_t* out, size_t len);
  * dm_count_motifs_directed: for k in 3..5, out_counts[c] (host, out_len >=
  * dm_motif_directed_num_classes(k)) = the number of vertex sets S, |S| = k,
  * whose induced subdigraph is weakly connected and in class c.  Enumeration
- * over the underlying undirected graph (every connected k-subset once, from
- * its smallest vertex id, by Section IV-E's canonical-candidate rule), one
- * wave per root, no donation; classification by the dictionary above.
- * Options: stream, chunk, waves_per_cu, wait_limit_us and DM_NO_DONATION
- * (no effect); anything else gives DM_E_ARG.  Errors: DM_E_ARG (null pointers,
- * a handle not made by dm_load_digraph), DM_E_K, DM_E_BUFSZ, DM_E_OVERFLOW,
- * DM_E_NOMEM / DM_E_HIP.
+ * over the underlying undirected graph renamed by (degree, id) rank (every
+ * connected k-subset once, from its lowest-rank vertex, by Section IV-E's
+ * canonical-candidate rule; the renaming is built at the first call and kept
+ * on the handle), one wave per root, no donation; classification by the
+ * dictionary above.  Options: stream, chunk, waves_per_cu (a cap on the
+ * resident waves per CU the launch is planned for), wait_limit_us and
+ * DM_NO_DONATION (no effect); anything else gives DM_E_ARG.  Errors: DM_E_ARG
+ * (null pointers, a handle not made by dm_load_digraph, a degree of 2^26 or
+ * more), DM_E_K, DM_E_BUFSZ, DM_E_OVERFLOW, DM_E_NOMEM / DM_E_HIP.
  */
 dm_status dm_count_motifs_directed(dm_graph* g, int k, uint64_t* out_counts, size_t out_len,
                                    const dm_options* opt);

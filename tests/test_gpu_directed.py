@@ -100,6 +100,38 @@ def test_directed_options_and_errors():
     assert not dm.count_motifs_directed(dm.load_digraph(gg.digraph_from_arcs(0, [])), 3).any()
 
 
+@pytest.mark.parametrize("k,leaves", [(4, 1500), (5, 700)])
+def test_directed_star_launch_shapes(k, leaves):
+    """A hub with out-, in- and two-way spokes: every weakly connected k-set
+    is the hub plus k-1 leaves, its class fixed by how many spokes of each
+    kind it holds (a closed form).  The leaf roots' level k-2 lists run from
+    about `leaves` entries down to none, so launches planned for different
+    resident-wave caps keep some of them in LDS and some in HBM."""
+    kinds = [j % 3 for j in range(leaves)]  # 0: hub -> leaf, 1: leaf -> hub, 2: both
+    arcs = []
+    for j, t in enumerate(kinds):
+        if t in (0, 2):
+            arcs.append((0, j + 1))
+        if t in (1, 2):
+            arcs.append((j + 1, 0))
+    h = dm.load_digraph(gg.digraph_from_arcs(leaves + 1, arcs))
+    nk = [kinds.count(t) for t in range(3)]
+    exp = np.zeros(dm.motif_directed_num_classes(k), dtype=np.uint64)
+    for a in range(k):
+        for b in range(k - a):
+            c = k - 1 - a - b
+            code = 0
+            for i in range(1, k):  # the hub at position 0, leaves 1..k-1
+                t = 0 if i <= a else (1 if i <= a + b else 2)
+                if t in (0, 2):
+                    code |= 1 << (2 * pbit(0, i))
+                if t in (1, 2):
+                    code |= 1 << (2 * pbit(0, i) + 1)
+            exp[O.dclass_of_code(k, code)] += math.comb(nk[0], a) * math.comb(nk[1], b) * math.comb(nk[2], c)
+    for cap in (0, 4, 1) if k == 4 else (0, 4):
+        assert np.array_equal(dm.count_motifs_directed(h, k, waves_per_cu=cap), exp), (k, cap)
+
+
 def test_directed_device_input_and_validation():
     import torch
     d = GRAPHS["ba400"]()

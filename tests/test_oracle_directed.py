@@ -146,6 +146,38 @@ def test_closed_forms(k):
     assert np.array_equal(c, exp)
 
 
+@pytest.mark.parametrize("k", [3, 4, 5])
+def test_mixed_star_closed_form(k):
+    """A hub with out-, in- and two-way spokes (every third leaf of each kind):
+    each weakly connected k-set is the hub plus k-1 leaves, in the class of the
+    star with that many spokes of each kind, so class counts are sums of
+    binomial products (the class read by networkx isomorphism, not the oracle)."""
+    leaves = 14
+    kinds = [j % 3 for j in range(leaves)]
+    arcs = [(0, j + 1) for j, t in enumerate(kinds) if t in (0, 2)]
+    arcs += [(j + 1, 0) for j, t in enumerate(kinds) if t in (1, 2)]
+    c = O.dmotif_count(gg.digraph_from_arcs(leaves + 1, arcs), k)
+    nk = [kinds.count(t) for t in range(3)]
+    canon = O.dclass_canon(k)
+    exp = np.zeros_like(c)
+    for a in range(k):
+        for b in range(k - a):
+            star = nx.DiGraph()
+            star.add_nodes_from(range(k))
+            for i in range(1, k):
+                t = 0 if i <= a else (1 if i <= a + b else 2)
+                if t in (0, 2):
+                    star.add_edge(0, i)
+                if t in (1, 2):
+                    star.add_edge(i, 0)
+            q = [c_ for c_ in range(len(canon))
+                 if nx.is_isomorphic(digraph_of_code(k, int(canon[c_])), star)]
+            assert len(q) == 1
+            exp[q[0]] += math.comb(nk[0], a) * math.comb(nk[1], b) * math.comb(nk[2], k - 1 - a - b)
+    assert np.array_equal(c, exp)
+    assert int(c.sum()) == math.comb(leaves, k - 1)
+
+
 def gg_edges(d):
     return [(v, int(u)) for v in range(d.n) for u in d.col[d.row_ptr[v]:d.row_ptr[v + 1]]]
 
