@@ -254,7 +254,8 @@ struct DLds {
   int* cursor;    // [kDSlots]
   int* endv;      // [kDSlots]
   int* esize;     // [kDSlots]
-  int* nnew;      // [4] [1]: the level k-2 list is in lv / lm / la
+  int* nnew;      // [4] [1]: the level k-2 list is in lv / lm / la; [2], [3]: its bucket base and shift
+  int* bk;        // [kDBuckets + 1] bucket b = entries in [base + (b << shift), base + ((b + 1) << shift))
   int32_t* lv;    // [leaf_cap] level k-2 list in LDS (when it fits): vertex
   uint16_t* la;   // [leaf_cap] arc bits
   uint8_t* lm;    // [leaf_cap] undirected mask
@@ -262,7 +263,8 @@ struct DLds {
   unsigned* cnt;  // [ncls] class counters since the last flush
 };
 
-constexpr int kDLdsInts = 3 * kDSlots + kDSlots * kDSlots + 3 * kDSlots + 4;
+constexpr int kDBuckets = 64;
+constexpr int kDLdsInts = 3 * kDSlots + kDSlots * kDSlots + 3 * kDSlots + 4 + kDBuckets + 1;
 
 // per-wave bytes: the traversal state and the LDS level list
 __host__ __device__ constexpr size_t dwave_lds_bytes(int leaf_cap) {
@@ -281,7 +283,8 @@ __device__ DLds dcarve(unsigned char* smem, int leaf_cap, int wid, int nw) {
   L.endv = L.cursor + kDSlots;
   L.esize = L.endv + kDSlots;
   L.nnew = L.esize + kDSlots;
-  L.lv = L.nnew + 4;
+  L.bk = L.nnew + 4;
+  L.lv = L.bk + kDBuckets + 1;
   L.la = reinterpret_cast<uint16_t*>(L.lv + leaf_cap);
   L.lm = reinterpret_cast<uint8_t*>(L.la + leaf_cap);
   L.lhit = L.lm + leaf_cap;
@@ -316,6 +319,34 @@ struct DWave {
   int32_t* nbuf;   // new entries of an extension
   uint8_t* ndir;
 };
+
+// Bucket index over the LDS level list (sorted ids, ns entries): the ids
+// from its first to its last split into kDBuckets ranges of 2^shift, bk[b]
+// the first entry of range b, so a search starts in about ns / kDBuckets
+// entries instead of ns.
+__device__ void dbuckets(const DLds& L, int ns) {
+  const int lane = lane_id();
+  dsync();
+  const LdsI32d* lv = (const LdsI32d*)(L.lv);
+  const int lo = ns > 0 ? lv[0] : 0;
+  const int span = ns > 0 ? lv[ns - 1] - lo : 0;
+  int sh = 0;
+  while ((span >> sh) >= kDBuckets) ++sh;
+  for (int b = lane; b <= kDBuckets; b += kWave) {
+    const int64_t key = static_cast<int64_t>(lo) + (static_cast<int64_t>(b) << sh);
+    int a = 0, e = ns;
+    while (a < e) {
+      const int mid = (a + e) >> 1;
+      if (lv[mid] < key) a = mid + 1; else e = mid;
+    }
+    L.bk[b] = a;
+  }
+  if (lane == 0) {
+    L.nnew[2] = lo;
+    L.nnew[3] = sh;
+  }
+  dsync();
+}
 
 // Level s+1 from level s by appending the entry at index px (vertex x).
 __device__ void dextend(const DMotifArgs& A, const DLds& L, const DWave& W, int s, int px, int x) {
@@ -403,6 +434,7 @@ __device__ void dextend(const DMotifArgs& A, const DLds& L, const DWave& W, int 
     L.sufmax[(s + 1) * kDSlots + s] = -1;
   }
   dsync();
+  if (to_lds) dbuckets(L, static_cast<int>(nsz));
 }
 
 // Move the workgroup's counters into the results.  Any wave may flush while
@@ -477,12 +509,20 @@ __device__ void dleaf(const DMotifArgs& A, const DLds& L, const DWave& W, int s,
     const int w = ok ? A.col[xb + i] : 0;
     const unsigned d = ok ? A.dir[xb + i] : 0u;
     int lo = 0, hi = ok ? ns : 0;
+    if (kLds && ok) {
+      const int rel = w - L.nnew[2];
+      const int b = rel < 0 ? kDBuckets : rel >> L.nnew[3];
+      lo = b < kDBuckets ? L.bk[b] : 0;
+      hi = b < kDBuckets ? L.bk[b + 1] : 0;
+    }
+    const int end = hi;
     while (lo < hi) {
       const int mid = (lo + hi) >> 1;
       if (ev(mid) < w) lo = mid + 1; else hi = mid;
     }
-    const bool found = ok && lo < ns && ev(lo) == w;
-    if (found && lo != px) hit[lo] = static_cast<uint8_t>(0x80u | d);
+    const bool found = ok && lo < end && ev(lo) == w;
+    // only entries above x can be canonical (below)
+    if (found && lo > px) hit[lo] = static_cast<uint8_t>(0x80u | d);
     bool intr = false;
     for (int t = 0; t < s; ++t) intr |= (L.tr[t] == w);
     const bool isnew = ok && !found && !intr;
@@ -494,9 +534,12 @@ __device__ void dleaf(const DMotifArgs& A, const DLds& L, const DWave& W, int s,
     pending += static_cast<uint64_t>(__popcll(ballot(isnew)));
   }
   dsync();
-  for (int c = 0; c < ns; c += kWave) {
+  // An old entry y's first traversal neighbour comes before x, so it is
+  // canonical only above x (and every later traversal vertex); the list is
+  // sorted, so only the entries after x's are looked at.
+  for (int c = px + 1; c < ns; c += kWave) {
     const int j = c + lane;
-    const bool valid = j < ns && j != px;
+    const bool valid = j < ns;
     const unsigned h = valid ? hit[j] : 0u;
     const unsigned m = valid ? (em(j) | ((h & 0x80u) ? (1u << s) : 0u)) : 0u;
     const bool ok = valid && dcanonical(L, s + 1, ev(j), m);
@@ -543,6 +586,7 @@ __device__ void dmotif_root(const DMotifArgs& A, const DLds& L, const DWave& W, 
       L.cursor[1] = 0;
       L.endv[1] = d0 - skip;
     }
+    if (lds1) dbuckets(L, d0 - skip);
   }
   dsync();
   int s = 1;
