@@ -232,6 +232,7 @@ namespace {
 
 constexpr int kDSlots = kDMotifMaxK + 1;
 constexpr int kDMaxWaves = 8;  // waves per workgroup
+static_assert(kDMaxWaves == 8, "the launch planner tries 1, 2, 4 and 8 waves per workgroup");
 // the level k-2 list (the one every x step at the last levels searches) is
 // built in LDS when it has at most this many entries
 typedef __attribute__((address_space(3))) int32_t LdsI32d;
@@ -663,10 +664,11 @@ hipError_t dmotif_plan(int ncls, int max_waves_per_cu, DMotifPlan* best) {
   // longest level list.
   constexpr size_t kCuLds = 160 * 1024;
   constexpr int kMinLeaf = 256;
-  DMotifPlan cand[64];
+  constexpr int kMaxGroups = 32;  // workgroups per CU tried
+  DMotifPlan cand[4 * kMaxGroups];  // nw = 1, 2, 4, 8
   int nc = 0;
   for (int nw = 1; nw <= kDMaxWaves; nw *= 2) {
-    for (int b = 1; b <= 32 && nc < 64; ++b) {
+    for (int b = 1; b <= kMaxGroups; ++b) {
       const long long per_wave = (static_cast<long long>(kCuLds / b) - 4ll * ncls) / nw -
                                  static_cast<long long>(dwave_lds_bytes(0));
       if (per_wave < 0) break;
