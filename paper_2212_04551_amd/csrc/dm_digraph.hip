@@ -489,19 +489,21 @@ __device__ void dleaf(const DMotifArgs& A, const DLds& L, const DWave& W, int s,
   auto ea = [&](int j) -> unsigned { return kLds ? Eal[j] : Eag[j]; };
   uint8_t* hit = kLds ? L.lhit : W.hit;
   const int ns = L.esize[s];
-  if (lane == 0) {
-    L.tr[s] = x;
-    L.dcode[s + 1] = L.dcode[s] | static_cast<int>((ea(px) & ((1u << (2 * s)) - 1u)) << (s * (s - 1)));
-    for (int f = 0; f < s; ++f) {
-      const int a = L.sufmax[s * kDSlots + f];
-      L.sufmax[(s + 1) * kDSlots + f] = a > x ? a : x;
-    }
-    L.sufmax[(s + 1) * kDSlots + s] = -1;
-  }
-  dsync();
-  const int base = L.dcode[s + 1];
-  const int shift = (s + 1) * s;  // v_{s+1}'s pairs with tr[0..s]
-  const int v0 = L.tr[0];
+  // The traversal v_0..v_{s-1} plus x, held in registers: the code of v_0..x
+  // (v_{s+1}'s pairs with them take the bits from `shift` up), the members a
+  // neighbour of x must not be (v_0 is below every neighbour kept), and the
+  // canonical test's thresholds (an entry whose first traversal neighbour is
+  // v_f must lie above every later traversal vertex; x is below every entry
+  // looked at).
+  static_assert(kDMotifMaxK - 2 <= 3, "the leaf holds at most three traversal vertices before x");
+  const int base = uni(L.dcode[s]) | static_cast<int>((ea(px) & ((1u << (2 * s)) - 1u)) << (s * (s - 1)));
+  const int shift = (s + 1) * s;
+  const int v0 = uni(L.tr[0]);
+  const int t1 = s > 1 ? uni(L.tr[1]) : -1;
+  const int t2 = s > 2 ? uni(L.tr[2]) : -1;
+  const int th0 = uni(L.sufmax[s * kDSlots + 0]);
+  const int th1 = s > 1 ? uni(L.sufmax[s * kDSlots + 1]) : 0;
+  const int th2 = s > 2 ? uni(L.sufmax[s * kDSlots + 2]) : 0;
   const int64_t xb = A.rp[x];
   const int dx = static_cast<int>(A.rp[x + 1] - xb);
   for (int c = 0; c < dx; c += kWave) {
@@ -524,8 +526,7 @@ __device__ void dleaf(const DMotifArgs& A, const DLds& L, const DWave& W, int s,
     const bool found = ok && lo < end && ev(lo) == w;
     // only entries above x can be canonical (below)
     if (found && lo > px) hit[lo] = static_cast<uint8_t>(0x80u | d);
-    bool intr = false;
-    for (int t = 0; t < s; ++t) intr |= (L.tr[t] == w);
+    const bool intr = w == t1 || w == t2;
     const bool isnew = ok && !found && !intr;
     if (isnew) {
       const int cls = A.table[base | static_cast<int>(((d & 3u) << (2 * s)) << shift)];
@@ -542,8 +543,10 @@ __device__ void dleaf(const DMotifArgs& A, const DLds& L, const DWave& W, int s,
     const int j = c + lane;
     const bool valid = j < ns;
     const unsigned h = valid ? hit[j] : 0u;
-    const unsigned m = valid ? (em(j) | ((h & 0x80u) ? (1u << s) : 0u)) : 0u;
-    const bool ok = valid && dcanonical(L, s + 1, ev(j), m);
+    const unsigned e = valid ? em(j) : 0u;  // over v_0..v_{s-1}: never 0 for an entry
+    const int f = __builtin_ctz(e | 0x80000000u);
+    const int th = f == 0 ? th0 : (f == 1 ? th1 : th2);
+    const bool ok = valid && e != 0u && ev(j) > th;
     if (ok) {
       const unsigned arcs = ea(j) | ((h & 3u) << (2 * s));
       const int cls = A.table[base | static_cast<int>(arcs << shift)];
