@@ -235,9 +235,17 @@ constexpr int kDMaxWaves = 8;  // waves per workgroup
 static_assert(kDMaxWaves == 8, "the launch planner tries 1, 2, 4 and 8 waves per workgroup");
 // the level k-2 list (the one every x step at the last levels searches) is
 // built in LDS when it has at most this many entries
-typedef __attribute__((address_space(3))) int32_t LdsI32d;
-typedef __attribute__((address_space(3))) uint16_t LdsU16d;
-typedef __attribute__((address_space(3))) uint8_t LdsU8d;
+typedef __attribute__((address_space(3))) uint64_t LdsU64d;
+
+// An entry of the LDS level list in one word: vertex (bits 0-31), arc bits
+// (32-47), undirected mask (48-55), so one read brings all three.
+__device__ __forceinline__ uint64_t dpack(int v, unsigned arcs, unsigned mask) {
+  return static_cast<uint32_t>(v) | (static_cast<uint64_t>(arcs & 0xffffu) << 32) |
+         (static_cast<uint64_t>(mask & 0xffu) << 48);
+}
+__device__ __forceinline__ int dp_v(uint64_t w) { return static_cast<int>(static_cast<uint32_t>(w)); }
+__device__ __forceinline__ unsigned dp_a(uint64_t w) { return static_cast<unsigned>(w >> 32) & 0xffffu; }
+__device__ __forceinline__ unsigned dp_m(uint64_t w) { return static_cast<unsigned>(w >> 48) & 0xffu; }
 
 // The workgroup's waves run independent traversals (they share only the class
 // counters), so lanes of one wave order their LDS and memory traffic with a
@@ -255,21 +263,20 @@ struct DLds {
   int* cursor;    // [kDSlots]
   int* endv;      // [kDSlots]
   int* esize;     // [kDSlots]
-  int* nnew;      // [4] [1]: the level k-2 list is in lv / lm / la; [2], [3]: its bucket base and shift
+  int* nnew;      // [4] [1]: the level k-2 list is in lp; [2], [3]: its bucket base and shift
   int* bk;        // [kDBuckets + 1] bucket b = entries in [base + (b << shift), base + ((b + 1) << shift))
-  int32_t* lv;    // [leaf_cap] level k-2 list in LDS (when it fits): vertex
-  uint16_t* la;   // [leaf_cap] arc bits
-  uint8_t* lm;    // [leaf_cap] undirected mask
+  uint64_t* lp;   // [leaf_cap] level k-2 list in LDS (when it fits), packed entries
   uint8_t* lhit;  // [leaf_cap] marks of the entries an x step touches
   unsigned* cnt;  // [ncls] class counters since the last flush
 };
 
 constexpr int kDBuckets = 64;
-constexpr int kDLdsInts = 3 * kDSlots + kDSlots * kDSlots + 3 * kDSlots + 4 + kDBuckets + 1;
+// (an even count, so the packed list after them is 8-byte aligned)
+constexpr int kDLdsInts = (3 * kDSlots + kDSlots * kDSlots + 3 * kDSlots + 4 + kDBuckets + 1 + 1) & ~1;
 
 // per-wave bytes: the traversal state and the LDS level list
 __host__ __device__ constexpr size_t dwave_lds_bytes(int leaf_cap) {
-  return kDLdsInts * sizeof(int) + static_cast<size_t>(leaf_cap) * (4 + 2 + 1 + 1);
+  return kDLdsInts * sizeof(int) + static_cast<size_t>(leaf_cap) * (8 + 1);
 }
 
 // Wave wid's part of the workgroup's LDS; the class counters after the
@@ -285,10 +292,8 @@ __device__ DLds dcarve(unsigned char* smem, int leaf_cap, int wid, int nw) {
   L.esize = L.endv + kDSlots;
   L.nnew = L.esize + kDSlots;
   L.bk = L.nnew + 4;
-  L.lv = L.bk + kDBuckets + 1;
-  L.la = reinterpret_cast<uint16_t*>(L.lv + leaf_cap);
-  L.lm = reinterpret_cast<uint8_t*>(L.la + leaf_cap);
-  L.lhit = L.lm + leaf_cap;
+  L.lp = reinterpret_cast<uint64_t*>(p + kDLdsInts);
+  L.lhit = reinterpret_cast<uint8_t*>(L.lp + leaf_cap);
   L.cnt = reinterpret_cast<unsigned*>(smem + nw * dwave_lds_bytes(leaf_cap));
   return L;
 }
@@ -328,9 +333,9 @@ struct DWave {
 __device__ void dbuckets(const DLds& L, int ns) {
   const int lane = lane_id();
   dsync();
-  const LdsI32d* lv = (const LdsI32d*)(L.lv);
-  const int lo = ns > 0 ? lv[0] : 0;
-  const int span = ns > 0 ? lv[ns - 1] - lo : 0;
+  const LdsU64d* lp = (const LdsU64d*)(L.lp);
+  const int lo = ns > 0 ? dp_v(lp[0]) : 0;
+  const int span = ns > 0 ? dp_v(lp[ns - 1]) - lo : 0;
   int sh = 0;
   while ((span >> sh) >= kDBuckets) ++sh;
   for (int b = lane; b <= kDBuckets; b += kWave) {
@@ -338,7 +343,7 @@ __device__ void dbuckets(const DLds& L, int ns) {
     int a = 0, e = ns;
     while (a < e) {
       const int mid = (a + e) >> 1;
-      if (lv[mid] < key) a = mid + 1; else e = mid;
+      if (dp_v(lp[mid]) < key) a = mid + 1; else e = mid;
     }
     L.bk[b] = a;
   }
@@ -387,9 +392,10 @@ __device__ void dextend(const DMotifArgs& A, const DLds& L, const DWave& W, int 
     nn = A.dmax;
   }
   const bool to_lds = s + 1 == A.k - 2 && static_cast<int64_t>(ns) - 1 + nn <= A.leaf_cap;
-  int32_t* Nv = to_lds ? L.lv : W.vert + A.level_off[s + 1];
-  uint8_t* Nm = to_lds ? L.lm : W.mask + A.level_off[s + 1];
-  uint16_t* Na = to_lds ? L.la : W.arcs + A.level_off[s + 1];
+  int32_t* Nv = W.vert + A.level_off[s + 1];
+  uint8_t* Nm = W.mask + A.level_off[s + 1];
+  uint16_t* Na = W.arcs + A.level_off[s + 1];
+  LdsU64d* Np = (LdsU64d*)(L.lp);
   const int64_t cap = to_lds ? A.leaf_cap : A.level_cap[s + 1];
   dsync();
   // both parts are sorted by id: every entry's place is its rank in the other part
@@ -400,9 +406,15 @@ __device__ void dextend(const DMotifArgs& A, const DLds& L, const DWave& W, int 
     const int r = lower_bound_i32(W.nbuf, nn, y);
     const int64_t out = static_cast<int64_t>(j) - (j > px ? 1 : 0) + r;
     if (out < cap) {
-      Nv[out] = y;
-      Nm[out] = static_cast<uint8_t>(Em[j] | ((h & 0x80u) ? (1u << s) : 0u));
-      Na[out] = static_cast<uint16_t>(Ea[j] | ((h & 3u) << (2 * s)));
+      const unsigned m = Em[j] | ((h & 0x80u) ? (1u << s) : 0u);
+      const unsigned a = Ea[j] | ((h & 3u) << (2 * s));
+      if (to_lds) {
+        Np[out] = dpack(y, a, m);
+      } else {
+        Nv[out] = y;
+        Nm[out] = static_cast<uint8_t>(m);
+        Na[out] = static_cast<uint16_t>(a);
+      }
     }
     if (h) W.hit[j] = 0;
   }
@@ -412,9 +424,14 @@ __device__ void dextend(const DMotifArgs& A, const DLds& L, const DWave& W, int 
     if (px < r) r -= 1;
     const int64_t out = static_cast<int64_t>(i) + r;
     if (out < cap) {
-      Nv[out] = w;
-      Nm[out] = static_cast<uint8_t>(1u << s);
-      Na[out] = static_cast<uint16_t>((W.ndir[i] & 3u) << (2 * s));
+      const unsigned a = (W.ndir[i] & 3u) << (2 * s);
+      if (to_lds) {
+        Np[out] = dpack(w, a, 1u << s);
+      } else {
+        Nv[out] = w;
+        Nm[out] = static_cast<uint8_t>(1u << s);
+        Na[out] = static_cast<uint16_t>(a);
+      }
     }
   }
   int64_t nsz = static_cast<int64_t>(ns) - 1 + nn;
@@ -456,11 +473,13 @@ __device__ __forceinline__ bool level_in_lds(const DMotifArgs& A, const DLds& L,
 __device__ int next_dcanonical(const DMotifArgs& A, const DLds& L, const DWave& W, int s, int from, int to) {
   const int lane = lane_id();
   const bool lds = level_in_lds(A, L, s);
-  const int32_t* Ev = lds ? L.lv : W.vert + A.level_off[s];
-  const uint8_t* Em = lds ? L.lm : W.mask + A.level_off[s];
+  const int32_t* Ev = W.vert + A.level_off[s];
+  const uint8_t* Em = W.mask + A.level_off[s];
   for (int c = from; c < to; c += kWave) {
     const int j = c + lane;
-    const bool ok = j < to && dcanonical(L, s, Ev[j], Em[j]);
+    uint64_t e = 0;
+    if (j < to) e = lds ? L.lp[j] : dpack(Ev[j], 0u, Em[j]);
+    const bool ok = j < to && dcanonical(L, s, dp_v(e), dp_m(e));
     const uint64_t b = ballot(ok);
     if (b) return uni(c + __ffsll(static_cast<long long>(b)) - 1);
   }
@@ -481,12 +500,11 @@ __device__ void dleaf(const DMotifArgs& A, const DLds& L, const DWave& W, int s,
   const int32_t* Evg = W.vert + A.level_off[s];
   const uint8_t* Emg = W.mask + A.level_off[s];
   const uint16_t* Eag = W.arcs + A.level_off[s];
-  LdsI32d* Evl = (LdsI32d*)(L.lv);
-  LdsU8d* Eml = (LdsU8d*)(L.lm);
-  LdsU16d* Eal = (LdsU16d*)(L.la);
-  auto ev = [&](int j) -> int { return kLds ? Evl[j] : Evg[j]; };
-  auto em = [&](int j) -> unsigned { return kLds ? Eml[j] : Emg[j]; };
-  auto ea = [&](int j) -> unsigned { return kLds ? Eal[j] : Eag[j]; };
+  LdsU64d* Epl = (LdsU64d*)(L.lp);
+  auto ev = [&](int j) -> int { return kLds ? dp_v(Epl[j]) : Evg[j]; };
+  auto ea = [&](int j) -> unsigned { return kLds ? dp_a(Epl[j]) : Eag[j]; };
+  // the whole entry: one LDS read, or three global ones
+  auto eall = [&](int j) -> uint64_t { return kLds ? Epl[j] : dpack(Evg[j], Eag[j], Emg[j]); };
   uint8_t* hit = kLds ? L.lhit : W.hit;
   const int ns = L.esize[s];
   // The traversal v_0..v_{s-1} plus x, held in registers: the code of v_0..x
@@ -543,12 +561,13 @@ __device__ void dleaf(const DMotifArgs& A, const DLds& L, const DWave& W, int s,
     const int j = c + lane;
     const bool valid = j < ns;
     const unsigned h = valid ? hit[j] : 0u;
-    const unsigned e = valid ? em(j) : 0u;  // over v_0..v_{s-1}: never 0 for an entry
+    const uint64_t wj = valid ? eall(j) : 0ull;
+    const unsigned e = dp_m(wj);  // over v_0..v_{s-1}: never 0 for an entry
     const int f = __builtin_ctz(e | 0x80000000u);
     const int th = f == 0 ? th0 : (f == 1 ? th1 : th2);
-    const bool ok = valid && e != 0u && ev(j) > th;
+    const bool ok = valid && e != 0u && dp_v(wj) > th;
     if (ok) {
-      const unsigned arcs = ea(j) | ((h & 3u) << (2 * s));
+      const unsigned arcs = dp_a(wj) | ((h & 3u) << (2 * s));
       const int cls = A.table[base | static_cast<int>(arcs << shift)];
       if (cls == kUnreachable) atomicOr(A.flags + 1, 2);
       else atomicAdd(L.cnt + cls, 1u);
@@ -573,14 +592,20 @@ __device__ void dmotif_root(const DMotifArgs& A, const DLds& L, const DWave& W, 
   const int skip = uni(lower_bound_i32(A.col + b0, d0, v0 + 1));
   {
     const bool lds1 = k == 3 && d0 - skip <= A.leaf_cap;  // level 1 is level k-2
-    int32_t* E1 = lds1 ? L.lv : W.vert + A.level_off[1];
-    uint8_t* M1 = lds1 ? L.lm : W.mask + A.level_off[1];
-    uint16_t* A1 = lds1 ? L.la : W.arcs + A.level_off[1];
+    int32_t* E1 = W.vert + A.level_off[1];
+    uint8_t* M1 = W.mask + A.level_off[1];
+    uint16_t* A1 = W.arcs + A.level_off[1];
     if (lane == 0 && k == 3) L.nnew[1] = lds1 ? 1 : 0;
     for (int i = lane; i < d0 - skip; i += kWave) {
-      E1[i] = A.col[b0 + skip + i];
-      M1[i] = 1;
-      A1[i] = static_cast<uint16_t>(A.dir[b0 + skip + i] & 3u);
+      const int w = A.col[b0 + skip + i];
+      const unsigned a = A.dir[b0 + skip + i] & 3u;
+      if (lds1) {
+        L.lp[i] = dpack(w, a, 1u);
+      } else {
+        E1[i] = w;
+        M1[i] = 1;
+        A1[i] = static_cast<uint16_t>(a);
+      }
     }
     if (lane == 0) {
       L.esize[1] = d0 - skip;
@@ -601,7 +626,7 @@ __device__ void dmotif_root(const DMotifArgs& A, const DLds& L, const DWave& W, 
       --s;
       continue;
     }
-    const int x = level_in_lds(A, L, s) ? L.lv[idx] : W.vert[A.level_off[s] + idx];
+    const int x = level_in_lds(A, L, s) ? dp_v(L.lp[idx]) : W.vert[A.level_off[s] + idx];
     if (lane == 0) L.cursor[s] = idx + 1;
     if (s == k - 2) {
       if (level_in_lds(A, L, s)) dleaf<true>(A, L, W, s, idx, x, pending);
@@ -675,7 +700,7 @@ hipError_t dmotif_plan(int ncls, int max_waves_per_cu, DMotifPlan* best) {
       const long long per_wave = (static_cast<long long>(kCuLds / b) - 4ll * ncls) / nw -
                                  static_cast<long long>(dwave_lds_bytes(0));
       if (per_wave < 0) break;
-      int leaf = static_cast<int>(per_wave / (4 + 2 + 1 + 1));
+      int leaf = static_cast<int>(per_wave / (8 + 1));
       if (leaf > 4096) leaf = 4096;
       leaf &= ~63;
       const size_t lds = dmotif_lds_bytes(ncls, leaf, nw);
