@@ -249,11 +249,14 @@ __device__ __forceinline__ unsigned dp_m(uint64_t w) { return static_cast<unsign
 
 // The workgroup's waves run independent traversals (they share only the class
 // counters), so lanes of one wave order their LDS and memory traffic with a
-// wave-scope fence pair, never with a workgroup barrier.
+// fence pair and no workgroup barrier.  The fences take workgroup scope: a
+// lane's stores (LDS and the level lists in HBM) complete before another
+// lane of the wave reads them, whatever the memory system does with one
+// wave's accesses in flight.
 __device__ __forceinline__ void dsync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
 struct DLds {
