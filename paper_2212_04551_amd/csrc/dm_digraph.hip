@@ -8,10 +8,11 @@
 //     by a radix sort of (head, tail) keys, and every vertex's out- and
 //     in-list merged into its undirected list; entry (u, w) carries
 //     dir = [u->w] | [w->u] << 1.
-//   - Directed motif counting (k = 3..5): one wave per root extends the
-//     traversal with the canonical-candidate rule of Section IV-E over the
-//     undirected lists, keeping for every list entry its undirected adjacency
-//     mask over the traversal and two arc bits per traversal vertex.  The
+//   - Directed motif counting (k = 3..5): on the graph renamed by (degree,
+//     id) rank, one wave per root extends the traversal with the
+//     canonical-candidate rule of Section IV-E over the undirected lists,
+//     keeping for every list entry its undirected adjacency mask over the
+//     traversal and two arc bits per traversal vertex.  The
 //     directed pattern code of Section IV-C's bitmap takes two bits per vertex
 //     pair.  Once |tr| = k-2, each canonical x and every canonical y of the
 //     extension set that x's step would build complete one subgraph, counted
@@ -233,8 +234,8 @@ namespace {
 constexpr int kDSlots = kDMotifMaxK + 1;
 constexpr int kDMaxWaves = 8;  // waves per workgroup
 static_assert(kDMaxWaves == 8, "the launch planner tries 1, 2, 4 and 8 waves per workgroup");
-// the level k-2 list (the one every x step at the last levels searches) is
-// built in LDS when it has at most this many entries
+// LDS-typed view of a pointer into the workgroup's LDS (its reads and
+// writes are then LDS instructions, not generic ones)
 typedef __attribute__((address_space(3))) uint64_t LdsU64d;
 
 // An entry of the LDS level list in one word: vertex (bits 0-31), arc bits
@@ -266,9 +267,9 @@ struct DLds {
   int* cursor;    // [kDSlots]
   int* endv;      // [kDSlots]
   int* esize;     // [kDSlots]
-  int* nnew;      // [4] [1]: the level k-2 list is in lp; [2], [3]: its bucket base and shift
+  int* meta;      // [4] [1]: the level k-2 list is in lp; [2], [3]: its bucket base and shift
   int* bk;        // [kDBuckets + 1] bucket b = entries in [base + (b << shift), base + ((b + 1) << shift))
-  uint64_t* lp;   // [leaf_cap] level k-2 list in LDS (when it fits), packed entries
+  uint64_t* lp;   // [leaf_cap] level k-2 list in LDS when it has at most leaf_cap entries, packed
   uint8_t* lhit;  // [leaf_cap] marks of the entries an x step touches
   unsigned* cnt;  // [ncls] class counters since the last flush
 };
@@ -293,8 +294,8 @@ __device__ DLds dcarve(unsigned char* smem, int leaf_cap, int wid, int nw) {
   L.cursor = L.sufmax + kDSlots * kDSlots;
   L.endv = L.cursor + kDSlots;
   L.esize = L.endv + kDSlots;
-  L.nnew = L.esize + kDSlots;
-  L.bk = L.nnew + 4;
+  L.meta = L.esize + kDSlots;
+  L.bk = L.meta + 4;
   L.lp = reinterpret_cast<uint64_t*>(p + kDLdsInts);
   L.lhit = reinterpret_cast<uint8_t*>(L.lp + leaf_cap);
   L.cnt = reinterpret_cast<unsigned*>(smem + nw * dwave_lds_bytes(leaf_cap));
@@ -351,8 +352,8 @@ __device__ void dbuckets(const DLds& L, int ns) {
     L.bk[b] = a;
   }
   if (lane == 0) {
-    L.nnew[2] = lo;
-    L.nnew[3] = sh;
+    L.meta[2] = lo;
+    L.meta[3] = sh;
   }
   dsync();
 }
@@ -444,7 +445,7 @@ __device__ void dextend(const DMotifArgs& A, const DLds& L, const DWave& W, int 
   }
   if (lane == 0) {
     L.esize[s + 1] = static_cast<int>(nsz);
-    if (s + 1 == A.k - 2) L.nnew[1] = to_lds ? 1 : 0;
+    if (s + 1 == A.k - 2) L.meta[1] = to_lds ? 1 : 0;
     L.tr[s] = x;
     // v_s's pairs with tr[0..s-1] take bits s(s-1) .. s(s-1) + 2s - 1
     L.dcode[s + 1] = L.dcode[s] | static_cast<int>((Ea[px] & ((1u << (2 * s)) - 1u)) << (s * (s - 1)));
@@ -470,7 +471,7 @@ __device__ void dflush(const DMotifArgs& A, const DLds& L) {
 
 // does level s live in LDS?  (only the level k-2 list, when it fits)
 __device__ __forceinline__ bool level_in_lds(const DMotifArgs& A, const DLds& L, int s) {
-  return s == A.k - 2 && L.nnew[1] != 0;
+  return s == A.k - 2 && L.meta[1] != 0;
 }
 
 __device__ int next_dcanonical(const DMotifArgs& A, const DLds& L, const DWave& W, int s, int from, int to) {
@@ -534,8 +535,8 @@ __device__ void dleaf(const DMotifArgs& A, const DLds& L, const DWave& W, int s,
     const unsigned d = ok ? A.dir[xb + i] : 0u;
     int lo = 0, hi = ok ? ns : 0;
     if (kLds && ok) {
-      const int rel = w - L.nnew[2];
-      const int b = rel < 0 ? kDBuckets : rel >> L.nnew[3];
+      const int rel = w - L.meta[2];
+      const int b = rel < 0 ? kDBuckets : rel >> L.meta[3];
       lo = b < kDBuckets ? L.bk[b] : 0;
       hi = b < kDBuckets ? L.bk[b + 1] : 0;
     }
@@ -581,7 +582,7 @@ __device__ void dleaf(const DMotifArgs& A, const DLds& L, const DWave& W, int s,
   dsync();
 }
 
-// Every weakly connected induced k-subgraph rooted at v0 (its smallest id)
+// Every weakly connected induced k-subgraph rooted at v0 (its lowest rank)
 // is counted once in its class.  `pending` counts this wave's increments since
 // its last flush of the workgroup's 32-bit LDS counters.  A counter holds only
 // increments its waves made after their own last flush, and a wave flushes
@@ -598,7 +599,7 @@ __device__ void dmotif_root(const DMotifArgs& A, const DLds& L, const DWave& W, 
     int32_t* E1 = W.vert + A.level_off[1];
     uint8_t* M1 = W.mask + A.level_off[1];
     uint16_t* A1 = W.arcs + A.level_off[1];
-    if (lane == 0 && k == 3) L.nnew[1] = lds1 ? 1 : 0;
+    if (lane == 0 && k == 3) L.meta[1] = lds1 ? 1 : 0;
     for (int i = lane; i < d0 - skip; i += kWave) {
       const int w = A.col[b0 + skip + i];
       const unsigned a = A.dir[b0 + skip + i] & 3u;
