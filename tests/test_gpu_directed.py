@@ -132,6 +132,29 @@ def test_directed_star_launch_shapes(k, leaves):
         assert np.array_equal(dm.count_motifs_directed(h, k, waves_per_cu=cap), exp), (k, cap)
 
 
+def test_directed_counts_ignore_vertex_ids():
+    """The kernel renames vertices by (degree, id) rank and roots each
+    subgraph at its lowest rank; the class counts depend on the digraph only,
+    so any renaming of the input ids gives the same counts (hubs at the lowest
+    ids, at the highest, or shuffled)."""
+    d = GRAPHS["cl1500"]()
+    src = np.repeat(np.arange(d.n), np.diff(d.row_ptr))
+    arcs = np.stack([src, d.col.astype(np.int64)], axis=1)
+    deg = np.bincount(arcs.ravel(), minlength=d.n)
+    orders = {
+        "hubs_first": np.argsort(-deg, kind="stable"),
+        "hubs_last": np.argsort(deg, kind="stable"),
+        "shuffled": np.random.default_rng(21).permutation(d.n),
+    }
+    base = {k: dm.count_motifs_directed(dm.load_digraph(d), k) for k in (3, 4, 5)}
+    for name, order in orders.items():
+        new_id = np.empty(d.n, dtype=np.int64)
+        new_id[order] = np.arange(d.n)
+        h = dm.load_digraph(gg.digraph_from_arcs(d.n, new_id[arcs].tolist()))
+        for k in (3, 4, 5):
+            assert np.array_equal(dm.count_motifs_directed(h, k), base[k]), (name, k)
+
+
 def test_directed_device_input_and_validation():
     import torch
     d = GRAPHS["ba400"]()
