@@ -46,9 +46,9 @@ def kernel_source_sha(kernel: str = "dm_clique.hip") -> str:
 
 # Counters of the motif kernel's timed launch on the sampled 5-motif workload
 # (same passes and scaling), valid only for the kernel source they were taken on.
-MOTIF_K5 = {"source_sha": "338cab95d4520563", "valu_insts": 899032450819.0,
-            "active_lane_fraction": 29455662262708.0 / (64 * 899032450819.0),
-            "hbm_bytes": 2.0 * 235390024.6875 * 1024 + 54998852.59375 * 1024,
+MOTIF_K5 = {"source_sha": "d29dfb677d40ed31", "valu_insts": 891021959665.0,
+            "active_lane_fraction": 28826449997317.0 / (64 * 891021959665.0),
+            "hbm_bytes": 2.0 * 241171174.9375 * 1024 + 55297142.46875 * 1024,
             "profile": "profiles/motif_kernel_cl100k_k5_sample_counters.md"}
 # MI355X VALU issue peak: 256 CUs x 4 SIMDs, a wave64 VALU instruction takes
 # 4 cycles on a 16-lane SIMD, at 2.4 GHz: 6.14e11 wave instructions/s, i.e.

@@ -382,6 +382,32 @@ __device__ __forceinline__ int leaf_level(const MotifArgs& A, const MotifLds& L,
   for (int i = lane; i < kBins; i += kWave) L.nw[i] = 0;
   for (int i = lane; i < 2 * kBins; i += kWave) L.ccount[i] = 0;
   wave_sync();
+  // The traversal's members and the canonical test's thresholds, held in
+  // registers for the leaf items (kBins = 2^kLog mask bins cover s <= kLog
+  // members): a neighbour equal to a member is no leaf, and an entry whose
+  // first traversal neighbour is tr[f] is canonical above sufmax[s][f].
+  constexpr int kLog = (kBins == 16 ? 4 : (kBins == 32 ? 5 : 6));
+  static_assert((1 << kLog) == kBins, "one mask bit per traversal member");
+  int trr[kLog];
+#pragma unroll
+  for (int t = 0; t < kLog; ++t) trr[t] = t < s ? uni(L.tr[t]) : -1;
+  auto in_tr_r = [&](int w) {
+    bool r = false;
+#pragma unroll
+    for (int t = 0; t < kLog; ++t) r = r || w == trr[t];
+    return r;
+  };
+  int thr[kLog];
+#pragma unroll
+  for (int t = 0; t < kLog; ++t) thr[t] = t < s ? uni(L.sufmax[s * kSuf + t]) : 0x7fffffff;
+  auto canon_r = [&](int y, unsigned mm) {
+    const unsigned lw = mm & low;
+    int th = 0x7fffffff;
+#pragma unroll
+    for (int t = kLog - 1; t >= 0; --t)
+      if ((lw >> t) & 1u) th = thr[t];
+    return y > v0 && y > th;
+  };
   for (int c = lo; c < hi; c += kWave) {
     // ---- slice: canonical entries and a prefix sum of their degrees
     const int j = c + lane;
@@ -431,8 +457,8 @@ __device__ __forceinline__ int leaf_level(const MotifArgs& A, const MotifLds& L,
         const int jj = maybe ? ev_find(w) : -1;
         if (jj >= 0) {
           const unsigned mj = em_at(jj);
-          if (jj > c + o && canonical(L, s, w, mj)) key = L.sl_mask[o] * kBins + static_cast<int>(mj & low);
-        } else if (!in_tr(L, s, w)) {
+          if (jj > c + o && canon_r(w, mj)) key = L.sl_mask[o] * kBins + static_cast<int>(mj & low);
+        } else if (!in_tr_r(w)) {
           key = kBins * kBins + L.sl_mask[o];
         }
       }
